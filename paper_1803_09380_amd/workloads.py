@@ -1,0 +1,139 @@
+"""Seeded synthetic inputs with the shapes of the paper's test cases.
+
+This module only describes problems: lattice sizes, relaxation times, boundary
+types, and the Lagrangian markers of circles (the discretised interface Gamma
+of Sec. 2.2).  It holds none of the method's arithmetic, so both the CPU
+oracle and the GPU library can take their inputs from it.
+
+Cases (lattice units):
+  * cylindrical Couette flow (Sec. 3.1.2, Eqs. 32-34): periodic box of side s,
+    k = s/64, outer circle R2 = 24k fixed, inner circle R1 = 12k turning
+    counter-clockwise at tangential speed 0.01/k, tau = 0.8, markers about one
+    lattice spacing apart (N = round(2 pi R)), Delta s = 2 pi R / N;
+  * flow past a fixed cylinder (Sec. 3.2): channel, uniform inflow U at the west
+    side, zero-gradient outflow at the east side, free-slip south/north, tau from
+    Re = U D / nu;
+  * settling particles (Sec. 3.3): closed box with walls, one or two free circles.
+"""
+import math
+
+import numpy as np
+
+PERIODIC, WALL, FREESLIP, VELOCITY, OUTFLOW = range(5)
+FIXED, FREE = 0, 1
+F64, F32 = 0, 1
+
+
+def circle_markers(xc, yc, R, n, phase=0.0):
+    """n markers on a circle, angle 2 pi l / n + phase, counter-clockwise."""
+    a = phase + 2.0 * np.pi * np.arange(n) / n
+    return np.stack([xc + R * np.cos(a), yc + R * np.sin(a)], axis=1)
+
+
+def couette(side=64, tau=0.8, u_inner=None, precision=F64, ib_iters=10):
+    """Cylindrical Couette flow between a fixed outer circle and a turning inner one."""
+    k = side / 64.0
+    R1, R2 = 12.0 * k, 24.0 * k
+    c = side / 2.0
+    U1 = 0.01 / k if u_inner is None else u_inner
+    n1, n2 = int(round(2 * math.pi * R1)), int(round(2 * math.pi * R2))
+    bodies = [
+        dict(kind=FIXED, n=n2, xy=circle_markers(c, c, R2, n2), uv=None,
+             ds=np.full(n2, 2 * math.pi * R2 / n2), xc=(c, c), U=(0.0, 0.0), omega=0.0,
+             theta=0.0, radius=R2, rho_s=0.0),
+        dict(kind=FIXED, n=n1, xy=circle_markers(c, c, R1, n1), uv=None,
+             ds=np.full(n1, 2 * math.pi * R1 / n1), xc=(c, c), U=(0.0, 0.0), omega=U1 / R1,
+             theta=0.0, radius=R1, rho_s=0.0),
+    ]
+    return dict(name="couette%d" % side, nx=side, ny=side, tau=tau, rho0=1.0,
+                bc=(PERIODIC,) * 4, u_in=(0.0, 0.0), u_init=(0.0, 0.0), ib_iters=ib_iters,
+                precision=precision, gravity=(0.0, 0.0), bodies=bodies,
+                meta=dict(R1=R1, R2=R2, omega1=U1 / R1, centre=(c, c), nu=(tau - 0.5) / 3.0))
+
+
+def cylinder(nx=1600, ny=800, D=40.0, centre=None, U=0.05, Re=20.0, precision=F32, ib_iters=10,
+             n_markers=None):
+    """Flow past a fixed circular cylinder in a channel."""
+    nu = U * D / Re
+    tau = 3.0 * nu + 0.5
+    R = D / 2.0
+    cx, cy = centre if centre is not None else (nx / 4.0, ny / 2.0)
+    n = n_markers if n_markers is not None else int(round(math.pi * D))
+    body = dict(kind=FIXED, n=n, xy=circle_markers(cx, cy, R, n), uv=np.zeros((n, 2)),
+                ds=np.full(n, 2 * math.pi * R / n), xc=(cx, cy), U=(0.0, 0.0), omega=0.0,
+                theta=0.0, radius=R, rho_s=0.0)
+    return dict(name="cylinder_%dx%d_D%g_Re%g" % (nx, ny, D, Re), nx=nx, ny=ny, tau=tau, rho0=1.0,
+                bc=(VELOCITY, OUTFLOW, FREESLIP, FREESLIP), u_in=(U, 0.0), u_init=(U, 0.0),
+                ib_iters=ib_iters, precision=precision, gravity=(0.0, 0.0), bodies=[body],
+                meta=dict(D=D, U=U, Re=Re, nu=nu))
+
+
+def settling(nx=400, ny=4000, D=24.0, density_ratio=1.2, two=False, tau=0.8, u_ref=0.04,
+             precision=F32, ib_iters=10, lower=None):
+    """One or two free circles settling under gravity in a closed box.
+
+    Gravity is g = u_ref^2 / ((rho_s/rho_f - 1) D), which keeps the settling
+    speed near u_ref (Mach well below 0.1)."""
+    R = D / 2.0
+    g = u_ref * u_ref / ((density_ratio - 1.0) * D)
+    x0, y0 = lower if lower is not None else (nx / 2.0, ny - 400.0)
+    n = int(round(math.pi * D))
+    bodies = [dict(kind=FREE, n=n, xy=None, uv=None, ds=None, xc=(x0, y0), U=(0.0, 0.0),
+                   omega=0.0, theta=0.0, radius=R, rho_s=density_ratio)]
+    if two:
+        bodies.append(dict(kind=FREE, n=n, xy=None, uv=None, ds=None,
+                           xc=(x0 + 0.01 * D, y0 + 2.0 * D), U=(0.0, 0.0), omega=0.0, theta=0.0,
+                           radius=R, rho_s=density_ratio))
+    return dict(name="settling_%dx%d_D%g_r%g_%s" % (nx, ny, D, density_ratio, "two" if two else "one"),
+                nx=nx, ny=ny, tau=tau, rho0=1.0, bc=(WALL,) * 4, u_in=(0.0, 0.0),
+                u_init=(0.0, 0.0), ib_iters=ib_iters, precision=precision, gravity=(0.0, -g),
+                bodies=bodies, meta=dict(D=D, g=g, density_ratio=density_ratio))
+
+
+def batch(seed=0, count=256, precision=F32):
+    """Uneven mix: each member is a Couette case (side uniform in 64..512) or a
+    fixed cylinder in a 20D x 10D channel (D uniform in 16..64, Re uniform in
+    10..100, U = 0.05, centre (5D, 5D))."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(count):
+        if rng.random() < 0.5:
+            side = int(rng.integers(64, 513))
+            out.append(couette(side=side, precision=precision))
+        else:
+            D = int(rng.integers(16, 65))
+            Re = float(rng.uniform(10.0, 100.0))
+            out.append(cylinder(nx=20 * D, ny=10 * D, D=float(D), centre=(5.0 * D, 5.0 * D),
+                                U=0.05, Re=Re, precision=precision))
+    return out
+
+
+def arrivals(seed=0, rate=20.0, count=200, nx=400, ny=4000, steps=2000, precision=F32):
+    """Poisson arrivals of settling requests: arrival time (s) and case."""
+    rng = np.random.default_rng(seed)
+    t = np.cumsum(rng.exponential(1.0 / rate, size=count))
+    reqs = []
+    for k in range(count):
+        D = float(rng.uniform(16.0, 40.0))
+        ratio = float(rng.uniform(1.01, 1.5))
+        two = bool(rng.random() < 0.5)
+        case = settling(nx=nx, ny=ny, D=D, density_ratio=ratio, two=two, precision=precision,
+                        lower=(nx / 2.0, ny - 400.0))
+        reqs.append(dict(t_arrive=float(t[k]), case=case, steps=steps, id=k))
+    return reqs
+
+
+def random_populations(seed, nx, ny, base, amp=0.02):
+    """Positive populations base[i] * (1 + amp * noise), [9, ny, nx] float64.
+    The caller supplies the nine base values (for example a rest state)."""
+    rng = np.random.default_rng(seed)
+    base = np.asarray(base, dtype=np.float64).reshape(9, 1, 1)
+    return base * (1.0 + amp * rng.standard_normal((9, ny, nx)))
+
+
+def random_fields(seed, nx, ny, rho0=1.0, amp_rho=0.01, amp_u=0.02):
+    rng = np.random.default_rng(seed)
+    rho = rho0 * (1.0 + amp_rho * rng.standard_normal((ny, nx)))
+    ux = amp_u * rng.standard_normal((ny, nx))
+    uy = amp_u * rng.standard_normal((ny, nx))
+    return rho, ux, uy
