@@ -1,0 +1,228 @@
+#!/usr/bin/env python3
+"""Benchmark of the MI355X IB-LBM hot path.
+
+Workload: the batched uneven set -- 256 seeded simulations, each either a
+cylindrical Couette case (side uniform in 64..512) or a fixed cylinder in a
+20D x 10D channel (D uniform in 16..64, Re uniform in 10..100), FP32 shifted
+populations, all advanced together by the batch (captured graphs of persistent
+kernels).  One step = collide-stream sweep, boundary rules, 10 correction
+sweeps with FP64 force/torque reductions, bookkeeping, for every member.
+
+Printed (one JSON line): aggregate MLUPS of the batched FP32 path over exactly
+--steps timed steps, the sweep kernel's HBM roofline fraction (per-launch
+duration from HIP events on the batch stream), the plain per-simulation FP64
+GPU path on a sample of the same set, and the FP64 CPU oracle timed on the
+host cores on a bounded sample.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "D2Q9+IB MLUPS (FP32 batched vs FP64 plain) at stated error; p50/p99 solve time"
+HBM_PEAK_GBS = 8000.0
+SWEEP_BYTES_F32 = 72  # 9 loads + 9 stores of 4 bytes per cell update
+SWEEP_BYTES_F64 = 144
+
+
+def _oracle_from_case(po, case):
+    o = po.Oracle(case["nx"], case["ny"], case["tau"], rho0=case["rho0"], bc=case["bc"], u_in=case["u_in"],
+                  u_init=case["u_init"], ib_iters=case["ib_iters"], gravity=case["gravity"])
+    for k, b in enumerate(case["bodies"]):
+        if b["kind"] == 1:
+            o.set_body(k, po.FREE, b["n"], xc=b["xc"], U=b["U"], omega=b["omega"], theta=b["theta"],
+                       radius=b["radius"], rho_s=b["rho_s"])
+        else:
+            o.set_body(k, po.FIXED, b["n"], xy=b["xy"], uv=b["uv"], ds=b["ds"], xc=b["xc"], U=b["U"],
+                       omega=b["omega"], theta=b["theta"])
+    return o
+
+
+def run_cpu_baseline(cases, seconds):
+    threads = max(1, min(16, os.cpu_count() or 1))
+    os.environ["OMP_NUM_THREADS"] = str(threads)
+    sys.path.insert(0, os.path.join(ROOT, "oracle"))
+    import pyoracle as po
+    po.build()
+    updates = 0
+    used = 0.0
+    members = 0
+    steps_each = []
+    for case in cases:
+        if used >= seconds:
+            break
+        o = _oracle_from_case(po, case)
+        n = 0
+        t0 = time.perf_counter()
+        while True:
+            o.step(5)
+            n += 5
+            el = time.perf_counter() - t0
+            if el > seconds / 4 or used + el >= seconds or n >= 200:
+                break
+        used += el
+        updates += case["nx"] * case["ny"] * n
+        members += 1
+        steps_each.append(n)
+    return {"value": updates / used / 1e6, "unit": "MLUPS", "cores": threads, "kind": "oracle",
+            "sample": "%d members of the set (first in seed order), %s steps each, %.1f s of host time, "
+                      "FP64, IB sweeps serial, collide/stream OpenMP" % (members, steps_each, used)}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=300)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--sims", type=int, default=256)
+    ap.add_argument("--profile-steps", type=int, default=20)
+    ap.add_argument("--fp64-sample", type=int, default=16)
+    ap.add_argument("--fp64-steps", type=int, default=50)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--autotune", action="store_true")
+    ap.add_argument("--tiling", type=int, default=-1)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: every simulation of the set fits one MI355X and the set "
+              "shards by simulation with no communication; --gpus %d is not supported" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+
+    from paper_1803_09380_amd import workloads as wl
+    cases = wl.batch(seed=args.seed, count=args.sims, precision=wl.F32)
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = run_cpu_baseline(cases, args.cpu_seconds)
+
+    import numpy as np
+    import torch
+    from paper_1803_09380_amd import lbmib
+
+    torch.cuda.init()
+    cells = sum(c["nx"] * c["ny"] for c in cases)
+    markers = sum(b["n"] for c in cases for b in c["bodies"])
+
+    # ---- FP32 shifted, batched
+    sims = [lbmib.Sim.from_case(c, precision=lbmib.F32_SHIFTED) for c in cases]
+    batch = lbmib.Batch(lbmib.F32_SHIFTED)
+    for s in sims:
+        assert batch.admit(s)
+    if args.tiling >= 0:
+        batch.set_tiling(args.tiling)
+    tiling = None
+    if args.autotune:
+        tiling = batch.autotune(trials=3)
+    batch.step(args.warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    batch.step(args.steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    wall = t1 - t0
+    mlups = cells * args.steps / wall / 1e6
+
+    # ---- per-kernel durations on the batch stream (HIP events), same tables and grids
+    ms, pcells = batch.profile(args.profile_steps)
+    sweep_ms = ms[0] / args.profile_steps
+    achieved = SWEEP_BYTES_F32 * pcells / (sweep_ms * 1e-3) / 1e9
+    unstable = 0
+    for s in sims:
+        try:
+            s.sync()
+        except lbmib.LbmError as e:
+            if e.code == lbmib.ERR_UNSTABLE:
+                unstable += 1
+            else:
+                raise
+    batch.close()
+    del sims
+    torch.cuda.synchronize()
+
+    # ---- FP64 plain path: members of the same set one at a time, direct launches
+    f64_updates, f64_time = 0, 0.0
+    for c in cases[:args.fp64_sample]:
+        s = lbmib.Sim.from_case(c, precision=lbmib.F64)
+        s.step(2)
+        s.sync()
+        t0 = time.perf_counter()
+        s.step(args.fp64_steps)
+        s.sync()
+        f64_time += time.perf_counter() - t0
+        f64_updates += c["nx"] * c["ny"] * args.fp64_steps
+        s.close()
+    f64_mlups = f64_updates / f64_time / 1e6
+    # batched FP32 on the same sample, for a like-for-like speedup
+    sample = [lbmib.Sim.from_case(c, precision=lbmib.F32_SHIFTED) for c in cases[:args.fp64_sample]]
+    b2 = lbmib.Batch(lbmib.F32_SHIFTED)
+    for s in sample:
+        b2.admit(s)
+    b2.step(4)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b2.step(args.fp64_steps)
+    torch.cuda.synchronize()
+    f32_sample_mlups = f64_updates / (time.perf_counter() - t0) / 1e6
+    b2.close()
+    del sample
+
+    # ---- accuracy of the FP32 path against the FP64 path on one member (Couette 64)
+    ref = wl.couette(64)
+    a = lbmib.Sim.from_case(ref, precision=lbmib.F64)
+    b = lbmib.Sim.from_case(ref, precision=lbmib.F32_SHIFTED)
+    a.step(2000)
+    b.step(2000)
+    _, ua, va = a.fields()
+    _, ub, vb = b.fields()
+    err = float(np.sqrt(np.sum((ua - ub) ** 2 + (va - vb) ** 2) / np.sum(ua ** 2 + va ** 2)))
+
+    out = {
+        "metric": METRIC,
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall / args.steps * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "batched uneven set: %d seeded simulations (Couette side 64..512 or cylinder "
+                        "channel 20Dx10D with D 16..64, Re 10..100), FP32 shifted populations, "
+                        "10 correction sweeps per step" % args.sims,
+            "seed": args.seed, "sims": args.sims, "cells": cells, "markers": markers,
+            "tiling": tiling if tiling is not None else args.tiling,
+        },
+        "roofline": {
+            "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "kernel": "k_sweep<float>", "launch_ms": round(sweep_ms, 4),
+            "bytes_per_cell": SWEEP_BYTES_F32, "cells_per_launch": pcells,
+            "step_split_ms": {"sweep": round(ms[0] / args.profile_steps, 4),
+                              "boundary": round(ms[1] / args.profile_steps, 4),
+                              "correction": round(ms[2] / args.profile_steps, 4),
+                              "bookkeeping": round(ms[3] / args.profile_steps, 4)},
+        },
+        "fp64_plain": {"value": round(f64_mlups, 1), "unit": "MLUPS",
+                       "sample": "first %d members, %d steps each, one at a time" % (args.fp64_sample, args.fp64_steps),
+                       "fp32_batched_same_sample": round(f32_sample_mlups, 1),
+                       "speedup_fp32_batched": round(f32_sample_mlups / f64_mlups, 2)},
+        "accuracy": {"fp32_vs_fp64_velocity_rel_l2": err, "case": "couette64, 2000 steps"},
+        "unstable_members": unstable,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,813 @@
+// gfx950 kernels of the distribution-function-correction IB-LBM.
+//
+//   k_sweep     fused BGK collision + streaming, in place (AA pattern), SoA
+//               planes, one lattice cell per thread-row step; HBM-bound.
+//   k_boundary  rules for populations entering through non-periodic sides.
+//   k_ib        one workgroup per body group: band gather, N Jacobi sweeps of
+//               the correction of Sec. 2.3 on the band's (rho, j), one final
+//               spread of the accumulated deviation into the nine populations,
+//               FP64 force/torque reductions and the rigid-body update.
+//   k_advance   per-simulation step bookkeeping of batches.
+//
+// T = double stores f_i; T = float stores h_i = f_i - w_i rho0 (rho_base).
+// The equilibrium is written in terms of S = sum_i h_i = rho - rho_base and
+// j = sum_i e_i h_i, which covers both: h_i^eq = w_i (S + 3 e.j + 4.5 (e.j)^2/rho
+// - 1.5 j.j/rho) (Eq. 3 with c_s^2 = 1/3 and rho u = j).
+#include <hip/hip_runtime.h>
+
+#include "kernels.hpp"
+
+namespace lbmib {
+
+const Tiling kTilings[kNumTilings] = {{64, 4, 1}, {64, 4, 2}, {128, 2, 2}, {256, 1, 2},
+                                      {256, 1, 4}, {64, 4, 4}};
+
+// ---------------------------------------------------------------- collision
+
+template <typename T>
+__device__ __forceinline__ void bgk(T h[9], T rho_base, T omega, uint32_t& bad) {
+    const T S = ((h[0] + h[1]) + (h[2] + h[3])) + ((h[4] + h[5]) + (h[6] + h[7])) + h[8];
+    const T jx = (h[1] + h[5] + h[8]) - (h[3] + h[6] + h[7]);
+    const T jy = (h[2] + h[5] + h[6]) - (h[4] + h[7] + h[8]);
+    const T rho = rho_base + S;
+    if (!(rho > T(0)) || !isfinite(jx + jy)) bad = 1u;
+    const T inv = T(1) / rho;
+    const T ux = jx * inv, uy = jy * inv;
+    const T ju = T(1.5) * (jx * ux + jy * uy);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        const T ej = T(ex_of(i)) * jx + T(ey_of(i)) * jy;
+        const T eu = T(ex_of(i)) * ux + T(ey_of(i)) * uy;
+        const T heq = weight_of<T>(i) * (S + T(3) * ej + T(4.5) * ej * eu - ju);
+        h[i] = h[i] + omega * (heq - h[i]);
+    }
+}
+
+// ---------------------------------------------------------------- sweep
+
+template <typename T, int TX, int TY, int RPT>
+__global__ void __launch_bounds__(TX* TY)
+    k_sweep(const SimDev* __restrict__ sims, const int4* __restrict__ tiles,
+            const BatchHeader* __restrict__ hdr, int ntiles_arg, int parity) {
+    const int ntiles = hdr ? hdr->ntiles : ntiles_arg;
+    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const int4 tile = tiles[t];
+        const SimDev& S = sims[tile.x];
+        if (!S.active) continue;
+        const int sw = parity >= 0 ? parity : S.swapped;
+        const int nx = S.nx, ny = S.ny, px = S.px, py = S.py;
+        const int64_t pl = S.plane;
+        const int pitch = S.pitch;
+        T* __restrict__ P = reinterpret_cast<T*>(S.pop) + S.xoff + pitch;  // (x=0, y=0)
+        const T rho_base = T(S.rho_base), omega = T(S.omega);
+        const int x = tile.y + threadIdx.x;
+        uint32_t bad = 0;
+        if (x < nx) {
+            const int xm = wrap(x - 1, nx, px), xp = wrap(x + 1, nx, px);
+#pragma unroll
+            for (int r = 0; r < RPT; ++r) {
+                const int y = tile.z + threadIdx.y * RPT + r;
+                if (y >= ny) break;
+                const int ym = wrap(y - 1, ny, py), yp = wrap(y + 1, ny, py);
+                const int r0 = y * pitch, rm = ym * pitch, rp = yp * pitch;
+                T h[9];
+                if (!sw) {
+                    // natural state: own slots; write f*_i into slot opp(i)
+#pragma unroll
+                    for (int i = 0; i < 9; ++i) h[i] = P[i * pl + r0 + x];
+                    bgk<T>(h, rho_base, omega, bad);
+#pragma unroll
+                    for (int i = 0; i < 9; ++i) P[opp_of(i) * pl + r0 + x] = h[i];
+                } else {
+                    // swapped state: f_i(x) = slot opp(i) of x - e_i
+                    h[0] = P[0 * pl + r0 + x];
+                    h[1] = P[3 * pl + r0 + xm];
+                    h[2] = P[4 * pl + rm + x];
+                    h[3] = P[1 * pl + r0 + xp];
+                    h[4] = P[2 * pl + rp + x];
+                    h[5] = P[7 * pl + rm + xm];
+                    h[6] = P[8 * pl + rm + xp];
+                    h[7] = P[5 * pl + rp + xp];
+                    h[8] = P[6 * pl + rp + xm];
+                    bgk<T>(h, rho_base, omega, bad);
+                    // f*_i goes to slot i of x + e_i
+                    P[0 * pl + r0 + x] = h[0];
+                    P[1 * pl + r0 + xp] = h[1];
+                    P[2 * pl + rp + x] = h[2];
+                    P[3 * pl + r0 + xm] = h[3];
+                    P[4 * pl + rm + x] = h[4];
+                    P[5 * pl + rp + xp] = h[5];
+                    P[6 * pl + rp + xm] = h[6];
+                    P[7 * pl + rm + xm] = h[7];
+                    P[8 * pl + rm + xp] = h[8];
+                }
+            }
+        }
+        if (bad) atomicOr(S.status, ST_UNSTABLE);
+    }
+}
+
+// ---------------------------------------------------------------- boundary rules
+
+// Perimeter node k of a simulation: south row, north row, then the west and
+// east columns without the corners already counted.
+__device__ __forceinline__ void perim_node(const SimDev& S, int k, int& x, int& y) {
+    const int nx = S.nx, ny = S.ny;
+    if (!S.py) {
+        if (k < nx) {
+            x = k;
+            y = 0;
+            return;
+        }
+        if (k < 2 * nx) {
+            x = k - nx;
+            y = ny - 1;
+            return;
+        }
+        k -= 2 * nx;
+    }
+    const int ys = S.py ? 0 : 1, ncol = S.py ? ny : ny - 2;
+    if (k < ncol) {
+        x = 0;
+        y = ys + k;
+    } else {
+        x = nx - 1;
+        y = ys + k - ncol;
+    }
+}
+
+// Post-stream f_i at an interior-in-x node, applying the south/north rule when
+// the source lies outside in y.  Reads post-collision values only.
+template <typename T>
+__device__ __forceinline__ T post_stream(const SimDev& S, int i, int x, int y, int sw) {
+    const int sx = wrap(x - ex_of(i), S.nx, S.px), sy = wrap(y - ey_of(i), S.ny, S.py);
+    if (sy >= 0 && sy < S.ny) return *pc<T>(S, i, sx, sy, sw);
+    const int side = sy < 0 ? S.bc[SIDE_S] : S.bc[SIDE_N];
+    if (side == BC_WALL) return *pc<T>(S, opp_of(i), x, y, sw);
+    return *pc<T>(S, mirror_y(i), wrap(x - ex_of(i), S.nx, S.px), y, sw);
+}
+
+// h^eq_i for shifted sum S (= rho - rho_base), density rho and momentum j.
+template <typename T>
+__device__ __forceinline__ T heq_i(int i, T S_, T rho, T jx, T jy) {
+    const T ej = T(ex_of(i)) * jx + T(ey_of(i)) * jy;
+    return weight_of<T>(i) * (S_ + T(3) * ej + (T(4.5) * ej * ej - T(1.5) * (jx * jx + jy * jy)) / rho);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+    k_boundary(const SimDev* __restrict__ sims, const int2* __restrict__ items,
+               const BatchHeader* __restrict__ hdr, int nitems_arg, int parity) {
+    const int nitems = hdr ? hdr->nbc : nitems_arg;
+    for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+        const int2 item = items[it];
+        const SimDev& S = sims[item.x];
+        if (!S.active) continue;
+        const int k = item.y + threadIdx.x;
+        if (k >= S.nperim) continue;
+        const int sw = 1 - (parity >= 0 ? parity : S.swapped);  // state after this step's sweep
+        int x, y;
+        perim_node(S, k, x, y);
+        const int nx = S.nx, ny = S.ny;
+        if (x == 0 && S.bc[SIDE_W] == BC_VELOCITY) {
+            // non-equilibrium extrapolation from column 1 (every population)
+            T f1[9];
+#pragma unroll
+            for (int i = 0; i < 9; ++i) f1[i] = post_stream<T>(S, i, 1, y, sw);
+            const T S1 = ((f1[0] + f1[1]) + (f1[2] + f1[3])) + ((f1[4] + f1[5]) + (f1[6] + f1[7])) + f1[8];
+            const T jx1 = (f1[1] + f1[5] + f1[8]) - (f1[3] + f1[6] + f1[7]);
+            const T jy1 = (f1[2] + f1[5] + f1[6]) - (f1[4] + f1[7] + f1[8]);
+            const T rho1 = T(S.rho_base) + S1;
+            const T jxb = rho1 * T(S.u_in[0]), jyb = rho1 * T(S.u_in[1]);
+#pragma unroll
+            for (int i = 0; i < 9; ++i) {
+                const T v = heq_i<T>(i, S1, rho1, jxb, jyb) + (f1[i] - heq_i<T>(i, S1, rho1, jx1, jy1));
+                *loc<T>(S, i, 0, y, sw) = v;
+            }
+            continue;
+        }
+#pragma unroll
+        for (int i = 1; i < 9; ++i) {
+            const int sx = wrap(x - ex_of(i), nx, S.px), sy = wrap(y - ey_of(i), ny, S.py);
+            const bool outx = sx < 0 || sx >= nx, outy = sy < 0 || sy >= ny;
+            if (!outx && !outy) continue;
+            T v;
+            if (outx) {
+                const int side = sx < 0 ? S.bc[SIDE_W] : S.bc[SIDE_E];
+                if (side == BC_WALL)
+                    v = *pc<T>(S, opp_of(i), x, y, sw);
+                else  // zero-gradient outlet (east, e_x = -1)
+                    v = post_stream<T>(S, i, nx - 2, y, sw);
+            } else {
+                const int side = sy < 0 ? S.bc[SIDE_S] : S.bc[SIDE_N];
+                if (side == BC_WALL)
+                    v = *pc<T>(S, opp_of(i), x, y, sw);
+                else  // specular reflection
+                    v = *pc<T>(S, mirror_y(i), wrap(x - ex_of(i), nx, S.px), y, sw);
+            }
+            *loc<T>(S, i, x, y, sw) = v;
+        }
+    }
+}
+
+// ---------------------------------------------------------------- correction sweeps
+
+template <typename T>
+__device__ __forceinline__ T phi4(T r) {
+    const T a = fabs(r);
+    return a <= T(2) ? T(0.25) * (T(1) + cos(T(M_PI) * a * T(0.5))) : T(0);
+}
+
+// group marker g -> index into the simulation's marker arrays, and its body slot
+__device__ __forceinline__ int marker_index(const SimDev& S, const GroupDev& G, int g, int& body) {
+    int base = 0;
+    for (int b = 0; b < G.nbody; ++b) {
+        const BodyDev& B = S.bodies[G.body[b]];
+        if (g < base + B.n) {
+            body = G.body[b];
+            return B.m0 + (g - base);
+        }
+        base += B.n;
+    }
+    body = G.body[0];
+    return 0;
+}
+
+__device__ __forceinline__ bool stencil_cell(const SimDev& S, double X, double Y, int kx, int ky, int& cell) {
+    int x = (int)floor(X) - 1 + kx, y = (int)floor(Y) - 1 + ky;
+    x = wrap(x, S.nx, S.px);
+    y = wrap(y, S.ny, S.py);
+    if (x < 0 || x >= S.nx || y < 0 || y >= S.ny) return false;
+    cell = y * S.nx + x;
+    return true;
+}
+
+// Block-wide exclusive scan of one int per thread (NT threads); returns the
+// prefix and the total in *total.
+template <int NT>
+__device__ __forceinline__ int block_scan(int v, int* tmp, int* total) {
+    const int tid = threadIdx.x;
+    tmp[tid] = v;
+    __syncthreads();
+    for (int off = 1; off < NT; off <<= 1) {
+        int add = tid >= off ? tmp[tid - off] : 0;
+        __syncthreads();
+        tmp[tid] += add;
+        __syncthreads();
+    }
+    const int incl = tmp[tid];
+    *total = tmp[NT - 1];
+    __syncthreads();
+    return incl - v;
+}
+
+// Rebuild a group's plan on the device: stencil entries (cell, marker, kx, ky)
+// sorted by cell then marker, runs of equal cells are the band nodes.
+template <int NT>
+__device__ void build_plan(const SimDev& S, const GroupDev& G, unsigned long long* keys, int* scan_tmp,
+                           int& nband_out, int& nent_out) {
+    const int tid = threadIdx.x;
+    const int NE = 16 * G.M;
+    int P2 = 16;
+    while (P2 < NE) P2 <<= 1;
+    for (int e = tid; e < P2; e += NT) {
+        unsigned long long key = ~0ull;
+        if (e < NE) {
+            const int g = e >> 4, s = e & 15, kx = s & 3, ky = s >> 2;
+            int body;
+            const int mi = marker_index(S, G, g, body);
+            int cell;
+            if (stencil_cell(S, S.mX[mi], S.mY[mi], kx, ky, cell))
+                key = ((unsigned long long)(unsigned)cell << 32) | (unsigned)((g << 4) | (ky << 2) | kx);
+        }
+        keys[e] = key;
+    }
+    for (int e = tid; e < NE; e += NT) G.mnode[e] = -1;
+    __syncthreads();
+    // bitonic sort, ascending
+    for (int k = 2; k <= P2; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int e = tid; e < P2; e += NT) {
+                const int p = e ^ j;
+                if (p > e) {
+                    const unsigned long long a = keys[e], b = keys[p];
+                    const bool up = (e & k) == 0;
+                    if ((a > b) == up) {
+                        keys[e] = b;
+                        keys[p] = a;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    // run starts -> band node indices (contiguous segment per thread, then scan)
+    const int per = (NE + NT - 1) / NT;
+    const int e0 = tid * per, e1 = min(NE, e0 + per);
+    int cnt = 0, valid = 0;
+    for (int e = e0; e < e1; ++e) {
+        const unsigned long long key = keys[e];
+        if (key == ~0ull) continue;
+        ++valid;
+        if (e == 0 || (keys[e - 1] >> 32) != (key >> 32)) ++cnt;
+    }
+    int total;
+    int node = block_scan<NT>(cnt, scan_tmp, &total) - 1;
+    int nvalid;
+    block_scan<NT>(valid, scan_tmp, &nvalid);
+    for (int e = e0; e < e1; ++e) {
+        const unsigned long long key = keys[e];
+        if (key == ~0ull) continue;
+        const int cell = (int)(key >> 32);
+        if (e == 0 || (keys[e - 1] >> 32) != (key >> 32)) {
+            ++node;
+            G.node_cell[node] = cell;
+            G.node_run[node] = e;
+        }
+        const int low = (int)(key & 0xffffffffu);
+        G.ent[e] = low;
+        G.mnode[low] = node;  // low = 16 * marker + stencil slot
+    }
+    if (tid == 0) G.node_run[total] = nvalid;
+    nband_out = total;
+    nent_out = nvalid;
+    __syncthreads();
+}
+
+// Deterministic FP64 sum over [0, n) of v(i) for any block size: fixed
+// 256-wide tree per chunk, chunks added in order by thread 0.
+template <int NT, typename F>
+__device__ double det_sum(int n, F v, double* red) {
+    const int tid = threadIdx.x;
+    double acc = 0.0;
+    for (int c0 = 0; c0 < n; c0 += 256) {
+        if (tid < 256) red[tid] = (c0 + tid < n) ? v(c0 + tid) : 0.0;
+        __syncthreads();
+        for (int s = 128; s > 0; s >>= 1) {
+            if (tid < s) red[tid] += red[tid + s];
+            __syncthreads();
+        }
+        if (tid == 0) acc += red[0];
+        __syncthreads();
+    }
+    return acc;  // valid on thread 0
+}
+
+template <int NT, typename F>
+__device__ double det_max(int n, F v, double* red) {
+    const int tid = threadIdx.x;
+    double acc = 0.0;
+    for (int c0 = 0; c0 < n; c0 += 256) {
+        if (tid < 256) red[tid] = (c0 + tid < n) ? v(c0 + tid) : 0.0;
+        __syncthreads();
+        for (int s = 128; s > 0; s >>= 1) {
+            if (tid < s) red[tid] = fmax(red[tid], red[tid + s]);
+            __syncthreads();
+        }
+        if (tid == 0) acc = fmax(acc, red[0]);
+        __syncthreads();
+    }
+    return acc;
+}
+
+// Eq. 39 with the numerator gap read as xi.
+__device__ void collision_force(double xi0, double xi1, double xj0, double xj1, double Ri, double Rj,
+                                double cij, double gap, double& fx, double& fy) {
+    const double dx = xi0 - xj0, dy = xi1 - xj1;
+    const double d = sqrt(dx * dx + dy * dy);
+    if (d > Ri + Rj + gap || d <= 0.0) return;
+    const double g = (d - Ri - Rj - gap) / gap;
+    const double mag = cij / 0.01 * g * g;
+    fx += mag * dx / d;
+    fy += mag * dy / d;
+}
+
+// marker pass: interpolate (rho, j, jj/rho) at every marker from the band,
+// deviation dm = rho* U - j*, dPi = rho* U U - Pi*
+template <typename T>
+__device__ __forceinline__ void interp_marker(const SimDev& S, const GroupDev& G, int g, const T* node_rho,
+                                              const T* node_jx, const T* node_jy, const T* phi,
+                                              double Ux, double Uy, T& dmx, T& dmy, T& dpxx, T& dpxy,
+                                              T& dpyy, T& rs) {
+    T px[4], py[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        px[k] = phi[g * 8 + k];
+        py[k] = phi[g * 8 + 4 + k];
+    }
+    T r = 0, jx = 0, jy = 0, pxx = 0, pxy = 0, pyy = 0;
+    const int* mn = G.mnode + g * 16;
+#pragma unroll
+    for (int ky = 0; ky < 4; ++ky)
+#pragma unroll
+        for (int kx = 0; kx < 4; ++kx) {
+            const int k = mn[ky * 4 + kx];
+            if (k < 0) continue;
+            const T D = px[kx] * py[ky];
+            const T nr = node_rho[k], nx = node_jx[k], ny = node_jy[k];
+            const T inv = T(1) / nr;
+            r += D * nr;
+            jx += D * nx;
+            jy += D * ny;
+            pxx += D * nx * nx * inv;
+            pxy += D * nx * ny * inv;
+            pyy += D * ny * ny * inv;
+        }
+    const T U = T(Ux), V = T(Uy);
+    dmx = r * U - jx;
+    dmy = r * V - jy;
+    dpxx = r * U * U - pxx;
+    dpxy = r * U * V - pxy;
+    dpyy = r * V * V - pyy;
+    rs = r;
+}
+
+template <typename T, int NT>
+__global__ void __launch_bounds__(NT)
+    k_ib(const SimDev* __restrict__ sims, GroupDev* __restrict__ groups, const BatchHeader* __restrict__ hdr,
+         int ngroups_arg, int parity) {
+    // LDS: plan keys (dynamic plans) share space with the per-marker weights
+    __shared__ unsigned long long smem_keys[kMaxDynEntries];  // 64 KiB
+    __shared__ double red[256];
+    __shared__ int scan_tmp[NT];
+    __shared__ double body_out[8][5];
+    T* lds_w = reinterpret_cast<T*>(smem_keys);  // 2 * M values, M <= 4096 (T = float) / 4096 (double)
+    const int ngroups = hdr ? hdr->ngroups : ngroups_arg;
+    const int tid = threadIdx.x;
+    for (int gi = blockIdx.x; gi < ngroups; gi += gridDim.x) {
+        const GroupDev& G = groups[gi];
+        const SimDev& S = sims[G.sim];
+        if (!S.active) continue;
+        const int sw = 1 - (parity >= 0 ? parity : S.swapped);
+        const int M = G.M;
+        int nband = G.nband, nent = G.nent;
+        if (G.dynamic) {
+            build_plan<NT>(S, G, smem_keys, scan_tmp, nband, nent);
+        }
+        (void)nent;
+        T* node_rho = reinterpret_cast<T*>(G.node_rho);
+        T* node_jx = reinterpret_cast<T*>(G.node_jx);
+        T* node_jy = reinterpret_cast<T*>(G.node_jy);
+        T* phi = reinterpret_cast<T*>(G.m_phi);
+        T* tot = reinterpret_cast<T*>(G.m_tot);
+        // stencil weights of Eq. 15(c) and zeroed accumulators
+        for (int g = tid; g < M; g += NT) {
+            int body;
+            const int mi = marker_index(S, G, g, body);
+            const double X = S.mX[mi], Y = S.mY[mi];
+            const double fx = floor(X) - 1.0, fy = floor(Y) - 1.0;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                phi[g * 8 + k] = phi4<T>(T(fx + k - X));
+                phi[g * 8 + 4 + k] = phi4<T>(T(fy + k - Y));
+            }
+#pragma unroll
+            for (int c = 0; c < 5; ++c) G.m_acc[g * 5 + c] = 0.0;
+        }
+        // gather (rho, j) of the band from the post-stream populations
+        const T rho_base = T(S.rho_base);
+        for (int k = tid; k < nband; k += NT) {
+            const int cell = G.node_cell[k];
+            const int x = cell % S.nx, y = cell / S.nx;
+            T h[9];
+#pragma unroll
+            for (int i = 0; i < 9; ++i) h[i] = *loc<T>(S, i, x, y, sw);
+            const T Ssum = ((h[0] + h[1]) + (h[2] + h[3])) + ((h[4] + h[5]) + (h[6] + h[7])) + h[8];
+            node_rho[k] = rho_base + Ssum;
+            node_jx[k] = (h[1] + h[5] + h[8]) - (h[3] + h[6] + h[7]);
+            node_jy[k] = (h[2] + h[5] + h[6]) - (h[4] + h[7] + h[8]);
+        }
+        __syncthreads();
+        const int iters = S.ib_iters;
+        for (int n = 0; n < iters; ++n) {
+            for (int g = tid; g < M; g += NT) {
+                int body;
+                const int mi = marker_index(S, G, g, body);
+                T dmx, dmy, dpxx, dpxy, dpyy, rs;
+                interp_marker<T>(S, G, g, node_rho, node_jx, node_jy, phi, S.mU[mi], S.mV[mi], dmx, dmy,
+                                 dpxx, dpxy, dpyy, rs);
+                double* acc = G.m_acc + g * 5;
+                acc[0] += (double)dmx;
+                acc[1] += (double)dmy;
+                acc[2] += (double)dpxx;
+                acc[3] += (double)dpxy;
+                acc[4] += (double)dpyy;
+                const T ds = T(S.mds[mi]);
+                lds_w[2 * g] = ds * dmx;
+                lds_w[2 * g + 1] = ds * dmy;
+            }
+            __syncthreads();
+            // Eqs. 26-27 on the momentum: j(x) += sum_l D(x - X_l) ds_l dm_l, ascending l
+            for (int k = tid; k < nband; k += NT) {
+                const int e0 = G.node_run[k], e1 = G.node_run[k + 1];
+                T ix = 0, iy = 0;
+                for (int e = e0; e < e1; ++e) {
+                    const int p = G.ent[e];
+                    const int g = p >> 4;
+                    const T D = phi[g * 8 + (p & 3)] * phi[g * 8 + 4 + ((p >> 2) & 3)];
+                    ix += D * lds_w[2 * g];
+                    iy += D * lds_w[2 * g + 1];
+                }
+                node_jx[k] += ix;
+                node_jy[k] += iy;
+            }
+            __syncthreads();
+        }
+        // mismatch left after the sweeps; totals for the final spread; per-marker force
+        for (int g = tid; g < M; g += NT) {
+            int body;
+            const int mi = marker_index(S, G, g, body);
+            T dmx, dmy, dpxx, dpxy, dpyy, rs;
+            interp_marker<T>(S, G, g, node_rho, node_jx, node_jy, phi, S.mU[mi], S.mV[mi], dmx, dmy, dpxx,
+                             dpxy, dpyy, rs);
+            const double ds = S.mds[mi];
+            const double* acc = G.m_acc + g * 5;
+#pragma unroll
+            for (int c = 0; c < 5; ++c) tot[g * 5 + c] = T(ds * acc[c]);
+            const BodyDev& B = S.bodies[body];
+            const double Fx = -ds * acc[0], Fy = -ds * acc[1];
+            const double r2 = (double)dmx * (double)dmx + (double)dmy * (double)dmy;
+            G.m_red[g * 4 + 0] = Fx;
+            G.m_red[g * 4 + 1] = Fy;
+            G.m_red[g * 4 + 2] = (S.mX[mi] - B.xc[0]) * Fy - (S.mY[mi] - B.xc[1]) * Fx;
+            G.m_red[g * 4 + 3] = r2;
+            lds_w[g] = T(sqrt(r2) / (double)rs);  // slip speed (reuses the weight buffer)
+        }
+        __syncthreads();
+        // final spread of sum_n delta f (Eq. 28 is linear in dm and dPi) and correction (Eq. 27)
+        for (int k = tid; k < nband; k += NT) {
+            const int e0 = G.node_run[k], e1 = G.node_run[k + 1];
+            T A0 = 0, A1 = 0, Bxx = 0, Bxy = 0, Byy = 0;
+            for (int e = e0; e < e1; ++e) {
+                const int p = G.ent[e];
+                const int g = p >> 4;
+                const T D = phi[g * 8 + (p & 3)] * phi[g * 8 + 4 + ((p >> 2) & 3)];
+                A0 += D * tot[g * 5 + 0];
+                A1 += D * tot[g * 5 + 1];
+                Bxx += D * tot[g * 5 + 2];
+                Bxy += D * tot[g * 5 + 3];
+                Byy += D * tot[g * 5 + 4];
+            }
+            const int cell = G.node_cell[k];
+            const int x = cell % S.nx, y = cell / S.nx;
+            const T trB = T(1.5) * (Bxx + Byy);
+#pragma unroll
+            for (int i = 0; i < 9; ++i) {
+                const T ex = T(ex_of(i)), ey = T(ey_of(i));
+                const T d = weight_of<T>(i) *
+                            (T(3) * (ex * A0 + ey * A1) + T(4.5) * (ex * ex * Bxx + T(2) * ex * ey * Bxy + ey * ey * Byy) - trB);
+                T* p = loc<T>(S, i, x, y, sw);
+                *p = *p + d;
+            }
+        }
+        __syncthreads();
+        // FP64 reductions per body (order fixed by the marker index)
+        int base = 0;
+        for (int b = 0; b < G.nbody; ++b) {
+            const int nb = S.bodies[G.body[b]].n;
+            const double* mr = G.m_red + base * 4;
+            const T* slip = lds_w + base;
+            double fx = det_sum<NT>(nb, [&](int l) { return mr[l * 4 + 0]; }, red);
+            double fy = det_sum<NT>(nb, [&](int l) { return mr[l * 4 + 1]; }, red);
+            double tq = det_sum<NT>(nb, [&](int l) { return mr[l * 4 + 2]; }, red);
+            double r2 = det_sum<NT>(nb, [&](int l) { return mr[l * 4 + 3]; }, red);
+            double mx = det_max<NT>(nb, [&](int l) { return (double)slip[l]; }, red);
+            if (tid == 0) {
+                body_out[b][0] = fx;
+                body_out[b][1] = fy;
+                body_out[b][2] = tq;
+                body_out[b][3] = sqrt(r2 / nb);
+                body_out[b][4] = mx;
+            }
+            base += nb;
+        }
+        __syncthreads();
+        // outputs and the rigid-body update of free circles (Eqs. 37, 39-42)
+        if (tid == 0) {
+            BodyDev* bodies = S.bodies;
+            for (int b = 0; b < G.nbody; ++b) {
+                BodyDev& B = bodies[G.body[b]];
+                B.F[0] = body_out[b][0];
+                B.F[1] = body_out[b][1];
+                B.T = body_out[b][2];
+                B.resid = body_out[b][3];
+                B.maxslip = body_out[b][4];
+            }
+            double Fc[8][2];
+            const double gmag = sqrt(S.gravity[0] * S.gravity[0] + S.gravity[1] * S.gravity[1]);
+            const double rho_f = S.rho0;
+            for (int b = 0; b < G.nbody; ++b) {
+                Fc[b][0] = Fc[b][1] = 0.0;
+                const BodyDev& B = bodies[G.body[b]];
+                if (B.kind != BODY_FREE) continue;
+                const double V = M_PI * B.R * B.R;
+                const double cij = (B.rho_s * V - rho_f * V) * gmag;
+                const double gap = 0.1 * B.R;
+                for (int c = 0; c < G.nbody; ++c) {
+                    const BodyDev& O = bodies[G.body[c]];
+                    if (c == b || O.kind != BODY_FREE) continue;
+                    collision_force(B.xc[0], B.xc[1], O.xc[0], O.xc[1], B.R, O.R, cij, gap, Fc[b][0], Fc[b][1]);
+                }
+                const double mir[4][2] = {{-1.0 - B.xc[0], B.xc[1]},
+                                          {2.0 * S.nx - 1.0 - B.xc[0], B.xc[1]},
+                                          {B.xc[0], -1.0 - B.xc[1]},
+                                          {B.xc[0], 2.0 * S.ny - 1.0 - B.xc[1]}};
+                for (int w = 0; w < 4; ++w) {
+                    if (S.bc[w] != BC_WALL && S.bc[w] != BC_FREESLIP) continue;
+                    collision_force(B.xc[0], B.xc[1], mir[w][0], mir[w][1], B.R, B.R, cij, gap, Fc[b][0],
+                                    Fc[b][1]);
+                }
+            }
+            for (int b = 0; b < G.nbody; ++b) {
+                BodyDev& B = bodies[G.body[b]];
+                if (B.kind != BODY_FREE) continue;
+                const double V = M_PI * B.R * B.R, Ms = B.rho_s * V, Is = 0.5 * Ms * B.R * B.R;
+                const double Ftx = B.F[0] + rho_f * V * (B.U[0] - B.Uprev[0]) + Fc[b][0] + (Ms - rho_f * V) * S.gravity[0];
+                const double Fty = B.F[1] + rho_f * V * (B.U[1] - B.Uprev[1]) + Fc[b][1] + (Ms - rho_f * V) * S.gravity[1];
+                const double Tt = B.T + (rho_f / B.rho_s) * Is * (B.omega - B.omega_prev);
+                B.xc[0] += B.U[0] + 0.5 * Ftx / Ms;
+                B.xc[1] += B.U[1] + 0.5 * Fty / Ms;
+                B.theta += B.omega + 0.5 * Tt / Is;
+                B.Uprev[0] = B.U[0];
+                B.Uprev[1] = B.U[1];
+                B.omega_prev = B.omega;
+                B.U[0] += Ftx / Ms;
+                B.U[1] += Fty / Ms;
+                B.omega += Tt / Is;
+            }
+        }
+        __syncthreads();
+        // regenerate the markers of free circles for the next step
+        for (int g = tid; g < M; g += NT) {
+            int body;
+            const int mi = marker_index(S, G, g, body);
+            const BodyDev& B = S.bodies[body];
+            if (B.kind != BODY_FREE) continue;
+            const int l = mi - B.m0;
+            const double a = 2.0 * M_PI * l / B.n + B.theta;
+            const double X = B.xc[0] + B.R * cos(a), Y = B.xc[1] + B.R * sin(a);
+            S.mX[mi] = X;
+            S.mY[mi] = Y;
+            S.mU[mi] = B.U[0] - B.omega * (Y - B.xc[1]);
+            S.mV[mi] = B.U[1] + B.omega * (X - B.xc[0]);
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------- bookkeeping and I/O
+
+__global__ void k_advance(SimDev* sims, const BatchHeader* hdr, int nsims_arg) {
+    const int nsims = hdr ? hdr->nsims : nsims_arg;
+    for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < nsims; s += gridDim.x * blockDim.x) {
+        SimDev& S = sims[s];
+        if (!S.active) continue;
+        S.swapped ^= 1;
+        S.steps_done += 1;
+        if (S.steps_left > 0) {
+            S.steps_left -= 1;
+            if (S.steps_left == 0) S.active = 0;
+        }
+    }
+}
+
+template <typename T>
+__global__ void k_fields(const SimDev* sim, int sw, double* rho, double* ux, double* uy) {
+    const SimDev& S = *sim;
+    const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
+    if (x >= S.nx) return;
+    double h[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) h[i] = (double)*loc<T>(S, i, x, y, sw);
+    const double Ssum = ((h[0] + h[1]) + (h[2] + h[3])) + ((h[4] + h[5]) + (h[6] + h[7])) + h[8];
+    const double r = S.rho_base + Ssum;
+    const double jx = (h[1] + h[5] + h[8]) - (h[3] + h[6] + h[7]);
+    const double jy = (h[2] + h[5] + h[6]) - (h[4] + h[7] + h[8]);
+    const int64_t c = (int64_t)y * S.nx + x;
+    if (rho) rho[c] = r;
+    if (ux) ux[c] = jx / r;
+    if (uy) uy[c] = jy / r;
+}
+
+template <typename T>
+__global__ void k_get_pop(const SimDev* sim, int sw, double* f) {
+    const SimDev& S = *sim;
+    const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
+    if (x >= S.nx) return;
+    const int64_t np = (int64_t)S.nx * S.ny, c = (int64_t)y * S.nx + x;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) f[i * np + c] = (double)*loc<T>(S, i, x, y, sw) + weight_of<double>(i) * S.rho_base;
+}
+
+template <typename T>
+__global__ void k_set_pop(const SimDev* sim, int sw, const double* f) {
+    const SimDev& S = *sim;
+    const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
+    if (x >= S.nx) return;
+    const int64_t np = (int64_t)S.nx * S.ny, c = (int64_t)y * S.nx + x;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) *loc<T>(S, i, x, y, sw) = T(f[i * np + c] - weight_of<double>(i) * S.rho_base);
+}
+
+template <typename T>
+__global__ void k_set_eq(const SimDev* sim, int sw, const double* rho, const double* ux, const double* uy,
+                         double rho0, double u0x, double u0y) {
+    const SimDev& S = *sim;
+    const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
+    if (x >= S.nx) return;
+    const int64_t c = (int64_t)y * S.nx + x;
+    const double r = rho ? rho[c] : rho0, u = ux ? ux[c] : u0x, v = uy ? uy[c] : u0y;
+    const double uu = u * u + v * v;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        const double eu = ex_of(i) * u + ey_of(i) * v;
+        const double feq = weight_of<double>(i) * r * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * uu);
+        *loc<T>(S, i, x, y, sw) = T(feq - weight_of<double>(i) * S.rho_base);
+    }
+}
+
+// ---------------------------------------------------------------- launchers
+
+template <typename T, int TX, int TY, int RPT>
+static hipError_t sweep_t(const SimDev* sims, const int4* tiles, const BatchHeader* hdr, int ntiles, int grid,
+                          int parity, hipStream_t st) {
+    hipLaunchKernelGGL((k_sweep<T, TX, TY, RPT>), dim3(grid), dim3(TX, TY), 0, st, sims, tiles, hdr, ntiles,
+                       parity);
+    return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t sweep_tt(int tiling, const SimDev* sims, const int4* tiles, const BatchHeader* hdr, int ntiles,
+                           int grid, int parity, hipStream_t st) {
+    switch (tiling) {
+        case 0: return sweep_t<T, 64, 4, 1>(sims, tiles, hdr, ntiles, grid, parity, st);
+        case 1: return sweep_t<T, 64, 4, 2>(sims, tiles, hdr, ntiles, grid, parity, st);
+        case 2: return sweep_t<T, 128, 2, 2>(sims, tiles, hdr, ntiles, grid, parity, st);
+        case 3: return sweep_t<T, 256, 1, 2>(sims, tiles, hdr, ntiles, grid, parity, st);
+        case 4: return sweep_t<T, 256, 1, 4>(sims, tiles, hdr, ntiles, grid, parity, st);
+        case 5: return sweep_t<T, 64, 4, 4>(sims, tiles, hdr, ntiles, grid, parity, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_sweep(bool f64, int tiling, const SimDev* sims, const int4* tiles, const BatchHeader* hdr,
+                        int ntiles, int grid, int parity, hipStream_t stream) {
+    if (grid <= 0) return hipSuccess;
+    return f64 ? sweep_tt<double>(tiling, sims, tiles, hdr, ntiles, grid, parity, stream)
+               : sweep_tt<float>(tiling, sims, tiles, hdr, ntiles, grid, parity, stream);
+}
+
+hipError_t launch_boundary(bool f64, const SimDev* sims, const int2* items, const BatchHeader* hdr, int nitems,
+                           int grid, int parity, hipStream_t stream) {
+    if (grid <= 0) return hipSuccess;
+    if (f64)
+        hipLaunchKernelGGL(k_boundary<double>, dim3(grid), dim3(256), 0, stream, sims, items, hdr, nitems, parity);
+    else
+        hipLaunchKernelGGL(k_boundary<float>, dim3(grid), dim3(256), 0, stream, sims, items, hdr, nitems, parity);
+    return hipGetLastError();
+}
+
+hipError_t launch_ib(bool f64, const SimDev* sims, GroupDev* groups, const BatchHeader* hdr, int ngroups, int grid,
+                     int parity, hipStream_t stream) {
+    if (grid <= 0) return hipSuccess;
+    if (f64)
+        hipLaunchKernelGGL((k_ib<double, kIbThreads>), dim3(grid), dim3(kIbThreads), 0, stream, sims, groups, hdr,
+                           ngroups, parity);
+    else
+        hipLaunchKernelGGL((k_ib<float, kIbThreads>), dim3(grid), dim3(kIbThreads), 0, stream, sims, groups, hdr,
+                           ngroups, parity);
+    return hipGetLastError();
+}
+
+hipError_t launch_advance(SimDev* sims, const BatchHeader* hdr, int nsims, hipStream_t stream) {
+    hipLaunchKernelGGL(k_advance, dim3(1), dim3(256), 0, stream, sims, hdr, nsims);
+    return hipGetLastError();
+}
+
+#define IO_LAUNCH(kern, ...)                                                                             \
+    do {                                                                                                 \
+        dim3 grid((nx + 127) / 128, ny), block(128);                                                     \
+        if (f64)                                                                                         \
+            hipLaunchKernelGGL(kern<double>, grid, block, 0, stream, __VA_ARGS__);                       \
+        else                                                                                             \
+            hipLaunchKernelGGL(kern<float>, grid, block, 0, stream, __VA_ARGS__);                        \
+        return hipGetLastError();                                                                        \
+    } while (0)
+
+hipError_t launch_fields(bool f64, const SimDev* sim, int nx, int ny, int sw, double* rho, double* ux, double* uy,
+                         hipStream_t stream) {
+    IO_LAUNCH(k_fields, sim, sw, rho, ux, uy);
+}
+hipError_t launch_get_pop(bool f64, const SimDev* sim, int nx, int ny, int sw, double* f, hipStream_t stream) {
+    IO_LAUNCH(k_get_pop, sim, sw, f);
+}
+hipError_t launch_set_pop(bool f64, const SimDev* sim, int nx, int ny, int sw, const double* f,
+                          hipStream_t stream) {
+    IO_LAUNCH(k_set_pop, sim, sw, f);
+}
+hipError_t launch_set_eq(bool f64, const SimDev* sim, int nx, int ny, int sw, const double* rho, const double* ux,
+                         const double* uy, double rho0, double u0x, double u0y, hipStream_t stream) {
+    IO_LAUNCH(k_set_eq, sim, sw, rho, ux, uy, rho0, u0x, u0y);
+}
+
+}  // namespace lbmib

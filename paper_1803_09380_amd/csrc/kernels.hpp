@@ -1,0 +1,48 @@
+// Host-side launchers of the gfx950 kernels (implemented in kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "lbm_device.hpp"
+
+namespace lbmib {
+
+// Sweep tilings: threads along x, thread rows per block, lattice rows per thread.
+struct Tiling {
+    int tx, ty, rpt;
+};
+constexpr int kNumTilings = 6;
+extern const Tiling kTilings[kNumTilings];
+
+// Threads per correction workgroup (the results do not depend on it).
+constexpr int kIbThreads = 512;
+// Entries sorted in LDS when a plan is rebuilt on the device (16 per marker).
+constexpr int kMaxDynEntries = 8192;
+constexpr int kMaxGroupMarkers = 4096;
+
+// All launchers enqueue on `stream`.  `parity` >= 0 forces the AA state the
+// step starts from; -1 reads it from each simulation's descriptor (batches).
+// Counts come from `hdr` when it is non-null (graph-captured batches),
+// otherwise from the explicit count arguments.
+hipError_t launch_sweep(bool f64, int tiling, const SimDev* sims, const int4* tiles,
+                        const BatchHeader* hdr, int ntiles, int grid, int parity,
+                        hipStream_t stream);
+hipError_t launch_boundary(bool f64, const SimDev* sims, const int2* items, const BatchHeader* hdr,
+                           int nitems, int grid, int parity, hipStream_t stream);
+hipError_t launch_ib(bool f64, const SimDev* sims, GroupDev* groups, const BatchHeader* hdr,
+                     int ngroups, int grid, int parity, hipStream_t stream);
+hipError_t launch_advance(SimDev* sims, const BatchHeader* hdr, int nsims, hipStream_t stream);
+// Field and population I/O of one simulation (state `sw` = AA state now).
+hipError_t launch_fields(bool f64, const SimDev* sim, int nx, int ny, int sw, double* rho,
+                         double* ux, double* uy, hipStream_t stream);
+hipError_t launch_get_pop(bool f64, const SimDev* sim, int nx, int ny, int sw, double* f,
+                          hipStream_t stream);
+hipError_t launch_set_pop(bool f64, const SimDev* sim, int nx, int ny, int sw, const double* f,
+                          hipStream_t stream);
+// Equilibrium of the given FP64 device fields (or of rho0/u0 when the field
+// pointers are null).
+hipError_t launch_set_eq(bool f64, const SimDev* sim, int nx, int ny, int sw, const double* rho,
+                         const double* ux, const double* uy, double rho0, double u0x, double u0y,
+                         hipStream_t stream);
+
+}  // namespace lbmib

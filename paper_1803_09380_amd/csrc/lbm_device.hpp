@@ -1,0 +1,150 @@
+// Device-side descriptors and lattice helpers of the gfx950 IB-LBM library.
+//
+// Population storage (per simulation): nine planes, one per lattice direction,
+// each (ny + 2) rows of `pitch` elements.  Row r holds lattice row y = r - 1,
+// so rows y = -1 and y = ny are a ghost layer; within a row, x = 0 sits at
+// element `xoff` (a 128-byte boundary) and x = -1, x = nx are ghost cells.
+// The ghost layer receives populations that leave through a non-periodic side
+// and holds the post-stream values that the boundary kernel writes for the
+// next sweep to read.
+//
+// In-place AA access pattern: `swapped` = 0 ("natural") means the post-stream
+// population f_i(x) lives in slot i of cell x; `swapped` = 1 means it lives
+// in slot opp(i) of cell x - e_i.  A sweep on a natural state reads its own
+// cell and writes the post-collision f*_i into slot opp(i) of the same cell
+// (result: swapped); a sweep on a swapped state reads slot opp(i) of x - e_i
+// and writes f*_i into slot i of x + e_i (result: natural).  Every slot is
+// read once and written once per sweep, by the same thread.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbmib {
+
+constexpr int Q = 9;
+
+// D2Q9 order fixed by the j_x and j_y rows of the moment matrix (Eq. 5).
+__host__ __device__ constexpr int ex_of(int i) {
+    return i == 1 || i == 5 || i == 8 ? 1 : (i == 3 || i == 6 || i == 7 ? -1 : 0);
+}
+__host__ __device__ constexpr int ey_of(int i) {
+    return i == 2 || i == 5 || i == 6 ? 1 : (i == 4 || i == 7 || i == 8 ? -1 : 0);
+}
+__host__ __device__ constexpr int opp_of(int i) {
+    return i == 0 ? 0 : (i <= 4 ? ((i + 1) % 4) + 1 : ((i - 3) % 4) + 5);
+}
+// mirror in y (specular reflection on a south/north wall)
+__host__ __device__ constexpr int mirror_y(int i) {
+    return i == 2 ? 4 : i == 4 ? 2 : i == 5 ? 8 : i == 8 ? 5 : i == 6 ? 7 : i == 7 ? 6 : i;
+}
+template <typename T>
+__host__ __device__ constexpr T weight_of(int i) {
+    return i == 0 ? T(4) / T(9) : (i <= 4 ? T(1) / T(9) : T(1) / T(36));
+}
+
+enum : int32_t { BC_PERIODIC = 0, BC_WALL = 1, BC_FREESLIP = 2, BC_VELOCITY = 3, BC_OUTFLOW = 4 };
+enum : int32_t { SIDE_W = 0, SIDE_E = 1, SIDE_S = 2, SIDE_N = 3 };
+enum : int32_t { BODY_FIXED = 0, BODY_FREE = 1 };
+
+// status bits (sticky, per simulation)
+enum : uint32_t { ST_UNSTABLE = 1u, ST_PLAN_OVERFLOW = 2u };
+
+struct BodyDev {
+    int32_t kind, n, m0, used;  // marker count, offset into the simulation's marker arrays
+    double xc[2], U[2], omega, theta, R, rho_s;
+    double Uprev[2], omega_prev;
+    double F[2], T, resid, maxslip;  // outputs of the last step
+};
+
+struct SimDev {
+    void* pop;           // T* base of the nine planes
+    int64_t plane;       // elements per plane
+    int32_t pitch, xoff; // elements per row, offset of x = 0
+    int32_t nx, ny;
+    int32_t bc[4];       // W, E, S, N
+    int32_t px, py;      // periodic axes
+    double omega;        // 1 / tau
+    double rho0;         // reference density
+    double rho_base;     // 0 (FP64 stores f) or rho0 (FP32 stores f - w rho0)
+    double u_in[2];
+    double gravity[2];
+    int32_t swapped;     // AA state of the populations (see above)
+    int32_t active;      // batch: still stepping
+    int64_t steps_left;  // batch: < 0 means unlimited
+    int64_t steps_done;
+    uint32_t* status;    // sticky status bits
+    int32_t nperim;      // boundary nodes that need a rule each step
+    int32_t nbody;
+    int32_t ib_iters;    // correction sweeps per step
+    int32_t pad_;
+    BodyDev* bodies;     // [LBM_MAX_BODIES]
+    double *mX, *mY, *mU, *mV, *mds;  // markers of all bodies, FP64
+};
+
+// One group of bodies whose delta stencils may share nodes; one workgroup
+// corrects a group.  Plan arrays describe the band (the union of the markers'
+// 4 x 4 stencils): band nodes in ascending cell order, and for each band node
+// the run of stencil entries touching it in ascending marker order.
+struct GroupDev {
+    int32_t sim;              // index into the simulation table
+    int32_t nbody;
+    int32_t body[8];          // body slots, ascending
+    int32_t M;                // markers in the group
+    int32_t dynamic;          // 1: plan rebuilt on the device every step
+    int32_t nband, nent;      // static plan sizes
+    int32_t cap_nodes, cap_ent;
+    int32_t* node_cell;       // [cap_nodes] cell key y * nx + x
+    int32_t* node_run;        // [cap_nodes + 1] first entry of each node
+    int32_t* ent;             // [cap_ent] (group marker << 4) | (ky << 2) | kx
+    int32_t* mnode;           // [M * 16] band node of each stencil slot, -1 if dropped
+    int32_t* plan_size;       // [2] device-side nband, nent (dynamic plans)
+    void* node_rho;           // T [cap_nodes]
+    void* node_jx;            // T [cap_nodes]
+    void* node_jy;            // T [cap_nodes]
+    void* m_phi;              // T [M * 8]: phi_x[4], phi_y[4]
+    void* m_tot;              // T [M * 5]: ds * (sum dm, sum dPi) for the final spread
+    double* m_acc;            // [M * 5] running sums of dm (2) and dPi (3), FP64
+    double* m_red;            // [M * 4] per-marker Fx, Fy, T, |dm|^2 for reductions
+};
+
+// Work counts of a batch, read by persistent kernels so that a captured graph
+// stays valid while the tables change.
+struct BatchHeader {
+    int32_t nsims, ntiles, nbc, ngroups;
+};
+
+// ---------------------------------------------------------------- indexing
+
+__device__ __forceinline__ int wrap(int v, int n, int periodic) {
+    if (periodic) {
+        if (v < 0) return v + n;
+        if (v >= n) return v - n;
+    }
+    return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T* slot(const SimDev& S, int i, int x, int y) {
+    return reinterpret_cast<T*>(S.pop) + (int64_t)i * S.plane + (int64_t)(y + 1) * S.pitch + S.xoff + x;
+}
+
+// Where the post-stream f_i(x, y) lives for AA state `sw`.
+template <typename T>
+__device__ __forceinline__ T* loc(const SimDev& S, int i, int x, int y, int sw) {
+    if (sw) {
+        int sx = wrap(x - ex_of(i), S.nx, S.px), sy = wrap(y - ey_of(i), S.ny, S.py);
+        return slot<T>(S, opp_of(i), sx, sy);
+    }
+    return slot<T>(S, i, x, y);
+}
+
+// Where the post-collision f*_i(x, y) of the sweep that produced state `sw` lives.
+template <typename T>
+__device__ __forceinline__ T* pc(const SimDev& S, int i, int x, int y, int sw) {
+    if (sw) return slot<T>(S, opp_of(i), x, y);
+    int tx = wrap(x + ex_of(i), S.nx, S.px), ty = wrap(y + ey_of(i), S.ny, S.py);
+    return slot<T>(S, i, tx, ty);
+}
+
+}  // namespace lbmib

@@ -1,0 +1,1093 @@
+// Host runtime and C ABI of the gfx950 IB-LBM library (declared in include/lbmib.h).
+//
+// A simulation owns its device state: the nine population planes with a ghost
+// layer (see lbm_device.hpp), a one-entry descriptor table, its body and
+// marker arrays, the work tables of its own steps (sweep tiles, boundary
+// chunks, body groups) and each group's plan and scratch.  Plans of groups
+// without free bodies are built here once, when markers are set; groups with
+// free bodies rebuild theirs on the device every step.  A batch concatenates
+// the work tables of its admitted simulations into device-resident tables and
+// replays captured HIP graphs of persistent kernels that read those tables.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "../../include/lbmib.h"
+#include "kernels.hpp"
+
+using namespace lbmib;
+
+namespace {
+
+constexpr int kTileDefault = 1;
+
+template <typename... A>
+std::string fmt(const char* f, A... a) {
+    char buf[512];
+    snprintf(buf, sizeof buf, f, a...);
+    return buf;
+}
+
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    hipError_t alloc(size_t n) {
+        release();
+        if (n == 0) return hipSuccess;
+        hipError_t e = hipMalloc(&p, n);
+        if (e != hipSuccess) {
+            p = nullptr;
+            return e;
+        }
+        bytes = n;
+        return hipSuccess;
+    }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    ~DevBuf() { release(); }
+    DevBuf() = default;
+    DevBuf(const DevBuf&) = delete;
+    DevBuf& operator=(const DevBuf&) = delete;
+};
+
+struct HostBody {
+    bool used = false;
+    int kind = 0, n = 0;
+    std::vector<double> X, Y, U, V, ds;
+    ib_body b{};
+};
+
+// One group's plan and scratch on the device plus its host descriptor.
+struct Group {
+    GroupDev d{};
+    DevBuf node_cell, node_run, ent, mnode, plan_size, node_rho, node_jx, node_jy, m_phi, m_tot, m_acc, m_red;
+};
+
+}  // namespace
+
+struct lbm_sim {
+    lbm_params p{};
+    bool f64 = true;
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    std::string err;
+    DevBuf pop, desc, status, bodies, markers, tiles, bcitems, groups;
+    SimDev h{};                // host mirror of the descriptor
+    HostBody body[LBM_MAX_BODIES];
+    std::vector<Group*> grp;
+    std::vector<int4> h_tiles;
+    std::vector<int2> h_bc;
+    int tiling = kTileDefault;
+    int64_t steps = 0;
+    int mcount = 0;
+    lbm_batch* batch = nullptr;
+    ~lbm_sim() {
+        for (Group* g : grp) delete g;
+    }
+};
+
+struct lbm_batch {
+    bool f64 = false;
+    size_t budget = 0;
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    std::vector<lbm_sim*> sims;
+    std::vector<int64_t> steps_req;
+    DevBuf d_sims, d_tiles, d_bc, d_groups, d_hdr;
+    size_t cap_sims = 0, cap_tiles = 0, cap_bc = 0, cap_groups = 0;
+    int ntiles = 0, nbc = 0, ngroups = 0;
+    int tiling = kTileDefault;
+    int grid_sweep = 0, grid_bc = 0, grid_ib = 0;
+    hipGraphExec_t graph1 = nullptr, graphK = nullptr;
+    int graphK_steps = 8;
+    size_t bytes = 0;
+    std::string err;
+    ~lbm_batch() {
+        if (graph1) (void)hipGraphExecDestroy(graph1);
+        if (graphK) (void)hipGraphExecDestroy(graphK);
+    }
+};
+
+namespace {
+
+lbm_status fail(lbm_sim* s, lbm_status st, const std::string& msg) {
+    if (s) s->err = msg;
+    return st;
+}
+lbm_status failb(lbm_batch* b, lbm_status st, const std::string& msg) {
+    if (b) b->err = msg;
+    return st;
+}
+lbm_status hipfail(lbm_sim* s, hipError_t e, const char* where) {
+    return fail(s, e == hipErrorOutOfMemory ? LBM_ERR_NOMEM : LBM_ERR_DEVICE,
+                fmt("%s: %s", where, hipGetErrorString(e)));
+}
+
+#define HIPS(s, call)                                      \
+    do {                                                   \
+        hipError_t e_ = (call);                            \
+        if (e_ != hipSuccess) return hipfail(s, e_, #call); \
+    } while (0)
+
+int num_cus(int dev) {
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) n = 256;
+    return n;
+}
+
+bool bc_valid(const lbm_params* p) {
+    auto ok = [](int v) { return v >= LBM_BC_PERIODIC && v <= LBM_BC_OUTFLOW; };
+    if (!ok(p->bc_west) || !ok(p->bc_east) || !ok(p->bc_south) || !ok(p->bc_north)) return false;
+    if ((p->bc_west == LBM_BC_PERIODIC) != (p->bc_east == LBM_BC_PERIODIC)) return false;
+    if ((p->bc_south == LBM_BC_PERIODIC) != (p->bc_north == LBM_BC_PERIODIC)) return false;
+    if (p->bc_west == LBM_BC_FREESLIP || p->bc_west == LBM_BC_OUTFLOW) return false;
+    if (p->bc_east == LBM_BC_FREESLIP || p->bc_east == LBM_BC_VELOCITY) return false;
+    if (p->bc_south == LBM_BC_VELOCITY || p->bc_south == LBM_BC_OUTFLOW) return false;
+    if (p->bc_north == LBM_BC_VELOCITY || p->bc_north == LBM_BC_OUTFLOW) return false;
+    return true;
+}
+
+int perimeter_count(const SimDev& h) {
+    int n = 0;
+    if (!h.py) n += 2 * h.nx;
+    if (!h.px) n += 2 * (h.py ? h.ny : h.ny - 2);
+    return n;
+}
+
+void build_tiles(lbm_sim* s, int sim_index, int tiling, std::vector<int4>& out) {
+    const Tiling& t = kTilings[tiling];
+    const int th = t.ty * t.rpt;
+    for (int y0 = 0; y0 < s->p.ny; y0 += th)
+        for (int x0 = 0; x0 < s->p.nx; x0 += t.tx) out.push_back(make_int4(sim_index, x0, y0, 0));
+}
+
+void build_bc(lbm_sim* s, int sim_index, std::vector<int2>& out) {
+    for (int k = 0; k < s->h.nperim; k += 256) out.push_back(make_int2(sim_index, k));
+}
+
+bool stencil_cell_host(const SimDev& S, double X, double Y, int kx, int ky, int& cell) {
+    int x = (int)std::floor(X) - 1 + kx, y = (int)std::floor(Y) - 1 + ky;
+    if (S.px) x = x < 0 ? x + S.nx : (x >= S.nx ? x - S.nx : x);
+    if (S.py) y = y < 0 ? y + S.ny : (y >= S.ny ? y - S.ny : y);
+    if (x < 0 || x >= S.nx || y < 0 || y >= S.ny) return false;
+    cell = y * S.nx + x;
+    return true;
+}
+
+std::vector<int> body_cells(const lbm_sim* s, int b) {
+    std::vector<int> c;
+    const HostBody& B = s->body[b];
+    for (int l = 0; l < B.n; ++l)
+        for (int k = 0; k < 16; ++k) {
+            int cell;
+            if (stencil_cell_host(s->h, B.X[l], B.Y[l], k & 3, k >> 2, cell)) c.push_back(cell);
+        }
+    std::sort(c.begin(), c.end());
+    c.erase(std::unique(c.begin(), c.end()), c.end());
+    return c;
+}
+
+template <typename V>
+hipError_t upload(DevBuf& buf, const std::vector<V>& v, hipStream_t st) {
+    hipError_t e = buf.alloc(std::max<size_t>(1, v.size()) * sizeof(V));
+    if (e != hipSuccess) return e;
+    if (v.empty()) return hipSuccess;
+    return hipMemcpyAsync(buf.p, v.data(), v.size() * sizeof(V), hipMemcpyHostToDevice, st);
+}
+
+// (Re)build bodies, markers and groups of a simulation after a marker change.
+lbm_status rebuild_ib(lbm_sim* s) {
+    hipStream_t st = s->stream;
+    // markers of all bodies, concatenated in slot order
+    std::vector<double> arr[5];
+    std::vector<BodyDev> bd(LBM_MAX_BODIES);
+    int m = 0, nbody = 0;
+    bool any_free = false;
+    for (int b = 0; b < LBM_MAX_BODIES; ++b) {
+        BodyDev& d = bd[b];
+        memset(&d, 0, sizeof d);
+        const HostBody& B = s->body[b];
+        if (!B.used) continue;
+        ++nbody;
+        d.used = 1;
+        d.kind = B.kind;
+        d.n = B.n;
+        d.m0 = m;
+        d.xc[0] = B.b.xc[0];
+        d.xc[1] = B.b.xc[1];
+        d.U[0] = B.b.U[0];
+        d.U[1] = B.b.U[1];
+        d.omega = B.b.omega;
+        d.theta = B.b.theta;
+        d.R = B.b.radius;
+        d.rho_s = B.b.rho_s;
+        d.Uprev[0] = d.U[0];
+        d.Uprev[1] = d.U[1];
+        d.omega_prev = d.omega;
+        any_free |= B.kind == IB_FREE;
+        for (int l = 0; l < B.n; ++l) {
+            arr[0].push_back(B.X[l]);
+            arr[1].push_back(B.Y[l]);
+            arr[2].push_back(B.U[l]);
+            arr[3].push_back(B.V[l]);
+            arr[4].push_back(B.ds[l]);
+        }
+        m += B.n;
+    }
+    s->mcount = m;
+    HIPS(s, s->bodies.alloc(sizeof(BodyDev) * LBM_MAX_BODIES));
+    HIPS(s, hipMemcpyAsync(s->bodies.p, bd.data(), sizeof(BodyDev) * LBM_MAX_BODIES, hipMemcpyHostToDevice, st));
+    HIPS(s, s->markers.alloc(sizeof(double) * 5 * std::max(1, m)));
+    double* mk = static_cast<double*>(s->markers.p);
+    for (int a = 0; a < 5; ++a)
+        if (m) HIPS(s, hipMemcpyAsync(mk + (size_t)a * m, arr[a].data(), sizeof(double) * m, hipMemcpyHostToDevice, st));
+    s->h.bodies = static_cast<BodyDev*>(s->bodies.p);
+    s->h.mX = mk;
+    s->h.mY = mk + m;
+    s->h.mU = mk + 2 * (size_t)m;
+    s->h.mV = mk + 3 * (size_t)m;
+    s->h.mds = mk + 4 * (size_t)m;
+    s->h.nbody = nbody;
+
+    // groups: all bodies together when one is free, else by shared stencil nodes
+    std::vector<std::vector<int>> groups;
+    if (any_free) {
+        std::vector<int> all;
+        for (int b = 0; b < LBM_MAX_BODIES; ++b)
+            if (s->body[b].used) all.push_back(b);
+        groups.push_back(all);
+    } else {
+        std::vector<std::vector<int>> cells(LBM_MAX_BODIES);
+        std::vector<int> parent(LBM_MAX_BODIES);
+        std::iota(parent.begin(), parent.end(), 0);
+        auto find = [&](int a) {
+            while (parent[a] != a) a = parent[a] = parent[parent[a]];
+            return a;
+        };
+        for (int b = 0; b < LBM_MAX_BODIES; ++b)
+            if (s->body[b].used) cells[b] = body_cells(s, b);
+        for (int a = 0; a < LBM_MAX_BODIES; ++a)
+            for (int b = a + 1; b < LBM_MAX_BODIES; ++b) {
+                if (!s->body[a].used || !s->body[b].used) continue;
+                std::vector<int> both;
+                std::set_intersection(cells[a].begin(), cells[a].end(), cells[b].begin(), cells[b].end(),
+                                      std::back_inserter(both));
+                if (!both.empty()) parent[find(a)] = find(b);
+            }
+        for (int b = 0; b < LBM_MAX_BODIES; ++b) {
+            if (!s->body[b].used) continue;
+            bool placed = false;
+            for (auto& g : groups)
+                if (find(g[0]) == find(b)) {
+                    g.push_back(b);
+                    placed = true;
+                    break;
+                }
+            if (!placed) groups.push_back({b});
+        }
+    }
+    for (Group* g : s->grp) delete g;
+    s->grp.clear();
+    const size_t tsz = s->f64 ? sizeof(double) : sizeof(float);
+    for (auto& members : groups) {
+        Group* G = new (std::nothrow) Group();
+        if (!G) return fail(s, LBM_ERR_NOMEM, "host allocation");
+        s->grp.push_back(G);
+        GroupDev& d = G->d;
+        d.sim = 0;
+        d.nbody = (int)members.size();
+        int M = 0;
+        for (int k = 0; k < d.nbody; ++k) {
+            d.body[k] = members[k];
+            M += s->body[members[k]].n;
+        }
+        d.M = M;
+        d.dynamic = any_free ? 1 : 0;
+        if (M > kMaxGroupMarkers) return fail(s, LBM_ERR_INVALID, "too many markers in one body group");
+        if (d.dynamic && 16 * M > kMaxDynEntries)
+            return fail(s, LBM_ERR_INVALID, "too many markers in a simulation with free bodies");
+        d.cap_ent = 16 * M;
+        int nband = 16 * M;
+        std::vector<int> node_cell, node_run, ent, mnode(16 * (size_t)M, -1);
+        if (!d.dynamic) {
+            // same definition as the device build: entries sorted by cell, then marker
+            std::vector<unsigned long long> keys;
+            int g = 0;
+            for (int b : members) {
+                const HostBody& B = s->body[b];
+                for (int l = 0; l < B.n; ++l, ++g)
+                    for (int k = 0; k < 16; ++k) {
+                        int cell;
+                        if (stencil_cell_host(s->h, B.X[l], B.Y[l], k & 3, k >> 2, cell))
+                            keys.push_back(((unsigned long long)(unsigned)cell << 32) | (unsigned)((g << 4) | k));
+                    }
+            }
+            std::sort(keys.begin(), keys.end());
+            for (size_t e = 0; e < keys.size(); ++e) {
+                const int cell = (int)(keys[e] >> 32), low = (int)(keys[e] & 0xffffffffu);
+                if (e == 0 || (keys[e - 1] >> 32) != (keys[e] >> 32)) {
+                    node_cell.push_back(cell);
+                    node_run.push_back((int)e);
+                }
+                ent.push_back(low);
+                mnode[low] = (int)node_cell.size() - 1;
+            }
+            node_run.push_back((int)ent.size());
+            nband = (int)node_cell.size();
+            d.nband = nband;
+            d.nent = (int)ent.size();
+        }
+        d.cap_nodes = std::max(1, nband);
+        HIPS(s, G->node_cell.alloc(sizeof(int) * d.cap_nodes));
+        HIPS(s, G->node_run.alloc(sizeof(int) * (d.cap_nodes + 1)));
+        HIPS(s, G->ent.alloc(sizeof(int) * std::max(1, d.cap_ent)));
+        HIPS(s, G->mnode.alloc(sizeof(int) * std::max(1, 16 * M)));
+        HIPS(s, G->plan_size.alloc(sizeof(int) * 2));
+        HIPS(s, G->node_rho.alloc(tsz * d.cap_nodes));
+        HIPS(s, G->node_jx.alloc(tsz * d.cap_nodes));
+        HIPS(s, G->node_jy.alloc(tsz * d.cap_nodes));
+        HIPS(s, G->m_phi.alloc(tsz * 8 * std::max(1, M)));
+        HIPS(s, G->m_tot.alloc(tsz * 5 * std::max(1, M)));
+        HIPS(s, G->m_acc.alloc(sizeof(double) * 5 * std::max(1, M)));
+        HIPS(s, G->m_red.alloc(sizeof(double) * 4 * std::max(1, M)));
+        d.node_cell = (int*)G->node_cell.p;
+        d.node_run = (int*)G->node_run.p;
+        d.ent = (int*)G->ent.p;
+        d.mnode = (int*)G->mnode.p;
+        d.plan_size = (int*)G->plan_size.p;
+        d.node_rho = G->node_rho.p;
+        d.node_jx = G->node_jx.p;
+        d.node_jy = G->node_jy.p;
+        d.m_phi = G->m_phi.p;
+        d.m_tot = G->m_tot.p;
+        d.m_acc = (double*)G->m_acc.p;
+        d.m_red = (double*)G->m_red.p;
+        if (!d.dynamic) {
+            HIPS(s, hipMemcpyAsync(d.node_cell, node_cell.data(), sizeof(int) * node_cell.size(), hipMemcpyHostToDevice, st));
+            HIPS(s, hipMemcpyAsync(d.node_run, node_run.data(), sizeof(int) * node_run.size(), hipMemcpyHostToDevice, st));
+            if (!ent.empty())
+                HIPS(s, hipMemcpyAsync(d.ent, ent.data(), sizeof(int) * ent.size(), hipMemcpyHostToDevice, st));
+            if (M) HIPS(s, hipMemcpyAsync(d.mnode, mnode.data(), sizeof(int) * mnode.size(), hipMemcpyHostToDevice, st));
+        }
+    }
+    std::vector<GroupDev> gd;
+    for (Group* g : s->grp) gd.push_back(g->d);
+    HIPS(s, upload(s->groups, gd, st));
+    HIPS(s, hipMemcpyAsync(s->desc.p, &s->h, sizeof(SimDev), hipMemcpyHostToDevice, st));
+    HIPS(s, hipStreamSynchronize(st));
+    return LBM_OK;
+}
+
+lbm_status sync_back(lbm_batch* b);
+
+// A simulation inside a batch has its step state in the batch's device table.
+lbm_status refresh(lbm_sim* s) {
+    if (!s->batch) return LBM_OK;
+    lbm_status rc = sync_back(s->batch);
+    if (rc != LBM_OK) return fail(s, rc, "could not read the batch state");
+    return LBM_OK;
+}
+
+lbm_status check_status(lbm_sim* s) {
+    uint32_t st = 0;
+    HIPS(s, hipMemcpyAsync(&st, s->status.p, sizeof st, hipMemcpyDeviceToHost, s->stream));
+    HIPS(s, hipStreamSynchronize(s->stream));
+    if (st & ST_UNSTABLE) return fail(s, LBM_ERR_UNSTABLE, "a density went non-positive or non-finite");
+    return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* lbm_version(void) { return "lbmib-gfx950 0.1"; }
+
+lbm_status lbm_create(const lbm_params* p, void* hip_stream, lbm_sim** out) {
+    if (!out) return LBM_ERR_INVALID;
+    *out = nullptr;
+    if (!p || p->nx < 4 || p->ny < 4 || !(p->tau > 0.5) || p->ib_iters < 0 || p->ib_iters > 1000 ||
+        !(p->rho0 > 0) || (p->precision != LBM_F64 && p->precision != LBM_F32_SHIFTED) || !bc_valid(p) ||
+        (int64_t)p->nx * p->ny > (int64_t)1 << 30)
+        return LBM_ERR_INVALID;
+    lbm_sim* s = new (std::nothrow) lbm_sim();
+    if (!s) return LBM_ERR_NOMEM;
+    s->p = *p;
+    s->f64 = p->precision == LBM_F64;
+    if (hipGetDevice(&s->device) != hipSuccess) {
+        delete s;
+        return LBM_ERR_DEVICE;
+    }
+    if (hip_stream) {
+        s->stream = (hipStream_t)hip_stream;
+    } else {
+        if (hipStreamCreate(&s->stream) != hipSuccess) {
+            delete s;
+            return LBM_ERR_DEVICE;
+        }
+        s->own_stream = true;
+    }
+    const int esz = s->f64 ? 8 : 4;
+    const int xoff = 128 / esz;
+    int pitch = xoff + p->nx + 1;
+    pitch = (pitch + xoff - 1) / xoff * xoff;
+    SimDev& h = s->h;
+    memset(&h, 0, sizeof h);
+    h.plane = (int64_t)pitch * (p->ny + 2);
+    h.pitch = pitch;
+    h.xoff = xoff;
+    h.nx = p->nx;
+    h.ny = p->ny;
+    h.bc[0] = p->bc_west;
+    h.bc[1] = p->bc_east;
+    h.bc[2] = p->bc_south;
+    h.bc[3] = p->bc_north;
+    h.px = p->bc_west == LBM_BC_PERIODIC;
+    h.py = p->bc_south == LBM_BC_PERIODIC;
+    h.omega = 1.0 / p->tau;
+    h.rho0 = p->rho0;
+    h.rho_base = s->f64 ? 0.0 : p->rho0;
+    h.u_in[0] = p->u_in[0];
+    h.u_in[1] = p->u_in[1];
+    h.gravity[0] = p->gravity[0];
+    h.gravity[1] = p->gravity[1];
+    h.swapped = 0;
+    h.active = 1;
+    h.steps_left = -1;
+    h.ib_iters = p->ib_iters;
+    h.nperim = perimeter_count(h);
+    lbm_status rc = LBM_OK;
+    auto bail = [&](lbm_status e) {
+        lbm_destroy(s);
+        return e;
+    };
+    if (s->pop.alloc((size_t)h.plane * 9 * esz) != hipSuccess) return bail(LBM_ERR_NOMEM);
+    if (s->desc.alloc(sizeof(SimDev)) != hipSuccess || s->status.alloc(sizeof(uint32_t)) != hipSuccess)
+        return bail(LBM_ERR_NOMEM);
+    if (hipMemsetAsync(s->pop.p, 0, s->pop.bytes, s->stream) != hipSuccess ||
+        hipMemsetAsync(s->status.p, 0, sizeof(uint32_t), s->stream) != hipSuccess)
+        return bail(LBM_ERR_DEVICE);
+    h.pop = s->pop.p;
+    h.status = (uint32_t*)s->status.p;
+    rc = rebuild_ib(s);
+    if (rc != LBM_OK) return bail(rc);
+    build_tiles(s, 0, s->tiling, s->h_tiles);
+    build_bc(s, 0, s->h_bc);
+    if (upload(s->tiles, s->h_tiles, s->stream) != hipSuccess || upload(s->bcitems, s->h_bc, s->stream) != hipSuccess)
+        return bail(LBM_ERR_NOMEM);
+    if (launch_set_eq(s->f64, (const SimDev*)s->desc.p, p->nx, p->ny, 0, nullptr, nullptr, nullptr, p->rho0,
+                      p->u_init[0], p->u_init[1], s->stream) != hipSuccess ||
+        hipStreamSynchronize(s->stream) != hipSuccess)
+        return bail(LBM_ERR_DEVICE);
+    *out = s;
+    return LBM_OK;
+}
+
+void lbm_destroy(lbm_sim* s) {
+    if (!s) return;
+    if (s->batch) lbm_batch_retire(s->batch, s);
+    if (s->stream) (void)hipStreamSynchronize(s->stream);
+    bool own = s->own_stream;
+    hipStream_t st = s->stream;
+    delete s;
+    if (own && st) (void)hipStreamDestroy(st);
+}
+
+const char* lbm_last_error(const lbm_sim* s) { return s ? s->err.c_str() : "null handle"; }
+
+lbm_status ib_set_markers(lbm_sim* s, int32_t id, int32_t n, const double* xy, const double* uv,
+                          const double* ds, const ib_body* body) {
+    if (!s) return LBM_ERR_INVALID;
+    if (s->batch) return fail(s, LBM_ERR_STATE, "markers cannot change while the simulation is in a batch");
+    if (id < 0 || id >= LBM_MAX_BODIES || n < 0) return fail(s, LBM_ERR_INVALID, "bad body id or count");
+    HostBody old = s->body[id];
+    HostBody& B = s->body[id];
+    if (n == 0) {
+        B = HostBody();
+    } else {
+        if (!body) return fail(s, LBM_ERR_INVALID, "body descriptor required");
+        HostBody nb;
+        nb.used = true;
+        nb.kind = body->kind;
+        nb.n = n;
+        nb.b = *body;
+        nb.X.resize(n);
+        nb.Y.resize(n);
+        nb.U.resize(n);
+        nb.V.resize(n);
+        nb.ds.resize(n);
+        if (body->kind == IB_FREE) {
+            if (xy || uv || ds || !(body->radius > 0) || !(body->rho_s > 0))
+                return fail(s, LBM_ERR_INVALID, "free bodies take radius and density, not marker arrays");
+            for (int l = 0; l < n; ++l) {
+                const double a = 2.0 * M_PI * l / n + body->theta;
+                nb.X[l] = body->xc[0] + body->radius * std::cos(a);
+                nb.Y[l] = body->xc[1] + body->radius * std::sin(a);
+                nb.U[l] = body->U[0] - body->omega * (nb.Y[l] - body->xc[1]);
+                nb.V[l] = body->U[1] + body->omega * (nb.X[l] - body->xc[0]);
+                nb.ds[l] = 2.0 * M_PI * body->radius / n;
+            }
+        } else if (body->kind == IB_FIXED) {
+            if (!xy) return fail(s, LBM_ERR_INVALID, "fixed bodies need marker positions");
+            for (int l = 0; l < n; ++l) {
+                nb.X[l] = xy[2 * l];
+                nb.Y[l] = xy[2 * l + 1];
+                if (!std::isfinite(nb.X[l]) || !std::isfinite(nb.Y[l]))
+                    return fail(s, LBM_ERR_INVALID, "non-finite marker position");
+            }
+            for (int l = 0; l < n; ++l) {
+                if (uv) {
+                    nb.U[l] = uv[2 * l];
+                    nb.V[l] = uv[2 * l + 1];
+                } else {
+                    nb.U[l] = body->U[0] - body->omega * (nb.Y[l] - body->xc[1]);
+                    nb.V[l] = body->U[1] + body->omega * (nb.X[l] - body->xc[0]);
+                }
+                if (ds) {
+                    nb.ds[l] = ds[l];
+                } else {
+                    const int a = (l + n - 1) % n, c = (l + 1) % n;
+                    nb.ds[l] = 0.5 * (std::hypot(nb.X[l] - nb.X[a], nb.Y[l] - nb.Y[a]) +
+                                      std::hypot(nb.X[c] - nb.X[l], nb.Y[c] - nb.Y[l]));
+                }
+            }
+        } else {
+            return fail(s, LBM_ERR_INVALID, "unknown body kind");
+        }
+        B = nb;
+    }
+    lbm_status rc = rebuild_ib(s);
+    if (rc != LBM_OK) {
+        s->body[id] = old;
+        std::string msg = s->err;
+        (void)rebuild_ib(s);
+        s->err = msg;
+    }
+    return rc;
+}
+
+lbm_status lbm_step(lbm_sim* s, int32_t nsteps) {
+    if (!s || nsteps < 0) return LBM_ERR_INVALID;
+    if (s->batch) return fail(s, LBM_ERR_STATE, "simulation is stepped by its batch");
+    const SimDev* d = (const SimDev*)s->desc.p;
+    const int ntiles = (int)s->h_tiles.size(), nbc = (int)s->h_bc.size(), ng = (int)s->grp.size();
+    for (int t = 0; t < nsteps; ++t) {
+        const int parity = s->h.swapped;
+        HIPS(s, launch_sweep(s->f64, s->tiling, d, (const int4*)s->tiles.p, nullptr, ntiles, ntiles, parity, s->stream));
+        if (nbc) HIPS(s, launch_boundary(s->f64, d, (const int2*)s->bcitems.p, nullptr, nbc, nbc, parity, s->stream));
+        if (ng) HIPS(s, launch_ib(s->f64, d, (GroupDev*)s->groups.p, nullptr, ng, ng, parity, s->stream));
+        s->h.swapped ^= 1;
+        s->h.steps_done += 1;
+        ++s->steps;
+    }
+    return LBM_OK;
+}
+
+lbm_status lbm_sync(lbm_sim* s) {
+    if (!s) return LBM_ERR_INVALID;
+    HIPS(s, hipStreamSynchronize(s->stream));
+    return check_status(s);
+}
+
+int64_t lbm_step_count(lbm_sim* s) {
+    if (!s) return -1;
+    if (refresh(s) != LBM_OK) return -1;
+    return s->steps;
+}
+
+lbm_status ib_forces(lbm_sim* s, int32_t id, double F[2], double* T, double diag[2], ib_body* state_out) {
+    if (!s || id < 0 || id >= LBM_MAX_BODIES) return LBM_ERR_INVALID;
+    {
+        lbm_status rc_ = refresh(s);
+        if (rc_ != LBM_OK) return rc_;
+    }
+    if (!s->body[id].used) return fail(s, LBM_ERR_INVALID, "no such body");
+    BodyDev b;
+    HIPS(s, hipMemcpyAsync(&b, (BodyDev*)s->bodies.p + id, sizeof b, hipMemcpyDeviceToHost, s->stream));
+    HIPS(s, hipStreamSynchronize(s->stream));
+    if (F) {
+        F[0] = b.F[0];
+        F[1] = b.F[1];
+    }
+    if (T) *T = b.T;
+    if (diag) {
+        diag[0] = b.resid;
+        diag[1] = b.maxslip;
+    }
+    if (state_out) {
+        *state_out = s->body[id].b;
+        state_out->xc[0] = b.xc[0];
+        state_out->xc[1] = b.xc[1];
+        state_out->U[0] = b.U[0];
+        state_out->U[1] = b.U[1];
+        state_out->omega = b.omega;
+        state_out->theta = b.theta;
+    }
+    return check_status(s);
+}
+
+lbm_status lbm_fields_device(lbm_sim* s, void* rho, void* ux, void* uy) {
+    if (!s) return LBM_ERR_INVALID;
+    {
+        lbm_status rc_ = refresh(s);
+        if (rc_ != LBM_OK) return rc_;
+    }
+    HIPS(s, launch_fields(s->f64, (const SimDev*)s->desc.p, s->p.nx, s->p.ny, s->h.swapped, (double*)rho,
+                          (double*)ux, (double*)uy, s->stream));
+    return LBM_OK;
+}
+
+lbm_status lbm_fields(lbm_sim* s, double* rho, double* ux, double* uy) {
+    if (!s) return LBM_ERR_INVALID;
+    {
+        lbm_status rc_ = refresh(s);
+        if (rc_ != LBM_OK) return rc_;
+    }
+    const size_t n = (size_t)s->p.nx * s->p.ny;
+    DevBuf tmp;
+    HIPS(s, tmp.alloc(3 * n * sizeof(double)));
+    double* d = (double*)tmp.p;
+    HIPS(s, launch_fields(s->f64, (const SimDev*)s->desc.p, s->p.nx, s->p.ny, s->h.swapped, d, d + n, d + 2 * n,
+                          s->stream));
+    if (rho) HIPS(s, hipMemcpyAsync(rho, d, n * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+    if (ux) HIPS(s, hipMemcpyAsync(ux, d + n, n * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+    if (uy) HIPS(s, hipMemcpyAsync(uy, d + 2 * n, n * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+    HIPS(s, hipStreamSynchronize(s->stream));
+    return check_status(s);
+}
+
+lbm_status lbm_get_populations(lbm_sim* s, double* f) {
+    if (!s || !f) return LBM_ERR_INVALID;
+    {
+        lbm_status rc_ = refresh(s);
+        if (rc_ != LBM_OK) return rc_;
+    }
+    const size_t n = (size_t)s->p.nx * s->p.ny * 9;
+    DevBuf tmp;
+    HIPS(s, tmp.alloc(n * sizeof(double)));
+    HIPS(s, launch_get_pop(s->f64, (const SimDev*)s->desc.p, s->p.nx, s->p.ny, s->h.swapped, (double*)tmp.p,
+                           s->stream));
+    HIPS(s, hipMemcpyAsync(f, tmp.p, n * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+    HIPS(s, hipStreamSynchronize(s->stream));
+    return LBM_OK;
+}
+
+lbm_status lbm_set_populations(lbm_sim* s, const double* f) {
+    if (!s || !f) return LBM_ERR_INVALID;
+    if (s->batch) return fail(s, LBM_ERR_STATE, "simulation is in a batch");
+    const size_t n = (size_t)s->p.nx * s->p.ny * 9;
+    DevBuf tmp;
+    HIPS(s, tmp.alloc(n * sizeof(double)));
+    HIPS(s, hipMemcpyAsync(tmp.p, f, n * sizeof(double), hipMemcpyHostToDevice, s->stream));
+    HIPS(s, launch_set_pop(s->f64, (const SimDev*)s->desc.p, s->p.nx, s->p.ny, s->h.swapped, (const double*)tmp.p,
+                           s->stream));
+    HIPS(s, hipStreamSynchronize(s->stream));
+    return LBM_OK;
+}
+
+lbm_status lbm_set_fields(lbm_sim* s, const double* rho, const double* ux, const double* uy) {
+    if (!s || !rho || !ux || !uy) return LBM_ERR_INVALID;
+    if (s->batch) return fail(s, LBM_ERR_STATE, "simulation is in a batch");
+    const size_t n = (size_t)s->p.nx * s->p.ny;
+    DevBuf tmp;
+    HIPS(s, tmp.alloc(3 * n * sizeof(double)));
+    double* d = (double*)tmp.p;
+    HIPS(s, hipMemcpyAsync(d, rho, n * sizeof(double), hipMemcpyHostToDevice, s->stream));
+    HIPS(s, hipMemcpyAsync(d + n, ux, n * sizeof(double), hipMemcpyHostToDevice, s->stream));
+    HIPS(s, hipMemcpyAsync(d + 2 * n, uy, n * sizeof(double), hipMemcpyHostToDevice, s->stream));
+    HIPS(s, launch_set_eq(s->f64, (const SimDev*)s->desc.p, s->p.nx, s->p.ny, s->h.swapped, d, d + n, d + 2 * n, 0,
+                          0, 0, s->stream));
+    HIPS(s, hipStreamSynchronize(s->stream));
+    return LBM_OK;
+}
+
+size_t lbm_device_bytes(const lbm_sim* s) {
+    if (!s) return 0;
+    size_t b = s->pop.bytes + s->desc.bytes + s->status.bytes + s->bodies.bytes + s->markers.bytes + s->tiles.bytes +
+               s->bcitems.bytes + s->groups.bytes;
+    for (const Group* g : s->grp)
+        b += g->node_cell.bytes + g->node_run.bytes + g->ent.bytes + g->mnode.bytes + g->plan_size.bytes +
+             g->node_rho.bytes + g->node_jx.bytes + g->node_jy.bytes + g->m_phi.bytes + g->m_tot.bytes +
+             g->m_acc.bytes + g->m_red.bytes;
+    return b;
+}
+
+int32_t lbm_tiling_count(void) { return kNumTilings; }
+
+lbm_status lbm_tiling_info(int32_t k, int32_t* tx, int32_t* ty, int32_t* rpt) {
+    if (k < 0 || k >= kNumTilings) return LBM_ERR_INVALID;
+    if (tx) *tx = kTilings[k].tx;
+    if (ty) *ty = kTilings[k].ty;
+    if (rpt) *rpt = kTilings[k].rpt;
+    return LBM_OK;
+}
+
+}  // extern "C"
+
+// ================================================================ batches
+
+namespace {
+
+lbm_status hipfailb(lbm_batch* b, hipError_t e, const char* where) {
+    return failb(b, e == hipErrorOutOfMemory ? LBM_ERR_NOMEM : LBM_ERR_DEVICE,
+                 fmt("%s: %s", where, hipGetErrorString(e)));
+}
+
+#define HIPB(b, call)                                       \
+    do {                                                    \
+        hipError_t e_ = (call);                             \
+        if (e_ != hipSuccess) return hipfailb(b, e_, #call); \
+    } while (0)
+
+void drop_graphs(lbm_batch* b) {
+    if (b->graph1) (void)hipGraphExecDestroy(b->graph1);
+    if (b->graphK) (void)hipGraphExecDestroy(b->graphK);
+    b->graph1 = b->graphK = nullptr;
+}
+
+// Copy the per-simulation step state (AA state, counters) of the device table
+// back into the simulations' host descriptors.
+lbm_status sync_back(lbm_batch* b) {
+    HIPB(b, hipStreamSynchronize(b->stream));
+    if (b->sims.empty()) return LBM_OK;
+    std::vector<SimDev> h(b->sims.size());
+    HIPB(b, hipMemcpy(h.data(), b->d_sims.p, sizeof(SimDev) * h.size(), hipMemcpyDeviceToHost));
+    for (size_t k = 0; k < h.size(); ++k) {
+        lbm_sim* s = b->sims[k];
+        s->h.swapped = h[k].swapped;
+        s->h.steps_done = h[k].steps_done;
+        s->h.steps_left = h[k].steps_left;
+        s->h.active = h[k].active;
+        s->steps = h[k].steps_done;
+    }
+    return LBM_OK;
+}
+
+template <typename V>
+hipError_t ensure_cap(DevBuf& buf, size_t& cap, size_t need, bool& grew) {
+    if (need <= cap && buf.p) return hipSuccess;
+    size_t c = std::max<size_t>(need + need / 2, 16);
+    hipError_t e = buf.alloc(c * sizeof(V));
+    if (e != hipSuccess) return e;
+    cap = c;
+    grew = true;
+    return hipSuccess;
+}
+
+// Rebuild and upload the batch's work tables from the admitted simulations'
+// host descriptors (call sync_back first when simulations are in flight).
+lbm_status upload_tables(lbm_batch* b) {
+    std::vector<SimDev> sims;
+    std::vector<int4> tiles;
+    std::vector<int2> bc;
+    std::vector<GroupDev> groups;
+    for (size_t k = 0; k < b->sims.size(); ++k) {
+        lbm_sim* s = b->sims[k];
+        sims.push_back(s->h);
+        build_tiles(s, (int)k, b->tiling, tiles);
+        build_bc(s, (int)k, bc);
+        for (Group* g : s->grp) {
+            GroupDev d = g->d;
+            d.sim = (int)k;
+            groups.push_back(d);
+        }
+    }
+    bool grew = false;
+    HIPB(b, ensure_cap<SimDev>(b->d_sims, b->cap_sims, sims.size(), grew));
+    HIPB(b, ensure_cap<int4>(b->d_tiles, b->cap_tiles, tiles.size(), grew));
+    HIPB(b, ensure_cap<int2>(b->d_bc, b->cap_bc, bc.size(), grew));
+    HIPB(b, ensure_cap<GroupDev>(b->d_groups, b->cap_groups, groups.size(), grew));
+    if (!b->d_hdr.p) {
+        HIPB(b, b->d_hdr.alloc(sizeof(BatchHeader)));
+        grew = true;
+    }
+    if (grew) drop_graphs(b);
+    if (!sims.empty()) HIPB(b, hipMemcpyAsync(b->d_sims.p, sims.data(), sizeof(SimDev) * sims.size(), hipMemcpyHostToDevice, b->stream));
+    if (!tiles.empty()) HIPB(b, hipMemcpyAsync(b->d_tiles.p, tiles.data(), sizeof(int4) * tiles.size(), hipMemcpyHostToDevice, b->stream));
+    if (!bc.empty()) HIPB(b, hipMemcpyAsync(b->d_bc.p, bc.data(), sizeof(int2) * bc.size(), hipMemcpyHostToDevice, b->stream));
+    if (!groups.empty()) HIPB(b, hipMemcpyAsync(b->d_groups.p, groups.data(), sizeof(GroupDev) * groups.size(), hipMemcpyHostToDevice, b->stream));
+    BatchHeader h{(int)sims.size(), (int)tiles.size(), (int)bc.size(), (int)groups.size()};
+    HIPB(b, hipMemcpyAsync(b->d_hdr.p, &h, sizeof h, hipMemcpyHostToDevice, b->stream));
+    HIPB(b, hipStreamSynchronize(b->stream));
+    b->ntiles = h.ntiles;
+    b->nbc = h.nbc;
+    b->ngroups = h.ngroups;
+    return LBM_OK;
+}
+
+hipError_t enqueue_steps(lbm_batch* b, int n) {
+    const SimDev* sims = (const SimDev*)b->d_sims.p;
+    const BatchHeader* hdr = (const BatchHeader*)b->d_hdr.p;
+    for (int t = 0; t < n; ++t) {
+        hipError_t e = launch_sweep(b->f64, b->tiling, sims, (const int4*)b->d_tiles.p, hdr, 0, b->grid_sweep, -1, b->stream);
+        if (e == hipSuccess) e = launch_boundary(b->f64, sims, (const int2*)b->d_bc.p, hdr, 0, b->grid_bc, -1, b->stream);
+        if (e == hipSuccess) e = launch_ib(b->f64, sims, (GroupDev*)b->d_groups.p, hdr, 0, b->grid_ib, -1, b->stream);
+        if (e == hipSuccess) e = launch_advance((SimDev*)b->d_sims.p, hdr, 0, b->stream);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t capture(lbm_batch* b, int n, hipGraphExec_t* out) {
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return e;
+    hipError_t e2 = enqueue_steps(b, n);
+    e = hipStreamEndCapture(b->stream, &g);
+    if (e2 != hipSuccess) e = e2;
+    if (e == hipSuccess) e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+    if (g) (void)hipGraphDestroy(g);
+    return e;
+}
+
+}  // namespace
+
+extern "C" {
+
+lbm_status lbm_batch_create(int32_t precision, size_t budget, void* hip_stream, lbm_batch** out) {
+    if (!out || (precision != LBM_F64 && precision != LBM_F32_SHIFTED)) return LBM_ERR_INVALID;
+    *out = nullptr;
+    lbm_batch* b = new (std::nothrow) lbm_batch();
+    if (!b) return LBM_ERR_NOMEM;
+    b->f64 = precision == LBM_F64;
+    b->budget = budget;
+    if (hipGetDevice(&b->device) != hipSuccess) {
+        delete b;
+        return LBM_ERR_DEVICE;
+    }
+    if (hip_stream) {
+        b->stream = (hipStream_t)hip_stream;
+    } else {
+        if (hipStreamCreate(&b->stream) != hipSuccess) {
+            delete b;
+            return LBM_ERR_DEVICE;
+        }
+        b->own_stream = true;
+    }
+    const int ncu = num_cus(b->device);
+    b->grid_sweep = ncu * 8;
+    b->grid_bc = ncu;
+    b->grid_ib = ncu * 2;
+    if (upload_tables(b) != LBM_OK) {
+        lbm_batch_destroy(b);
+        return LBM_ERR_NOMEM;
+    }
+    *out = b;
+    return LBM_OK;
+}
+
+void lbm_batch_destroy(lbm_batch* b) {
+    if (!b) return;
+    (void)sync_back(b);
+    for (lbm_sim* s : b->sims) {
+        s->batch = nullptr;
+        s->h.active = 1;
+        s->h.steps_left = -1;
+        (void)hipMemcpy(s->desc.p, &s->h, sizeof(SimDev), hipMemcpyHostToDevice);
+    }
+    b->sims.clear();
+    drop_graphs(b);
+    bool own = b->own_stream;
+    hipStream_t st = b->stream;
+    delete b;
+    if (own && st) (void)hipStreamDestroy(st);
+}
+
+lbm_status lbm_batch_admit(lbm_batch* b, lbm_sim* s, int64_t steps) {
+    if (!b || !s) return LBM_ERR_INVALID;
+    if (s->batch) return failb(b, LBM_ERR_INVALID, "simulation already in a batch");
+    if (s->f64 != b->f64) return failb(b, LBM_ERR_INVALID, "precision differs from the batch");
+    const size_t need = lbm_device_bytes(s);
+    if (b->budget && b->bytes + need > b->budget) return failb(b, LBM_ERR_NOMEM, "HBM budget exhausted");
+    lbm_status rc = sync_back(b);
+    if (rc != LBM_OK) return rc;
+    HIPB(b, hipStreamSynchronize(s->stream));
+    s->h.active = steps == 0 ? 0 : 1;
+    s->h.steps_left = steps > 0 ? steps : -1;
+    b->sims.push_back(s);
+    s->batch = b;
+    b->bytes += need;
+    rc = upload_tables(b);
+    if (rc != LBM_OK) {
+        b->sims.pop_back();
+        s->batch = nullptr;
+        b->bytes -= need;
+        s->h.active = 1;
+        s->h.steps_left = -1;
+    }
+    return rc;
+}
+
+lbm_status lbm_batch_retire(lbm_batch* b, lbm_sim* s) {
+    if (!b || !s || s->batch != b) return LBM_ERR_INVALID;
+    lbm_status rc = sync_back(b);
+    if (rc != LBM_OK) return rc;
+    auto it = std::find(b->sims.begin(), b->sims.end(), s);
+    b->sims.erase(it);
+    b->bytes -= std::min(b->bytes, lbm_device_bytes(s));
+    s->batch = nullptr;
+    s->h.active = 1;
+    s->h.steps_left = -1;
+    HIPB(b, hipMemcpy(s->desc.p, &s->h, sizeof(SimDev), hipMemcpyHostToDevice));
+    return upload_tables(b);
+}
+
+lbm_status lbm_batch_step(lbm_batch* b, int32_t nsteps) {
+    if (!b || nsteps < 0) return LBM_ERR_INVALID;
+    if (!b->graph1) HIPB(b, capture(b, 1, &b->graph1));
+    if (!b->graphK) HIPB(b, capture(b, b->graphK_steps, &b->graphK));
+    int left = nsteps;
+    while (left >= b->graphK_steps) {
+        HIPB(b, hipGraphLaunch(b->graphK, b->stream));
+        left -= b->graphK_steps;
+    }
+    while (left-- > 0) HIPB(b, hipGraphLaunch(b->graph1, b->stream));
+    return LBM_OK;
+}
+
+lbm_status lbm_batch_sync(lbm_batch* b) {
+    if (!b) return LBM_ERR_INVALID;
+    lbm_status rc = sync_back(b);
+    if (rc != LBM_OK) return rc;
+    for (lbm_sim* s : b->sims) {
+        uint32_t st = 0;
+        HIPB(b, hipMemcpy(&st, s->status.p, sizeof st, hipMemcpyDeviceToHost));
+        if (st & ST_UNSTABLE) return failb(b, LBM_ERR_UNSTABLE, "a simulation in the batch went unstable");
+    }
+    return LBM_OK;
+}
+
+lbm_status lbm_batch_remaining(lbm_batch* b, lbm_sim* s, int64_t* remaining) {
+    if (!b || !s || s->batch != b || !remaining) return LBM_ERR_INVALID;
+    lbm_status rc = sync_back(b);
+    if (rc != LBM_OK) return rc;
+    *remaining = s->h.active ? (s->h.steps_left < 0 ? -1 : s->h.steps_left) : 0;
+    return LBM_OK;
+}
+
+size_t lbm_batch_bytes(const lbm_batch* b) { return b ? b->bytes : 0; }
+
+lbm_status lbm_batch_set_tiling(lbm_batch* b, int32_t tiling) {
+    if (!b || tiling < 0 || tiling >= kNumTilings) return LBM_ERR_INVALID;
+    lbm_status rc = sync_back(b);
+    if (rc != LBM_OK) return rc;
+    b->tiling = tiling;
+    drop_graphs(b);
+    return upload_tables(b);
+}
+
+lbm_status lbm_batch_autotune(lbm_batch* b, int32_t trials, int32_t* chosen) {
+    if (!b || trials <= 0) return LBM_ERR_INVALID;
+    lbm_status rc = sync_back(b);
+    if (rc != LBM_OK) return rc;
+    if (b->sims.empty()) {
+        if (chosen) *chosen = b->tiling;
+        return LBM_OK;
+    }
+    // save the state every candidate will advance
+    struct Saved {
+        DevBuf pop, bodies, markers;
+        SimDev h;
+    };
+    std::vector<Saved> saved(b->sims.size());
+    for (size_t k = 0; k < b->sims.size(); ++k) {
+        lbm_sim* s = b->sims[k];
+        saved[k].h = s->h;
+        HIPB(b, saved[k].pop.alloc(s->pop.bytes));
+        HIPB(b, saved[k].bodies.alloc(s->bodies.bytes));
+        HIPB(b, saved[k].markers.alloc(s->markers.bytes));
+        HIPB(b, hipMemcpyAsync(saved[k].pop.p, s->pop.p, s->pop.bytes, hipMemcpyDeviceToDevice, b->stream));
+        HIPB(b, hipMemcpyAsync(saved[k].bodies.p, s->bodies.p, s->bodies.bytes, hipMemcpyDeviceToDevice, b->stream));
+        HIPB(b, hipMemcpyAsync(saved[k].markers.p, s->markers.p, s->markers.bytes, hipMemcpyDeviceToDevice, b->stream));
+    }
+    HIPB(b, hipStreamSynchronize(b->stream));
+    const int old = b->tiling;
+    int best = old;
+    float best_ms = 1e30f;
+    hipEvent_t e0, e1;
+    HIPB(b, hipEventCreate(&e0));
+    HIPB(b, hipEventCreate(&e1));
+    for (int k = 0; k < kNumTilings; ++k) {
+        b->tiling = k;
+        rc = upload_tables(b);
+        if (rc != LBM_OK) break;
+        HIPB(b, enqueue_steps(b, 1));  // warm-up
+        HIPB(b, hipEventRecord(e0, b->stream));
+        HIPB(b, enqueue_steps(b, trials));
+        HIPB(b, hipEventRecord(e1, b->stream));
+        HIPB(b, hipEventSynchronize(e1));
+        float ms = 0;
+        HIPB(b, hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = k;
+        }
+        // restore
+        for (size_t q = 0; q < b->sims.size(); ++q) {
+            lbm_sim* s = b->sims[q];
+            s->h = saved[q].h;
+            HIPB(b, hipMemcpyAsync(s->pop.p, saved[q].pop.p, s->pop.bytes, hipMemcpyDeviceToDevice, b->stream));
+            HIPB(b, hipMemcpyAsync(s->bodies.p, saved[q].bodies.p, s->bodies.bytes, hipMemcpyDeviceToDevice, b->stream));
+            HIPB(b, hipMemcpyAsync(s->markers.p, saved[q].markers.p, s->markers.bytes, hipMemcpyDeviceToDevice, b->stream));
+            HIPB(b, hipMemsetAsync(s->status.p, 0, sizeof(uint32_t), b->stream));
+        }
+        HIPB(b, hipStreamSynchronize(b->stream));
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    b->tiling = best;
+    drop_graphs(b);
+    lbm_status rc2 = upload_tables(b);
+    if (rc == LBM_OK) rc = rc2;
+    if (chosen) *chosen = best;
+    return rc;
+}
+
+lbm_status lbm_batch_profile(lbm_batch* b, int32_t nsteps, double ms[4], int64_t* cells) {
+    if (!b || nsteps < 0 || !ms) return LBM_ERR_INVALID;
+    lbm_status rc = sync_back(b);
+    if (rc != LBM_OK) return rc;
+    int64_t c = 0;
+    for (lbm_sim* s : b->sims)
+        if (s->h.active) c += (int64_t)s->p.nx * s->p.ny;
+    if (cells) *cells = c;
+    for (int k = 0; k < 4; ++k) ms[k] = 0.0;
+    hipEvent_t ev[5];
+    for (int k = 0; k < 5; ++k) HIPB(b, hipEventCreate(&ev[k]));
+    const SimDev* sims = (const SimDev*)b->d_sims.p;
+    const BatchHeader* hdr = (const BatchHeader*)b->d_hdr.p;
+    for (int t = 0; t < nsteps; ++t) {
+        HIPB(b, hipEventRecord(ev[0], b->stream));
+        HIPB(b, launch_sweep(b->f64, b->tiling, sims, (const int4*)b->d_tiles.p, hdr, 0, b->grid_sweep, -1, b->stream));
+        HIPB(b, hipEventRecord(ev[1], b->stream));
+        HIPB(b, launch_boundary(b->f64, sims, (const int2*)b->d_bc.p, hdr, 0, b->grid_bc, -1, b->stream));
+        HIPB(b, hipEventRecord(ev[2], b->stream));
+        HIPB(b, launch_ib(b->f64, sims, (GroupDev*)b->d_groups.p, hdr, 0, b->grid_ib, -1, b->stream));
+        HIPB(b, hipEventRecord(ev[3], b->stream));
+        HIPB(b, launch_advance((SimDev*)b->d_sims.p, hdr, 0, b->stream));
+        HIPB(b, hipEventRecord(ev[4], b->stream));
+        HIPB(b, hipEventSynchronize(ev[4]));
+        for (int k = 0; k < 4; ++k) {
+            float m = 0.f;
+            HIPB(b, hipEventElapsedTime(&m, ev[k], ev[k + 1]));
+            ms[k] += m;
+        }
+    }
+    for (int k = 0; k < 5; ++k) (void)hipEventDestroy(ev[k]);
+    return LBM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,135 @@
+"""Batched stepping: a simulation gives the same bits alone and inside a batch,
+with any sweep tiling, with step budgets, and across admission/retirement."""
+import sys
+
+import numpy as np
+import pytest
+
+from gpu_helpers import gpu_from_case
+from paper_1803_09380_amd import lbmib
+from paper_1803_09380_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _cases():
+    return [
+        wl.couette(48, precision=wl.F32),
+        wl.cylinder(nx=120, ny=60, D=12.0, centre=(30.0, 30.0), U=0.05, Re=30.0),
+        wl.settling(nx=40, ny=90, D=10.0, density_ratio=1.4, two=True, lower=(20.0, 40.0), u_ref=0.05),
+        wl.couette(70, precision=wl.F32),
+    ]
+
+
+def _state(sim, nb):
+    return sim.populations(), [sim.forces(k) for k in range(nb)]
+
+
+def _same(a, b):
+    pa, fa = a
+    pb, fb = b
+    assert np.array_equal(pa, pb)
+    for x, y in zip(fa, fb):
+        assert np.array_equal(x[0], y[0]) and x[1] == y[1] and np.array_equal(x[3], y[3])
+
+
+@pytest.mark.parametrize("steps", [13, 24])
+def test_batch_equals_alone_bitwise(steps):
+    _say("batch vs alone, %d steps" % steps)
+    cases = _cases()
+    alone = []
+    for c in cases:
+        s = gpu_from_case(c, precision=lbmib.F32_SHIFTED)
+        s.step(steps)
+        alone.append(_state(s, len(c["bodies"])))
+    sims = [gpu_from_case(c, precision=lbmib.F32_SHIFTED) for c in cases]
+    b = lbmib.Batch(lbmib.F32_SHIFTED)
+    for s in sims:
+        assert b.admit(s)
+    b.step(steps)
+    b.sync()
+    for s, c, ref in zip(sims, cases, alone):
+        assert s.step_count == steps
+        _same(_state(s, len(c["bodies"])), ref)
+
+
+def test_batch_every_tiling_same_bits():
+    _say("tilings")
+    cases = _cases()[:3]
+    ref = None
+    for k in range(len(lbmib.tilings())):
+        sims = [gpu_from_case(c, precision=lbmib.F32_SHIFTED) for c in cases]
+        b = lbmib.Batch(lbmib.F32_SHIFTED)
+        for s in sims:
+            b.admit(s)
+        b.set_tiling(k)
+        b.step(9)
+        st = [_state(s, len(c["bodies"])) for s, c in zip(sims, cases)]
+        if ref is None:
+            ref = st
+        else:
+            for x, y in zip(st, ref):
+                _same(x, y)
+        b.close()
+
+
+def test_autotune_keeps_state_and_bits():
+    _say("autotune")
+    cases = _cases()[:3]
+    sims = [gpu_from_case(c, precision=lbmib.F32_SHIFTED) for c in cases]
+    b = lbmib.Batch(lbmib.F32_SHIFTED)
+    for s in sims:
+        b.admit(s)
+    b.step(3)
+    k = b.autotune(trials=2)
+    assert 0 <= k < len(lbmib.tilings())
+    b.step(5)
+    b.sync()
+    for s, c in zip(sims, cases):
+        ref = gpu_from_case(c, precision=lbmib.F32_SHIFTED)
+        ref.step(8)
+        assert s.step_count == 8
+        _same(_state(s, len(c["bodies"])), _state(ref, len(c["bodies"])))
+
+
+def test_step_budget_and_retire():
+    _say("budget + retire")
+    cases = _cases()[:2]
+    sims = [gpu_from_case(c, precision=lbmib.F32_SHIFTED) for c in cases]
+    b = lbmib.Batch(lbmib.F32_SHIFTED)
+    assert b.admit(sims[0], steps=7)
+    assert b.admit(sims[1])
+    b.step(11)
+    assert b.remaining(sims[0]) == 0
+    assert b.remaining(sims[1]) == -1
+    assert sims[0].step_count == 7 and sims[1].step_count == 11
+    b.retire(sims[1])
+    sims[1].step(4)  # continues on its own
+    for s, c, n in ((sims[0], cases[0], 7), (sims[1], cases[1], 15)):
+        ref = gpu_from_case(c, precision=lbmib.F32_SHIFTED)
+        ref.step(n)
+        _same(_state(s, len(c["bodies"])), _state(ref, len(c["bodies"])))
+
+
+def test_hbm_budget_refuses_admission():
+    _say("hbm budget")
+    c = wl.couette(64, precision=wl.F32)
+    a = gpu_from_case(c, precision=lbmib.F32_SHIFTED)
+    b2 = gpu_from_case(c, precision=lbmib.F32_SHIFTED)
+    b = lbmib.Batch(lbmib.F32_SHIFTED, hbm_budget=int(a.device_bytes * 1.5))
+    assert b.admit(a)
+    assert not b.admit(b2)
+    b.retire(a)
+    assert b.admit(b2)
+
+
+def test_precision_mismatch_is_rejected():
+    s = gpu_from_case(wl.couette(32), precision=lbmib.F64)
+    b = lbmib.Batch(lbmib.F32_SHIFTED)
+    with pytest.raises(lbmib.LbmError):
+        b.admit(s)

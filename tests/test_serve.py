@@ -1,0 +1,126 @@
+"""CPU tests of the continuous-batching policy with a mock executor on a
+virtual clock (no GPU): admission by HBM budget in arrival order, overlap of
+requests, completion at the step budget, latency accounting."""
+import numpy as np
+import pytest
+
+from paper_1803_09380_amd import workloads as wl
+from paper_1803_09380_amd.serve import Request, Server
+
+
+class VirtualClock:
+    def __init__(self):
+        self.t = 0.0
+
+    def __call__(self):
+        return self.t
+
+    def sleep(self, dt):
+        self.t += max(dt, 1e-9)
+
+
+class MockExecutor:
+    """Costs one virtual second per 1e8 node updates of the whole batch."""
+
+    def __init__(self, clock, bytes_per_node=36):
+        self.clock = clock
+        self.bpn = bytes_per_node
+        self.live = {}
+        self.trace = []
+
+    def create(self, req):
+        return {"rid": req.rid, "nodes": req.case["nx"] * req.case["ny"], "left": req.steps, "ran": 0}
+
+    def bytes(self, h):
+        return h["nodes"] * self.bpn
+
+    def admit(self, req, h):
+        self.live[req.rid] = h
+        self.trace.append(("admit", req.rid, self.clock()))
+        return True
+
+    def step(self, n):
+        work = 0
+        for h in self.live.values():
+            k = min(n, h["left"])
+            h["left"] -= k
+            h["ran"] += k
+            work += k * h["nodes"]
+        self.clock.t += work / 1e8
+
+    def sync(self):
+        pass
+
+    def finish(self, req):
+        h = self.live.pop(req.rid)
+        self.trace.append(("done", req.rid, self.clock()))
+        return {"steps": h["ran"]}
+
+    def discard(self, h):
+        pass
+
+
+def _reqs(n, rate, steps, nx=100, ny=400, seed=1):
+    rng = np.random.default_rng(seed)
+    t = np.cumsum(rng.exponential(1.0 / rate, size=n))
+    return [Request(rid=k, t_arrive=float(t[k]),
+                    case=wl.settling(nx=nx, ny=ny, D=12.0, density_ratio=1.2, lower=(nx / 2, ny - 50.0)),
+                    steps=steps) for k in range(n)]
+
+
+def test_every_request_runs_exactly_its_budget():
+    clk = VirtualClock()
+    ex = MockExecutor(clk)
+    srv = Server(ex, hbm_budget=0, chunk=37, clock=clk, sleep=clk.sleep)
+    reqs = _reqs(12, rate=50.0, steps=300)
+    done = srv.run(reqs)
+    assert len(done) == 12
+    assert all(r.result["steps"] == 300 for r in done)
+    s = srv.stats.summary()
+    assert s["requests"] == 12 and s["p99_s"] >= s["p50_s"] > 0
+    assert srv.stats.updates == 12 * 300 * 100 * 400
+
+
+def test_budget_limits_concurrency_and_keeps_arrival_order():
+    clk = VirtualClock()
+    ex = MockExecutor(clk)
+    per = 100 * 400 * 36
+    srv = Server(ex, hbm_budget=3 * per, chunk=50, clock=clk, sleep=clk.sleep)
+    reqs = _reqs(10, rate=1000.0, steps=200)  # all arrive almost at once
+    done = srv.run(reqs)
+    assert len(done) == 10
+    assert srv.stats.max_live == 3
+    admits = [rid for kind, rid, _ in ex.trace if kind == "admit"]
+    assert admits == sorted(admits)
+    assert srv.stats.queue_peak >= 5
+
+
+def test_requests_arriving_while_others_run_are_admitted_between_chunks():
+    clk = VirtualClock()
+    ex = MockExecutor(clk)
+    srv = Server(ex, hbm_budget=0, chunk=20, clock=clk, sleep=clk.sleep)
+    r0 = Request(0, 0.0, wl.settling(nx=100, ny=400, D=12.0, lower=(50.0, 350.0)), 400)
+    r1 = Request(1, 0.05, wl.settling(nx=100, ny=400, D=12.0, lower=(50.0, 350.0)), 100)
+    done = srv.run([r0, r1])
+    t = {(k, rid): tt for k, rid, tt in ex.trace}
+    # r1 joined before r0 finished and finished first
+    assert t[("admit", 1)] < t[("done", 0)]
+    assert t[("done", 1)] < t[("done", 0)]
+    assert {r.rid for r in done} == {0, 1}
+
+
+def test_request_larger_than_the_budget_is_refused():
+    clk = VirtualClock()
+    ex = MockExecutor(clk)
+    srv = Server(ex, hbm_budget=1000, chunk=20, clock=clk, sleep=clk.sleep)
+    with pytest.raises(ValueError):
+        srv.run(_reqs(1, rate=10.0, steps=10))
+
+
+def test_idle_server_waits_for_the_next_arrival():
+    clk = VirtualClock()
+    ex = MockExecutor(clk)
+    srv = Server(ex, hbm_budget=0, chunk=50, clock=clk, sleep=clk.sleep)
+    reqs = [Request(0, 5.0, wl.settling(nx=100, ny=400, D=12.0, lower=(50.0, 350.0)), 50)]
+    done = srv.run(reqs)
+    assert done[0].t_admit >= 5.0
