@@ -74,6 +74,49 @@ def run_cpu_baseline(cases, seconds):
                       "FP64, IB sweeps serial, collide/stream OpenMP" % (members, steps_each, used)}
 
 
+def fp64_leg(args, cases, lbmib, wl, torch, np):
+    """Plain FP64 path on the first members (one at a time, direct launches),
+    the batched FP32 path on the same members, and the FP32-vs-FP64 velocity
+    difference on a Couette member."""
+    f64_updates, f64_time = 0, 0.0
+    for c in cases[:args.fp64_sample]:
+        s = lbmib.Sim.from_case(c, precision=lbmib.F64)
+        s.step(2)
+        s.sync()
+        t0 = time.perf_counter()
+        s.step(args.fp64_steps)
+        s.sync()
+        f64_time += time.perf_counter() - t0
+        f64_updates += c["nx"] * c["ny"] * args.fp64_steps
+        s.close()
+    f64_mlups = f64_updates / f64_time / 1e6
+    # batched FP32 on the same sample, for a like-for-like speedup
+    sample = [lbmib.Sim.from_case(c, precision=lbmib.F32_SHIFTED) for c in cases[:args.fp64_sample]]
+    b2 = lbmib.Batch(lbmib.F32_SHIFTED)
+    for s in sample:
+        b2.admit(s)
+    b2.step(4)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b2.step(args.fp64_steps)
+    torch.cuda.synchronize()
+    f32_sample_mlups = f64_updates / (time.perf_counter() - t0) / 1e6
+    b2.close()
+    del sample
+
+    # ---- accuracy of the FP32 path against the FP64 path on one member (Couette 64)
+    ref = wl.couette(64)
+    a = lbmib.Sim.from_case(ref, precision=lbmib.F64)
+    b = lbmib.Sim.from_case(ref, precision=lbmib.F32_SHIFTED)
+    a.step(2000)
+    b.step(2000)
+    _, ua, va = a.fields()
+    _, ub, vb = b.fields()
+    err = float(np.sqrt(np.sum((ua - ub) ** 2 + (va - vb) ** 2) / np.sum(ua ** 2 + va ** 2)))
+
+    return f64_mlups, f32_sample_mlups, err
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -88,6 +131,11 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--autotune", action="store_true")
     ap.add_argument("--tiling", type=int, default=-1)
+    ap.add_argument("--serve-requests", type=int, default=24)
+    ap.add_argument("--serve-steps", type=int, default=2000)
+    ap.add_argument("--only-batch", action="store_true",
+                    help="time the batched set only (for profiler runs): no CPU baseline, FP64 sample, "
+                         "accuracy or serving legs")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: every simulation of the set fits one MI355X and the set "
@@ -98,6 +146,10 @@ def main():
     from paper_1803_09380_amd import workloads as wl
     cases = wl.batch(seed=args.seed, count=args.sims, precision=wl.F32)
 
+    if args.only_batch:
+        args.no_cpu = True
+        args.fp64_sample = 0
+        args.serve_requests = 0
     cpu = None
     if not args.no_cpu:
         cpu = run_cpu_baseline(cases, args.cpu_seconds)
@@ -147,41 +199,27 @@ def main():
     torch.cuda.synchronize()
 
     # ---- FP64 plain path: members of the same set one at a time, direct launches
+    f64_mlups = f32_sample_mlups = err = None
     f64_updates, f64_time = 0, 0.0
-    for c in cases[:args.fp64_sample]:
-        s = lbmib.Sim.from_case(c, precision=lbmib.F64)
-        s.step(2)
-        s.sync()
-        t0 = time.perf_counter()
-        s.step(args.fp64_steps)
-        s.sync()
-        f64_time += time.perf_counter() - t0
-        f64_updates += c["nx"] * c["ny"] * args.fp64_steps
-        s.close()
-    f64_mlups = f64_updates / f64_time / 1e6
-    # batched FP32 on the same sample, for a like-for-like speedup
-    sample = [lbmib.Sim.from_case(c, precision=lbmib.F32_SHIFTED) for c in cases[:args.fp64_sample]]
-    b2 = lbmib.Batch(lbmib.F32_SHIFTED)
-    for s in sample:
-        b2.admit(s)
-    b2.step(4)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    b2.step(args.fp64_steps)
-    torch.cuda.synchronize()
-    f32_sample_mlups = f64_updates / (time.perf_counter() - t0) / 1e6
-    b2.close()
-    del sample
+    if args.fp64_sample > 0:
+        f64_mlups, f32_sample_mlups, err = fp64_leg(args, cases, lbmib, wl, torch, np)
 
-    # ---- accuracy of the FP32 path against the FP64 path on one member (Couette 64)
-    ref = wl.couette(64)
-    a = lbmib.Sim.from_case(ref, precision=lbmib.F64)
-    b = lbmib.Sim.from_case(ref, precision=lbmib.F32_SHIFTED)
-    a.step(2000)
-    b.step(2000)
-    _, ua, va = a.fields()
-    _, ub, vb = b.fields()
-    err = float(np.sqrt(np.sum((ua - ub) ** 2 + (va - vb) ** 2) / np.sum(ua ** 2 + va ** 2)))
+    # ---- served stream: Poisson arrivals of settling requests, continuous batching
+    # ---- served stream: Poisson arrivals of settling requests, continuous batching
+    serving = None
+    if args.serve_requests > 0:
+        from paper_1803_09380_amd.serve import GpuExecutor, Request, Server
+        arr = wl.arrivals(seed=args.seed, rate=20.0, count=args.serve_requests, steps=args.serve_steps)
+        reqs = [Request(rid=r["id"], t_arrive=r["t_arrive"], case=r["case"], steps=r["steps"]) for r in arr]
+        budget = 64 << 30
+        ex = GpuExecutor(lbmib.F32_SHIFTED, hbm_budget=budget)
+        srv = Server(ex, hbm_budget=budget, chunk=100)
+        srv.run(reqs)
+        ex.close()
+        serving = srv.stats.summary()
+        serving.update({"arrivals": "Poisson, mean 20/s, seed %d" % args.seed, "lattice": "400x4000 closed box",
+                        "steps_per_request": args.serve_steps, "hbm_budget_bytes": budget,
+                        "particles": "1 or 2 free circles, D 16..40, density ratio 1.01..1.5"})
 
     out = {
         "metric": METRIC,
@@ -213,12 +251,14 @@ def main():
                               "correction": round(ms[2] / args.profile_steps, 4),
                               "bookkeeping": round(ms[3] / args.profile_steps, 4)},
         },
-        "fp64_plain": {"value": round(f64_mlups, 1), "unit": "MLUPS",
-                       "sample": "first %d members, %d steps each, one at a time" % (args.fp64_sample, args.fp64_steps),
-                       "fp32_batched_same_sample": round(f32_sample_mlups, 1),
-                       "speedup_fp32_batched": round(f32_sample_mlups / f64_mlups, 2)},
-        "accuracy": {"fp32_vs_fp64_velocity_rel_l2": err, "case": "couette64, 2000 steps"},
+        "fp64_plain": None if f64_mlups is None else {
+            "value": round(f64_mlups, 1), "unit": "MLUPS",
+            "sample": "first %d members, %d steps each, one at a time" % (args.fp64_sample, args.fp64_steps),
+            "fp32_batched_same_sample": round(f32_sample_mlups, 1),
+            "speedup_fp32_batched": round(f32_sample_mlups / f64_mlups, 2)},
+        "accuracy": None if err is None else {"fp32_vs_fp64_velocity_rel_l2": err, "case": "couette64, 2000 steps"},
         "unstable_members": unstable,
+        "serving": serving,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

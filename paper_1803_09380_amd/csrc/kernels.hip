@@ -49,8 +49,14 @@ template <typename T, int TX, int TY, int RPT>
 __global__ void __launch_bounds__(TX* TY)
     k_sweep(const SimDev* __restrict__ sims, const int4* __restrict__ tiles,
             const BatchHeader* __restrict__ hdr, int ntiles_arg, int parity) {
-    const int ntiles = hdr ? hdr->ntiles : ntiles_arg;
-    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    int t0 = blockIdx.x, t1 = hdr ? hdr->ntiles : ntiles_arg, dt = gridDim.x;
+    if (hdr && (gridDim.x & 7) == 0) {
+        const int xcd = blockIdx.x & 7;
+        t0 = hdr->xcd_start[xcd] + (blockIdx.x >> 3);
+        t1 = hdr->xcd_start[xcd + 1];
+        dt = gridDim.x >> 3;
+    }
+    for (int t = t0; t < t1; t += dt) {
         const int4 tile = tiles[t];
         const SimDev& S = sims[tile.x];
         if (!S.active) continue;
@@ -382,29 +388,50 @@ __device__ void collision_force(double xi0, double xi1, double xj0, double xj1, 
     fy += mag * dy / d;
 }
 
-// marker pass: interpolate (rho, j, jj/rho) at every marker from the band,
+// LDS arena of the correction kernel: the per-marker weights, the band's run
+// offsets and the band's (rho, j) are placed here when they fit, otherwise
+// they stay in the group's global scratch (generic pointers serve both).  A
+// plan rebuilt on the device first uses the arena for its sort keys.
+constexpr int kIbArenaBytes = 120 * 1024;
+
+struct Bump {
+    char* base;
+    int off;
+    __device__ void* take(long bytes, void* fallback) {
+        const long a = (bytes + 15) & ~15L;
+        if (off + a <= kIbArenaBytes) {
+            void* p = base + off;
+            off += (int)a;
+            return p;
+        }
+        return fallback;
+    }
+};
+
+// marker pass: interpolate (rho, j, jj/rho) at marker g from the band,
 // deviation dm = rho* U - j*, dPi = rho* U U - Pi*
 template <typename T>
-__device__ __forceinline__ void interp_marker(const SimDev& S, const GroupDev& G, int g, const T* node_rho,
-                                              const T* node_jx, const T* node_jy, const T* phi,
-                                              double Ux, double Uy, T& dmx, T& dmy, T& dpxx, T& dpxy,
-                                              T& dpyy, T& rs) {
+__device__ __forceinline__ void interp_marker(const GroupDev& G, int g, const T* nrho, const T* njx,
+                                              const T* njy, const T* phi, double Ux, double Uy, T& dmx,
+                                              T& dmy, T& dpxx, T& dpxy, T& dpyy, T& rs) {
+    int k[16];
     T px[4], py[4];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        px[k] = phi[g * 8 + k];
-        py[k] = phi[g * 8 + 4 + k];
+    for (int q = 0; q < 16; ++q) k[q] = G.mnode[g * 16 + q];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        px[q] = phi[g * 8 + q];
+        py[q] = phi[g * 8 + 4 + q];
     }
     T r = 0, jx = 0, jy = 0, pxx = 0, pxy = 0, pyy = 0;
-    const int* mn = G.mnode + g * 16;
 #pragma unroll
     for (int ky = 0; ky < 4; ++ky)
 #pragma unroll
         for (int kx = 0; kx < 4; ++kx) {
-            const int k = mn[ky * 4 + kx];
-            if (k < 0) continue;
+            const int n = k[ky * 4 + kx];
+            if (n < 0) continue;
             const T D = px[kx] * py[ky];
-            const T nr = node_rho[k], nx = node_jx[k], ny = node_jy[k];
+            const T nr = nrho[n], nx = njx[n], ny = njy[n];
             const T inv = T(1) / nr;
             r += D * nr;
             jx += D * nx;
@@ -422,16 +449,43 @@ __device__ __forceinline__ void interp_marker(const SimDev& S, const GroupDev& G
     rs = r;
 }
 
+// node pass: sum over the node's stencil entries (ascending marker) of
+// D * w[stride * g + c] for C components
+template <typename T, int C>
+__device__ __forceinline__ void spread_node(const int* __restrict__ ent, const T* __restrict__ entD, const T* w,
+                                            int stride, int e0, int e1, T out[C]) {
+#pragma unroll
+    for (int c = 0; c < C; ++c) out[c] = T(0);
+    int e = e0;
+    for (; e + 4 <= e1; e += 4) {
+        int g[4];
+        T d[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            g[q] = ent[e + q] >> 4;
+            d[q] = entD[e + q];
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int c = 0; c < C; ++c) out[c] += d[q] * w[stride * g[q] + c];
+    }
+    for (; e < e1; ++e) {
+        const int g = ent[e] >> 4;
+        const T d = entD[e];
+#pragma unroll
+        for (int c = 0; c < C; ++c) out[c] += d * w[stride * g + c];
+    }
+}
+
 template <typename T, int NT>
 __global__ void __launch_bounds__(NT)
     k_ib(const SimDev* __restrict__ sims, GroupDev* __restrict__ groups, const BatchHeader* __restrict__ hdr,
          int ngroups_arg, int parity) {
-    // LDS: plan keys (dynamic plans) share space with the per-marker weights
-    __shared__ unsigned long long smem_keys[kMaxDynEntries];  // 64 KiB
+    __shared__ __align__(16) char arena[kIbArenaBytes];
     __shared__ double red[256];
     __shared__ int scan_tmp[NT];
     __shared__ double body_out[8][5];
-    T* lds_w = reinterpret_cast<T*>(smem_keys);  // 2 * M values, M <= 4096 (T = float) / 4096 (double)
     const int ngroups = hdr ? hdr->ngroups : ngroups_arg;
     const int tid = threadIdx.x;
     for (int gi = blockIdx.x; gi < ngroups; gi += gridDim.x) {
@@ -441,29 +495,45 @@ __global__ void __launch_bounds__(NT)
         const int sw = 1 - (parity >= 0 ? parity : S.swapped);
         const int M = G.M;
         int nband = G.nband, nent = G.nent;
-        if (G.dynamic) {
-            build_plan<NT>(S, G, smem_keys, scan_tmp, nband, nent);
-        }
-        (void)nent;
-        T* node_rho = reinterpret_cast<T*>(G.node_rho);
-        T* node_jx = reinterpret_cast<T*>(G.node_jx);
-        T* node_jy = reinterpret_cast<T*>(G.node_jy);
+        if (G.dynamic) build_plan<NT>(S, G, reinterpret_cast<unsigned long long*>(arena), scan_tmp, nband, nent);
         T* phi = reinterpret_cast<T*>(G.m_phi);
-        T* tot = reinterpret_cast<T*>(G.m_tot);
-        // stencil weights of Eq. 15(c) and zeroed accumulators
-        for (int g = tid; g < M; g += NT) {
-            int body;
-            const int mi = marker_index(S, G, g, body);
-            const double X = S.mX[mi], Y = S.mY[mi];
-            const double fx = floor(X) - 1.0, fy = floor(Y) - 1.0;
+        T* entD = reinterpret_cast<T*>(G.ent_D);
+        // stencil weights of Eq. 15(c): phi per marker, D per stencil entry (static plans: once)
+        const bool fresh = G.dynamic || G.flags[0] == 0;
+        __syncthreads();
+        if (fresh) {
+            for (int g = tid; g < M; g += NT) {
+                int body;
+                const int mi = marker_index(S, G, g, body);
+                const double X = S.mX[mi], Y = S.mY[mi];
+                const double fx = floor(X) - 1.0, fy = floor(Y) - 1.0;
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                phi[g * 8 + k] = phi4<T>(T(fx + k - X));
-                phi[g * 8 + 4 + k] = phi4<T>(T(fy + k - Y));
+                for (int q = 0; q < 4; ++q) {
+                    phi[g * 8 + q] = phi4<T>(T(fx + q - X));
+                    phi[g * 8 + 4 + q] = phi4<T>(T(fy + q - Y));
+                }
             }
+            __syncthreads();
+            for (int e = tid; e < nent; e += NT) {
+                const int p = G.ent[e];
+                const int g = p >> 4;
+                entD[e] = phi[g * 8 + (p & 3)] * phi[g * 8 + 4 + ((p >> 2) & 3)];
+            }
+            __syncthreads();
+            if (tid == 0 && !G.dynamic) G.flags[0] = 1;
+        }
+        for (int g = tid; g < M; g += NT)
 #pragma unroll
             for (int c = 0; c < 5; ++c) G.m_acc[g * 5 + c] = 0.0;
-        }
+        // LDS placement (uniform across the workgroup)
+        Bump bump{arena, 0};
+        T* wt = reinterpret_cast<T*>(bump.take(5L * M * sizeof(T), G.m_wtot));
+        int* run = reinterpret_cast<int*>(bump.take(4L * (nband + 1), G.node_run));
+        T* nrho = reinterpret_cast<T*>(bump.take((long)nband * sizeof(T), G.node_rho));
+        T* njx = reinterpret_cast<T*>(bump.take((long)nband * sizeof(T), G.node_jx));
+        T* njy = reinterpret_cast<T*>(bump.take((long)nband * sizeof(T), G.node_jy));
+        if (run != G.node_run)
+            for (int k = tid; k <= nband; k += NT) run[k] = G.node_run[k];
         // gather (rho, j) of the band from the post-stream populations
         const T rho_base = T(S.rho_base);
         for (int k = tid; k < nband; k += NT) {
@@ -473,9 +543,9 @@ __global__ void __launch_bounds__(NT)
 #pragma unroll
             for (int i = 0; i < 9; ++i) h[i] = *loc<T>(S, i, x, y, sw);
             const T Ssum = ((h[0] + h[1]) + (h[2] + h[3])) + ((h[4] + h[5]) + (h[6] + h[7])) + h[8];
-            node_rho[k] = rho_base + Ssum;
-            node_jx[k] = (h[1] + h[5] + h[8]) - (h[3] + h[6] + h[7]);
-            node_jy[k] = (h[2] + h[5] + h[6]) - (h[4] + h[7] + h[8]);
+            nrho[k] = rho_base + Ssum;
+            njx[k] = (h[1] + h[5] + h[8]) - (h[3] + h[6] + h[7]);
+            njy[k] = (h[2] + h[5] + h[6]) - (h[4] + h[7] + h[8]);
         }
         __syncthreads();
         const int iters = S.ib_iters;
@@ -484,8 +554,7 @@ __global__ void __launch_bounds__(NT)
                 int body;
                 const int mi = marker_index(S, G, g, body);
                 T dmx, dmy, dpxx, dpxy, dpyy, rs;
-                interp_marker<T>(S, G, g, node_rho, node_jx, node_jy, phi, S.mU[mi], S.mV[mi], dmx, dmy,
-                                 dpxx, dpxy, dpyy, rs);
+                interp_marker<T>(G, g, nrho, njx, njy, phi, S.mU[mi], S.mV[mi], dmx, dmy, dpxx, dpxy, dpyy, rs);
                 double* acc = G.m_acc + g * 5;
                 acc[0] += (double)dmx;
                 acc[1] += (double)dmy;
@@ -493,23 +562,16 @@ __global__ void __launch_bounds__(NT)
                 acc[3] += (double)dpxy;
                 acc[4] += (double)dpyy;
                 const T ds = T(S.mds[mi]);
-                lds_w[2 * g] = ds * dmx;
-                lds_w[2 * g + 1] = ds * dmy;
+                wt[2 * g] = ds * dmx;
+                wt[2 * g + 1] = ds * dmy;
             }
             __syncthreads();
             // Eqs. 26-27 on the momentum: j(x) += sum_l D(x - X_l) ds_l dm_l, ascending l
             for (int k = tid; k < nband; k += NT) {
-                const int e0 = G.node_run[k], e1 = G.node_run[k + 1];
-                T ix = 0, iy = 0;
-                for (int e = e0; e < e1; ++e) {
-                    const int p = G.ent[e];
-                    const int g = p >> 4;
-                    const T D = phi[g * 8 + (p & 3)] * phi[g * 8 + 4 + ((p >> 2) & 3)];
-                    ix += D * lds_w[2 * g];
-                    iy += D * lds_w[2 * g + 1];
-                }
-                node_jx[k] += ix;
-                node_jy[k] += iy;
+                T inc[2];
+                spread_node<T, 2>(G.ent, entD, wt, 2, run[k], run[k + 1], inc);
+                njx[k] += inc[0];
+                njy[k] += inc[1];
             }
             __syncthreads();
         }
@@ -518,44 +580,41 @@ __global__ void __launch_bounds__(NT)
             int body;
             const int mi = marker_index(S, G, g, body);
             T dmx, dmy, dpxx, dpxy, dpyy, rs;
-            interp_marker<T>(S, G, g, node_rho, node_jx, node_jy, phi, S.mU[mi], S.mV[mi], dmx, dmy, dpxx,
-                             dpxy, dpyy, rs);
+            interp_marker<T>(G, g, nrho, njx, njy, phi, S.mU[mi], S.mV[mi], dmx, dmy, dpxx, dpxy, dpyy, rs);
             const double ds = S.mds[mi];
             const double* acc = G.m_acc + g * 5;
-#pragma unroll
-            for (int c = 0; c < 5; ++c) tot[g * 5 + c] = T(ds * acc[c]);
             const BodyDev& B = S.bodies[body];
             const double Fx = -ds * acc[0], Fy = -ds * acc[1];
             const double r2 = (double)dmx * (double)dmx + (double)dmy * (double)dmy;
-            G.m_red[g * 4 + 0] = Fx;
-            G.m_red[g * 4 + 1] = Fy;
-            G.m_red[g * 4 + 2] = (S.mX[mi] - B.xc[0]) * Fy - (S.mY[mi] - B.xc[1]) * Fx;
-            G.m_red[g * 4 + 3] = r2;
-            lds_w[g] = T(sqrt(r2) / (double)rs);  // slip speed (reuses the weight buffer)
+            double* mr = G.m_red + g * 5;
+            mr[0] = Fx;
+            mr[1] = Fy;
+            mr[2] = (S.mX[mi] - B.xc[0]) * Fy - (S.mY[mi] - B.xc[1]) * Fx;
+            mr[3] = r2;
+            mr[4] = sqrt(r2) / (double)rs;
+        }
+        __syncthreads();
+        for (int g = tid; g < M; g += NT) {
+            int body;
+            const int mi = marker_index(S, G, g, body);
+            const double ds = S.mds[mi];
+            const double* acc = G.m_acc + g * 5;
+#pragma unroll
+            for (int c = 0; c < 5; ++c) wt[g * 5 + c] = T(ds * acc[c]);
         }
         __syncthreads();
         // final spread of sum_n delta f (Eq. 28 is linear in dm and dPi) and correction (Eq. 27)
         for (int k = tid; k < nband; k += NT) {
-            const int e0 = G.node_run[k], e1 = G.node_run[k + 1];
-            T A0 = 0, A1 = 0, Bxx = 0, Bxy = 0, Byy = 0;
-            for (int e = e0; e < e1; ++e) {
-                const int p = G.ent[e];
-                const int g = p >> 4;
-                const T D = phi[g * 8 + (p & 3)] * phi[g * 8 + 4 + ((p >> 2) & 3)];
-                A0 += D * tot[g * 5 + 0];
-                A1 += D * tot[g * 5 + 1];
-                Bxx += D * tot[g * 5 + 2];
-                Bxy += D * tot[g * 5 + 3];
-                Byy += D * tot[g * 5 + 4];
-            }
+            T t5[5];
+            spread_node<T, 5>(G.ent, entD, wt, 5, run[k], run[k + 1], t5);
             const int cell = G.node_cell[k];
             const int x = cell % S.nx, y = cell / S.nx;
-            const T trB = T(1.5) * (Bxx + Byy);
+            const T trB = T(1.5) * (t5[2] + t5[4]);
 #pragma unroll
             for (int i = 0; i < 9; ++i) {
                 const T ex = T(ex_of(i)), ey = T(ey_of(i));
-                const T d = weight_of<T>(i) *
-                            (T(3) * (ex * A0 + ey * A1) + T(4.5) * (ex * ex * Bxx + T(2) * ex * ey * Bxy + ey * ey * Byy) - trB);
+                const T d = weight_of<T>(i) * (T(3) * (ex * t5[0] + ey * t5[1]) +
+                                               T(4.5) * (ex * ex * t5[2] + T(2) * ex * ey * t5[3] + ey * ey * t5[4]) - trB);
                 T* p = loc<T>(S, i, x, y, sw);
                 *p = *p + d;
             }
@@ -565,13 +624,12 @@ __global__ void __launch_bounds__(NT)
         int base = 0;
         for (int b = 0; b < G.nbody; ++b) {
             const int nb = S.bodies[G.body[b]].n;
-            const double* mr = G.m_red + base * 4;
-            const T* slip = lds_w + base;
-            double fx = det_sum<NT>(nb, [&](int l) { return mr[l * 4 + 0]; }, red);
-            double fy = det_sum<NT>(nb, [&](int l) { return mr[l * 4 + 1]; }, red);
-            double tq = det_sum<NT>(nb, [&](int l) { return mr[l * 4 + 2]; }, red);
-            double r2 = det_sum<NT>(nb, [&](int l) { return mr[l * 4 + 3]; }, red);
-            double mx = det_max<NT>(nb, [&](int l) { return (double)slip[l]; }, red);
+            const double* mr = G.m_red + base * 5;
+            double fx = det_sum<NT>(nb, [&](int l) { return mr[l * 5 + 0]; }, red);
+            double fy = det_sum<NT>(nb, [&](int l) { return mr[l * 5 + 1]; }, red);
+            double tq = det_sum<NT>(nb, [&](int l) { return mr[l * 5 + 2]; }, red);
+            double r2 = det_sum<NT>(nb, [&](int l) { return mr[l * 5 + 3]; }, red);
+            double mx = det_max<NT>(nb, [&](int l) { return mr[l * 5 + 4]; }, red);
             if (tid == 0) {
                 body_out[b][0] = fx;
                 body_out[b][1] = fy;

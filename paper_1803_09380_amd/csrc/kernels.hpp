@@ -15,7 +15,7 @@ constexpr int kNumTilings = 6;
 extern const Tiling kTilings[kNumTilings];
 
 // Threads per correction workgroup (the results do not depend on it).
-constexpr int kIbThreads = 512;
+constexpr int kIbThreads = 1024;
 // Entries sorted in LDS when a plan is rebuilt on the device (16 per marker).
 constexpr int kMaxDynEntries = 8192;
 constexpr int kMaxGroupMarkers = 4096;

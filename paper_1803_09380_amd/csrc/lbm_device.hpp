@@ -98,20 +98,26 @@ struct GroupDev {
     int32_t* node_run;        // [cap_nodes + 1] first entry of each node
     int32_t* ent;             // [cap_ent] (group marker << 4) | (ky << 2) | kx
     int32_t* mnode;           // [M * 16] band node of each stencil slot, -1 if dropped
-    int32_t* plan_size;       // [2] device-side nband, nent (dynamic plans)
-    void* node_rho;           // T [cap_nodes]
+    int32_t* flags;           // [1] device flag: stencil weights of a static plan are current
+    void* node_rho;           // T [cap_nodes] (used when the band does not fit in LDS)
     void* node_jx;            // T [cap_nodes]
     void* node_jy;            // T [cap_nodes]
+    void* ent_D;              // T [cap_ent] delta weight D of every stencil entry
     void* m_phi;              // T [M * 8]: phi_x[4], phi_y[4]
-    void* m_tot;              // T [M * 5]: ds * (sum dm, sum dPi) for the final spread
+    void* m_wtot;             // T [M * 5]: per-sweep ds*dm (first 2M), then ds * (sum dm, sum dPi)
     double* m_acc;            // [M * 5] running sums of dm (2) and dPi (3), FP64
-    double* m_red;            // [M * 4] per-marker Fx, Fy, T, |dm|^2 for reductions
+    double* m_red;            // [M * 5] per-marker Fx, Fy, T, |dm|^2, slip for the reductions
 };
 
 // Work counts of a batch, read by persistent kernels so that a captured graph
 // stays valid while the tables change.
+// Sweep tiles are stored grouped by XCD: tiles [xcd_start[k], xcd_start[k+1])
+// are swept by the blocks with blockIdx.x % 8 == k (workgroups are dealt to
+// the eight XCDs round-robin), so x-neighbouring tiles, which share cache lines
+// through the shifted accesses of the swapped sweep, meet in one L2.
 struct BatchHeader {
     int32_t nsims, ntiles, nbc, ngroups;
+    int32_t xcd_start[9];
 };
 
 // ---------------------------------------------------------------- indexing

@@ -72,7 +72,7 @@ struct HostBody {
 // One group's plan and scratch on the device plus its host descriptor.
 struct Group {
     GroupDev d{};
-    DevBuf node_cell, node_run, ent, mnode, plan_size, node_rho, node_jx, node_jy, m_phi, m_tot, m_acc, m_red;
+    DevBuf node_cell, node_run, ent, mnode, flags, node_rho, node_jx, node_jy, ent_D, m_phi, m_wtot, m_acc, m_red;
 };
 
 }  // namespace
@@ -356,24 +356,27 @@ lbm_status rebuild_ib(lbm_sim* s) {
         HIPS(s, G->node_run.alloc(sizeof(int) * (d.cap_nodes + 1)));
         HIPS(s, G->ent.alloc(sizeof(int) * std::max(1, d.cap_ent)));
         HIPS(s, G->mnode.alloc(sizeof(int) * std::max(1, 16 * M)));
-        HIPS(s, G->plan_size.alloc(sizeof(int) * 2));
+        HIPS(s, G->flags.alloc(sizeof(int) * 4));
+        HIPS(s, hipMemsetAsync(G->flags.p, 0, sizeof(int) * 4, st));
         HIPS(s, G->node_rho.alloc(tsz * d.cap_nodes));
         HIPS(s, G->node_jx.alloc(tsz * d.cap_nodes));
         HIPS(s, G->node_jy.alloc(tsz * d.cap_nodes));
+        HIPS(s, G->ent_D.alloc(tsz * std::max(1, d.cap_ent)));
         HIPS(s, G->m_phi.alloc(tsz * 8 * std::max(1, M)));
-        HIPS(s, G->m_tot.alloc(tsz * 5 * std::max(1, M)));
+        HIPS(s, G->m_wtot.alloc(tsz * 5 * std::max(1, M)));
         HIPS(s, G->m_acc.alloc(sizeof(double) * 5 * std::max(1, M)));
-        HIPS(s, G->m_red.alloc(sizeof(double) * 4 * std::max(1, M)));
+        HIPS(s, G->m_red.alloc(sizeof(double) * 5 * std::max(1, M)));
         d.node_cell = (int*)G->node_cell.p;
         d.node_run = (int*)G->node_run.p;
         d.ent = (int*)G->ent.p;
         d.mnode = (int*)G->mnode.p;
-        d.plan_size = (int*)G->plan_size.p;
+        d.flags = (int*)G->flags.p;
         d.node_rho = G->node_rho.p;
         d.node_jx = G->node_jx.p;
         d.node_jy = G->node_jy.p;
+        d.ent_D = G->ent_D.p;
         d.m_phi = G->m_phi.p;
-        d.m_tot = G->m_tot.p;
+        d.m_wtot = G->m_wtot.p;
         d.m_acc = (double*)G->m_acc.p;
         d.m_red = (double*)G->m_red.p;
         if (!d.dynamic) {
@@ -719,9 +722,9 @@ size_t lbm_device_bytes(const lbm_sim* s) {
     size_t b = s->pop.bytes + s->desc.bytes + s->status.bytes + s->bodies.bytes + s->markers.bytes + s->tiles.bytes +
                s->bcitems.bytes + s->groups.bytes;
     for (const Group* g : s->grp)
-        b += g->node_cell.bytes + g->node_run.bytes + g->ent.bytes + g->mnode.bytes + g->plan_size.bytes +
-             g->node_rho.bytes + g->node_jx.bytes + g->node_jy.bytes + g->m_phi.bytes + g->m_tot.bytes +
-             g->m_acc.bytes + g->m_red.bytes;
+        b += g->node_cell.bytes + g->node_run.bytes + g->ent.bytes + g->mnode.bytes + g->flags.bytes +
+             g->node_rho.bytes + g->node_jx.bytes + g->node_jy.bytes + g->ent_D.bytes + g->m_phi.bytes +
+             g->m_wtot.bytes + g->m_acc.bytes + g->m_red.bytes;
     return b;
 }
 
@@ -794,10 +797,19 @@ lbm_status upload_tables(lbm_batch* b) {
     std::vector<int4> tiles;
     std::vector<int2> bc;
     std::vector<GroupDev> groups;
+    // row bands of tiles dealt round-robin to the eight XCDs
+    std::vector<int4> per_xcd[8];
+    int band = 0;
     for (size_t k = 0; k < b->sims.size(); ++k) {
         lbm_sim* s = b->sims[k];
         sims.push_back(s->h);
-        build_tiles(s, (int)k, b->tiling, tiles);
+        std::vector<int4> mine;
+        build_tiles(s, (int)k, b->tiling, mine);
+        for (size_t i = 0; i < mine.size(); ++i) {
+            if (i > 0 && mine[i].z != mine[i - 1].z) ++band;
+            per_xcd[band & 7].push_back(mine[i]);
+        }
+        ++band;
         build_bc(s, (int)k, bc);
         for (Group* g : s->grp) {
             GroupDev d = g->d;
@@ -805,6 +817,16 @@ lbm_status upload_tables(lbm_batch* b) {
             groups.push_back(d);
         }
     }
+    BatchHeader h{};
+    h.nsims = (int)sims.size();
+    h.nbc = (int)bc.size();
+    h.ngroups = (int)groups.size();
+    for (int x = 0; x < 8; ++x) {
+        h.xcd_start[x] = (int)tiles.size();
+        tiles.insert(tiles.end(), per_xcd[x].begin(), per_xcd[x].end());
+    }
+    h.xcd_start[8] = (int)tiles.size();
+    h.ntiles = (int)tiles.size();
     bool grew = false;
     HIPB(b, ensure_cap<SimDev>(b->d_sims, b->cap_sims, sims.size(), grew));
     HIPB(b, ensure_cap<int4>(b->d_tiles, b->cap_tiles, tiles.size(), grew));
@@ -819,7 +841,6 @@ lbm_status upload_tables(lbm_batch* b) {
     if (!tiles.empty()) HIPB(b, hipMemcpyAsync(b->d_tiles.p, tiles.data(), sizeof(int4) * tiles.size(), hipMemcpyHostToDevice, b->stream));
     if (!bc.empty()) HIPB(b, hipMemcpyAsync(b->d_bc.p, bc.data(), sizeof(int2) * bc.size(), hipMemcpyHostToDevice, b->stream));
     if (!groups.empty()) HIPB(b, hipMemcpyAsync(b->d_groups.p, groups.data(), sizeof(GroupDev) * groups.size(), hipMemcpyHostToDevice, b->stream));
-    BatchHeader h{(int)sims.size(), (int)tiles.size(), (int)bc.size(), (int)groups.size()};
     HIPB(b, hipMemcpyAsync(b->d_hdr.p, &h, sizeof h, hipMemcpyHostToDevice, b->stream));
     HIPB(b, hipStreamSynchronize(b->stream));
     b->ntiles = h.ntiles;

@@ -82,9 +82,18 @@ _lib = None
 
 
 def load():
-    """Load liblbmib.so; raises when it is missing (build it with build.py)."""
+    """Load liblbmib.so; raises when it is missing (build it with build.py).
+
+    When PyTorch is installed it is imported first: its HIP runtime then
+    serves the library too (the library's libamdhip64.so.7 dependency resolves
+    to the runtime torch already loaded), so device pointers and streams can be
+    shared and the process holds one HIP runtime."""
     global _lib
     if _lib is None:
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         if not os.path.exists(LIB_PATH):
             raise RuntimeError("liblbmib.so is not built (%s); run paper_1803_09380_amd/build.py" % LIB_PATH)
         L = ctypes.CDLL(LIB_PATH)
