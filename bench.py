@@ -129,7 +129,8 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=50)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--autotune", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default sweep tiling instead of timing the candidates on the set")
     ap.add_argument("--tiling", type=int, default=-1)
     ap.add_argument("--serve-requests", type=int, default=24)
     ap.add_argument("--serve-steps", type=int, default=2000)
@@ -169,8 +170,8 @@ def main():
         assert batch.admit(s)
     if args.tiling >= 0:
         batch.set_tiling(args.tiling)
-    tiling = None
-    if args.autotune:
+    tiling = args.tiling
+    if args.tiling < 0 and not args.no_autotune:
         tiling = batch.autotune(trials=3)
     batch.step(args.warmup)
     torch.cuda.synchronize()
@@ -239,7 +240,7 @@ def main():
                         "channel 20Dx10D with D 16..64, Re 10..100), FP32 shifted populations, "
                         "10 correction sweeps per step" % args.sims,
             "seed": args.seed, "sims": args.sims, "cells": cells, "markers": markers,
-            "tiling": tiling if tiling is not None else args.tiling,
+            "tiling": tiling,
         },
         "roofline": {
             "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -19,8 +19,26 @@
 
 namespace lbmib {
 
-const Tiling kTilings[kNumTilings] = {{64, 4, 1}, {64, 4, 2}, {128, 2, 2}, {256, 1, 2},
-                                      {256, 1, 4}, {64, 4, 4}};
+// Tilings 6..11 repeat 0..5 with non-temporal loads and stores (streamed
+// data is not kept in the caches).  None of them changes the arithmetic.
+const Tiling kTilings[kNumTilings] = {{64, 4, 1, 0},  {64, 4, 2, 0}, {128, 2, 2, 0}, {256, 1, 2, 0},
+                                      {256, 1, 4, 0}, {64, 4, 4, 0}, {64, 4, 1, 1},  {64, 4, 2, 1},
+                                      {128, 2, 2, 1}, {256, 1, 2, 1}, {256, 1, 4, 1}, {64, 4, 4, 1}};
+
+template <bool NTMP, typename T>
+__device__ __forceinline__ T ldg(const T* p) {
+    if constexpr (NTMP)
+        return __builtin_nontemporal_load(p);
+    else
+        return *p;
+}
+template <bool NTMP, typename T>
+__device__ __forceinline__ void stg(T* p, T v) {
+    if constexpr (NTMP)
+        __builtin_nontemporal_store(v, p);
+    else
+        *p = v;
+}
 
 // ---------------------------------------------------------------- collision
 
@@ -45,7 +63,7 @@ __device__ __forceinline__ void bgk(T h[9], T rho_base, T omega, uint32_t& bad) 
 
 // ---------------------------------------------------------------- sweep
 
-template <typename T, int TX, int TY, int RPT>
+template <typename T, int TX, int TY, int RPT, bool NTMP>
 __global__ void __launch_bounds__(TX* TY)
     k_sweep(const SimDev* __restrict__ sims, const int4* __restrict__ tiles,
             const BatchHeader* __restrict__ hdr, int ntiles_arg, int parity) {
@@ -80,32 +98,32 @@ __global__ void __launch_bounds__(TX* TY)
                 if (!sw) {
                     // natural state: own slots; write f*_i into slot opp(i)
 #pragma unroll
-                    for (int i = 0; i < 9; ++i) h[i] = P[i * pl + r0 + x];
+                    for (int i = 0; i < 9; ++i) h[i] = ldg<NTMP>(&P[i * pl + r0 + x]);
                     bgk<T>(h, rho_base, omega, bad);
 #pragma unroll
-                    for (int i = 0; i < 9; ++i) P[opp_of(i) * pl + r0 + x] = h[i];
+                    for (int i = 0; i < 9; ++i) stg<NTMP>(&P[opp_of(i) * pl + r0 + x], h[i]);
                 } else {
                     // swapped state: f_i(x) = slot opp(i) of x - e_i
-                    h[0] = P[0 * pl + r0 + x];
-                    h[1] = P[3 * pl + r0 + xm];
-                    h[2] = P[4 * pl + rm + x];
-                    h[3] = P[1 * pl + r0 + xp];
-                    h[4] = P[2 * pl + rp + x];
-                    h[5] = P[7 * pl + rm + xm];
-                    h[6] = P[8 * pl + rm + xp];
-                    h[7] = P[5 * pl + rp + xp];
-                    h[8] = P[6 * pl + rp + xm];
+                    h[0] = ldg<NTMP>(&P[0 * pl + r0 + x]);
+                    h[1] = ldg<NTMP>(&P[3 * pl + r0 + xm]);
+                    h[2] = ldg<NTMP>(&P[4 * pl + rm + x]);
+                    h[3] = ldg<NTMP>(&P[1 * pl + r0 + xp]);
+                    h[4] = ldg<NTMP>(&P[2 * pl + rp + x]);
+                    h[5] = ldg<NTMP>(&P[7 * pl + rm + xm]);
+                    h[6] = ldg<NTMP>(&P[8 * pl + rm + xp]);
+                    h[7] = ldg<NTMP>(&P[5 * pl + rp + xp]);
+                    h[8] = ldg<NTMP>(&P[6 * pl + rp + xm]);
                     bgk<T>(h, rho_base, omega, bad);
                     // f*_i goes to slot i of x + e_i
-                    P[0 * pl + r0 + x] = h[0];
-                    P[1 * pl + r0 + xp] = h[1];
-                    P[2 * pl + rp + x] = h[2];
-                    P[3 * pl + r0 + xm] = h[3];
-                    P[4 * pl + rm + x] = h[4];
-                    P[5 * pl + rp + xp] = h[5];
-                    P[6 * pl + rp + xm] = h[6];
-                    P[7 * pl + rm + xm] = h[7];
-                    P[8 * pl + rm + xp] = h[8];
+                    stg<NTMP>(&P[0 * pl + r0 + x], h[0]);
+                    stg<NTMP>(&P[1 * pl + r0 + xp], h[1]);
+                    stg<NTMP>(&P[2 * pl + rp + x], h[2]);
+                    stg<NTMP>(&P[3 * pl + r0 + xm], h[3]);
+                    stg<NTMP>(&P[4 * pl + rm + x], h[4]);
+                    stg<NTMP>(&P[5 * pl + rp + xp], h[5]);
+                    stg<NTMP>(&P[6 * pl + rp + xm], h[6]);
+                    stg<NTMP>(&P[7 * pl + rm + xm], h[7]);
+                    stg<NTMP>(&P[8 * pl + rm + xp], h[8]);
                 }
             }
         }
@@ -388,50 +406,90 @@ __device__ void collision_force(double xi0, double xi1, double xj0, double xj1, 
     fy += mag * dy / d;
 }
 
-// LDS arena of the correction kernel: the per-marker weights, the band's run
-// offsets and the band's (rho, j) are placed here when they fit, otherwise
-// they stay in the group's global scratch (generic pointers serve both).  A
-// plan rebuilt on the device first uses the arena for its sort keys.
-constexpr int kIbArenaBytes = 120 * 1024;
+// LDS arena of the correction kernel.  In order of use per sweep, the band's
+// (rho, j), the per-marker weights, the band's run offsets, the stencil node
+// indices (16-bit), the per-marker phi values and the stencil entries are
+// placed here while they fit; the rest stay in the group's global scratch
+// (generic pointers serve both).  A plan rebuilt on the device first uses the
+// arena for its sort keys.
+constexpr int kIbArenaBytes = 144 * 1024;
 
 struct Bump {
     char* base;
     int off;
-    __device__ void* take(long bytes, void* fallback) {
+    __device__ void* take(long bytes) {
         const long a = (bytes + 15) & ~15L;
         if (off + a <= kIbArenaBytes) {
             void* p = base + off;
             off += (int)a;
             return p;
         }
-        return fallback;
+        return nullptr;
     }
+};
+
+// group marker -> body slot and index into the simulation's marker arrays
+struct GroupLookup {
+    int nb;
+    int body[8];
+    int m0[8];
+    int gbase[9];
+};
+
+__device__ __forceinline__ int lookup(const GroupLookup& L, int g, int& body) {
+    int b = 0;
+#pragma unroll
+    for (int k = 1; k < 8; ++k)
+        if (k < L.nb && g >= L.gbase[k]) b = k;
+    body = L.body[b];
+    return L.m0[b] + g - L.gbase[b];
+}
+
+template <typename T>
+struct BandView {
+    T *rho, *jx, *jy;          // band (rho, j)
+    T* wt;                     // per-marker weights
+    const int* run;            // band run offsets
+    const unsigned short* mn16;  // stencil node indices in LDS (0xFFFF: dropped), or null
+    const int* mn32;           // the same in global memory
+    const T* phi;              // per-marker phi_x[4], phi_y[4]
+    const unsigned short* ent16;  // stencil entry -> marker in LDS, or null
+    const int* ent32;          // packed entries in global memory
+    const T* entD;             // delta weight of every entry
 };
 
 // marker pass: interpolate (rho, j, jj/rho) at marker g from the band,
 // deviation dm = rho* U - j*, dPi = rho* U U - Pi*
 template <typename T>
-__device__ __forceinline__ void interp_marker(const GroupDev& G, int g, const T* nrho, const T* njx,
-                                              const T* njy, const T* phi, double Ux, double Uy, T& dmx,
-                                              T& dmy, T& dpxx, T& dpxy, T& dpyy, T& rs) {
+__device__ __forceinline__ void interp_marker(const BandView<T>& B, int g, T U, T V, T& dmx, T& dmy, T& dpxx,
+                                              T& dpxy, T& dpyy, T& rs) {
     int k[16];
     T px[4], py[4];
+    if (B.mn16) {
 #pragma unroll
-    for (int q = 0; q < 16; ++q) k[q] = G.mnode[g * 16 + q];
+        for (int q = 0; q < 16; ++q) {
+            const int v = B.mn16[g * 16 + q];
+            k[q] = v == 0xFFFF ? -1 : v;
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < 16; ++q) k[q] = B.mn32[g * 16 + q];
+    }
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-        px[q] = phi[g * 8 + q];
-        py[q] = phi[g * 8 + 4 + q];
+        px[q] = B.phi[g * 8 + q];
+        py[q] = B.phi[g * 8 + 4 + q];
     }
     T r = 0, jx = 0, jy = 0, pxx = 0, pxy = 0, pyy = 0;
 #pragma unroll
-    for (int ky = 0; ky < 4; ++ky)
+    for (int ky = 0; ky < 4; ++ky) {
+        if (ky == 2) __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int kx = 0; kx < 4; ++kx) {
             const int n = k[ky * 4 + kx];
             if (n < 0) continue;
             const T D = px[kx] * py[ky];
-            const T nr = nrho[n], nx = njx[n], ny = njy[n];
+            const T nr = B.rho[n], nx = B.jx[n], ny = B.jy[n];
             const T inv = T(1) / nr;
             r += D * nr;
             jx += D * nx;
@@ -440,7 +498,7 @@ __device__ __forceinline__ void interp_marker(const GroupDev& G, int g, const T*
             pxy += D * nx * ny * inv;
             pyy += D * ny * ny * inv;
         }
-    const T U = T(Ux), V = T(Uy);
+    }
     dmx = r * U - jx;
     dmy = r * V - jy;
     dpxx = r * U * U - pxx;
@@ -452,18 +510,18 @@ __device__ __forceinline__ void interp_marker(const GroupDev& G, int g, const T*
 // node pass: sum over the node's stencil entries (ascending marker) of
 // D * w[stride * g + c] for C components
 template <typename T, int C>
-__device__ __forceinline__ void spread_node(const int* __restrict__ ent, const T* __restrict__ entD, const T* w,
-                                            int stride, int e0, int e1, T out[C]) {
+__device__ __forceinline__ void spread_node(const BandView<T>& B, int stride, int e0, int e1, T out[C]) {
 #pragma unroll
     for (int c = 0; c < C; ++c) out[c] = T(0);
+    const T* w = B.wt;
     int e = e0;
     for (; e + 4 <= e1; e += 4) {
         int g[4];
         T d[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            g[q] = ent[e + q] >> 4;
-            d[q] = entD[e + q];
+            g[q] = B.ent16 ? (int)B.ent16[e + q] : (B.ent32[e + q] >> 4);
+            d[q] = B.entD[e + q];
         }
 #pragma unroll
         for (int q = 0; q < 4; ++q)
@@ -471,14 +529,14 @@ __device__ __forceinline__ void spread_node(const int* __restrict__ ent, const T
             for (int c = 0; c < C; ++c) out[c] += d[q] * w[stride * g[q] + c];
     }
     for (; e < e1; ++e) {
-        const int g = ent[e] >> 4;
-        const T d = entD[e];
+        const int g = B.ent16 ? (int)B.ent16[e] : (B.ent32[e] >> 4);
+        const T d = B.entD[e];
 #pragma unroll
         for (int c = 0; c < C; ++c) out[c] += d * w[stride * g + c];
     }
 }
 
-template <typename T, int NT>
+template <typename T, int NT, int MPT>
 __global__ void __launch_bounds__(NT)
     k_ib(const SimDev* __restrict__ sims, GroupDev* __restrict__ groups, const BatchHeader* __restrict__ hdr,
          int ngroups_arg, int parity) {
@@ -486,6 +544,7 @@ __global__ void __launch_bounds__(NT)
     __shared__ double red[256];
     __shared__ int scan_tmp[NT];
     __shared__ double body_out[8][5];
+    __shared__ GroupLookup L;
     const int ngroups = hdr ? hdr->ngroups : ngroups_arg;
     const int tid = threadIdx.x;
     for (int gi = blockIdx.x; gi < ngroups; gi += gridDim.x) {
@@ -496,44 +555,85 @@ __global__ void __launch_bounds__(NT)
         const int M = G.M;
         int nband = G.nband, nent = G.nent;
         if (G.dynamic) build_plan<NT>(S, G, reinterpret_cast<unsigned long long*>(arena), scan_tmp, nband, nent);
-        T* phi = reinterpret_cast<T*>(G.m_phi);
-        T* entD = reinterpret_cast<T*>(G.ent_D);
+        if (tid == 0) {
+            int base = 0;
+            L.nb = G.nbody;
+            for (int b = 0; b < G.nbody; ++b) {
+                const BodyDev& Bd = S.bodies[G.body[b]];
+                L.body[b] = G.body[b];
+                L.m0[b] = Bd.m0;
+                L.gbase[b] = base;
+                base += Bd.n;
+            }
+            L.gbase[G.nbody] = base;
+        }
+        T* phi_g = reinterpret_cast<T*>(G.m_phi);
+        T* entD_g = reinterpret_cast<T*>(G.ent_D);
         // stencil weights of Eq. 15(c): phi per marker, D per stencil entry (static plans: once)
         const bool fresh = G.dynamic || G.flags[0] == 0;
         __syncthreads();
         if (fresh) {
             for (int g = tid; g < M; g += NT) {
                 int body;
-                const int mi = marker_index(S, G, g, body);
+                const int mi = lookup(L, g, body);
                 const double X = S.mX[mi], Y = S.mY[mi];
                 const double fx = floor(X) - 1.0, fy = floor(Y) - 1.0;
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
-                    phi[g * 8 + q] = phi4<T>(T(fx + q - X));
-                    phi[g * 8 + 4 + q] = phi4<T>(T(fy + q - Y));
+                    phi_g[g * 8 + q] = phi4<T>(T(fx + q - X));
+                    phi_g[g * 8 + 4 + q] = phi4<T>(T(fy + q - Y));
                 }
             }
             __syncthreads();
             for (int e = tid; e < nent; e += NT) {
                 const int p = G.ent[e];
                 const int g = p >> 4;
-                entD[e] = phi[g * 8 + (p & 3)] * phi[g * 8 + 4 + ((p >> 2) & 3)];
+                entD_g[e] = phi_g[g * 8 + (p & 3)] * phi_g[g * 8 + 4 + ((p >> 2) & 3)];
             }
             __syncthreads();
             if (tid == 0 && !G.dynamic) G.flags[0] = 1;
         }
-        for (int g = tid; g < M; g += NT)
-#pragma unroll
-            for (int c = 0; c < 5; ++c) G.m_acc[g * 5 + c] = 0.0;
-        // LDS placement (uniform across the workgroup)
+        // LDS placement (the same decisions on every thread)
         Bump bump{arena, 0};
-        T* wt = reinterpret_cast<T*>(bump.take(5L * M * sizeof(T), G.m_wtot));
-        int* run = reinterpret_cast<int*>(bump.take(4L * (nband + 1), G.node_run));
-        T* nrho = reinterpret_cast<T*>(bump.take((long)nband * sizeof(T), G.node_rho));
-        T* njx = reinterpret_cast<T*>(bump.take((long)nband * sizeof(T), G.node_jx));
-        T* njy = reinterpret_cast<T*>(bump.take((long)nband * sizeof(T), G.node_jy));
-        if (run != G.node_run)
-            for (int k = tid; k <= nband; k += NT) run[k] = G.node_run[k];
+        BandView<T> B;
+        B.rho = reinterpret_cast<T*>(bump.take((long)nband * sizeof(T)));
+        B.jx = reinterpret_cast<T*>(bump.take((long)nband * sizeof(T)));
+        B.jy = reinterpret_cast<T*>(bump.take((long)nband * sizeof(T)));
+        if (!B.rho || !B.jx || !B.jy) {
+            B.rho = reinterpret_cast<T*>(G.node_rho);
+            B.jx = reinterpret_cast<T*>(G.node_jx);
+            B.jy = reinterpret_cast<T*>(G.node_jy);
+        }
+        T* wt_l = reinterpret_cast<T*>(bump.take(5L * M * sizeof(T)));
+        B.wt = wt_l ? wt_l : reinterpret_cast<T*>(G.m_wtot);
+        int* run_l = reinterpret_cast<int*>(bump.take(4L * (nband + 1)));
+        B.run = run_l ? run_l : G.node_run;
+        unsigned short* mn_l =
+            nband < 0xFFFF ? reinterpret_cast<unsigned short*>(bump.take(2L * 16 * M)) : nullptr;
+        B.mn16 = mn_l;
+        B.mn32 = G.mnode;
+        T* phi_l = reinterpret_cast<T*>(bump.take(8L * M * sizeof(T)));
+        B.phi = phi_l ? phi_l : phi_g;
+        unsigned short* ent_l = reinterpret_cast<unsigned short*>(bump.take(2L * nent));
+        T* entD_l = ent_l ? reinterpret_cast<T*>(bump.take((long)nent * sizeof(T))) : nullptr;
+        if (!entD_l) ent_l = nullptr;
+        B.ent16 = ent_l;
+        B.ent32 = G.ent;
+        B.entD = entD_l ? entD_l : entD_g;
+        if (run_l)
+            for (int k = tid; k <= nband; k += NT) run_l[k] = G.node_run[k];
+        if (mn_l)
+            for (int e = tid; e < 16 * M; e += NT) {
+                const int v = G.mnode[e];
+                mn_l[e] = v < 0 ? (unsigned short)0xFFFF : (unsigned short)v;
+            }
+        if (phi_l)
+            for (int e = tid; e < 8 * M; e += NT) phi_l[e] = phi_g[e];
+        if (ent_l)
+            for (int e = tid; e < nent; e += NT) {
+                ent_l[e] = (unsigned short)(G.ent[e] >> 4);
+                entD_l[e] = entD_g[e];
+            }
         // gather (rho, j) of the band from the post-stream populations
         const T rho_base = T(S.rho_base);
         for (int k = tid; k < nband; k += NT) {
@@ -543,70 +643,86 @@ __global__ void __launch_bounds__(NT)
 #pragma unroll
             for (int i = 0; i < 9; ++i) h[i] = *loc<T>(S, i, x, y, sw);
             const T Ssum = ((h[0] + h[1]) + (h[2] + h[3])) + ((h[4] + h[5]) + (h[6] + h[7])) + h[8];
-            nrho[k] = rho_base + Ssum;
-            njx[k] = (h[1] + h[5] + h[8]) - (h[3] + h[6] + h[7]);
-            njy[k] = (h[2] + h[5] + h[6]) - (h[4] + h[7] + h[8]);
+            B.rho[k] = rho_base + Ssum;
+            B.jx[k] = (h[1] + h[5] + h[8]) - (h[3] + h[6] + h[7]);
+            B.jy[k] = (h[2] + h[5] + h[6]) - (h[4] + h[7] + h[8]);
+        }
+        // per-thread markers: velocities, arc lengths and running sums over the
+        // sweeps in registers (storage precision; the reductions over markers are FP64)
+        T mu[MPT], mv[MPT], mds[MPT];
+        T acc[MPT][5];
+#pragma unroll
+        for (int q = 0; q < MPT; ++q) {
+            const int g = tid + q * NT;
+            mu[q] = mv[q] = mds[q] = T(0);
+            if (g < M) {
+                int body;
+                const int mi = lookup(L, g, body);
+                mu[q] = T(S.mU[mi]);
+                mv[q] = T(S.mV[mi]);
+                mds[q] = T(S.mds[mi]);
+            }
+#pragma unroll
+            for (int c = 0; c < 5; ++c) acc[q][c] = T(0);
         }
         __syncthreads();
         const int iters = S.ib_iters;
         for (int n = 0; n < iters; ++n) {
-            for (int g = tid; g < M; g += NT) {
-                int body;
-                const int mi = marker_index(S, G, g, body);
-                T dmx, dmy, dpxx, dpxy, dpyy, rs;
-                interp_marker<T>(G, g, nrho, njx, njy, phi, S.mU[mi], S.mV[mi], dmx, dmy, dpxx, dpxy, dpyy, rs);
-                double* acc = G.m_acc + g * 5;
-                acc[0] += (double)dmx;
-                acc[1] += (double)dmy;
-                acc[2] += (double)dpxx;
-                acc[3] += (double)dpxy;
-                acc[4] += (double)dpyy;
-                const T ds = T(S.mds[mi]);
-                wt[2 * g] = ds * dmx;
-                wt[2 * g + 1] = ds * dmy;
+#pragma unroll
+            for (int q = 0; q < MPT; ++q) {
+                const int g = tid + q * NT;
+                if (g < M) {
+                    T dmx, dmy, dpxx, dpxy, dpyy, rs;
+                    interp_marker<T>(B, g, mu[q], mv[q], dmx, dmy, dpxx, dpxy, dpyy, rs);
+                    acc[q][0] += dmx;
+                    acc[q][1] += dmy;
+                    acc[q][2] += dpxx;
+                    acc[q][3] += dpxy;
+                    acc[q][4] += dpyy;
+                    B.wt[2 * g] = mds[q] * dmx;
+                    B.wt[2 * g + 1] = mds[q] * dmy;
+                }
+                // keep the markers' loads from piling up in registers
+                __builtin_amdgcn_sched_barrier(0);
             }
             __syncthreads();
             // Eqs. 26-27 on the momentum: j(x) += sum_l D(x - X_l) ds_l dm_l, ascending l
             for (int k = tid; k < nband; k += NT) {
                 T inc[2];
-                spread_node<T, 2>(G.ent, entD, wt, 2, run[k], run[k + 1], inc);
-                njx[k] += inc[0];
-                njy[k] += inc[1];
+                spread_node<T, 2>(B, 2, B.run[k], B.run[k + 1], inc);
+                B.jx[k] += inc[0];
+                B.jy[k] += inc[1];
             }
             __syncthreads();
         }
-        // mismatch left after the sweeps; totals for the final spread; per-marker force
-        for (int g = tid; g < M; g += NT) {
-            int body;
-            const int mi = marker_index(S, G, g, body);
-            T dmx, dmy, dpxx, dpxy, dpyy, rs;
-            interp_marker<T>(G, g, nrho, njx, njy, phi, S.mU[mi], S.mV[mi], dmx, dmy, dpxx, dpxy, dpyy, rs);
-            const double ds = S.mds[mi];
-            const double* acc = G.m_acc + g * 5;
-            const BodyDev& B = S.bodies[body];
-            const double Fx = -ds * acc[0], Fy = -ds * acc[1];
-            const double r2 = (double)dmx * (double)dmx + (double)dmy * (double)dmy;
-            double* mr = G.m_red + g * 5;
-            mr[0] = Fx;
-            mr[1] = Fy;
-            mr[2] = (S.mX[mi] - B.xc[0]) * Fy - (S.mY[mi] - B.xc[1]) * Fx;
-            mr[3] = r2;
-            mr[4] = sqrt(r2) / (double)rs;
-        }
-        __syncthreads();
-        for (int g = tid; g < M; g += NT) {
-            int body;
-            const int mi = marker_index(S, G, g, body);
-            const double ds = S.mds[mi];
-            const double* acc = G.m_acc + g * 5;
+        // mismatch left after the sweeps, per-marker force and torque; totals for the final spread
 #pragma unroll
-            for (int c = 0; c < 5; ++c) wt[g * 5 + c] = T(ds * acc[c]);
+        for (int q = 0; q < MPT; ++q) {
+            const int g = tid + q * NT;
+            if (g < M) {
+                int body;
+                const int mi = lookup(L, g, body);
+                T dmx, dmy, dpxx, dpxy, dpyy, rs;
+                interp_marker<T>(B, g, mu[q], mv[q], dmx, dmy, dpxx, dpxy, dpyy, rs);
+                const double ds = S.mds[mi];
+                const BodyDev& Bd = S.bodies[body];
+                const double Fx = -ds * (double)acc[q][0], Fy = -ds * (double)acc[q][1];
+                const double r2 = (double)dmx * (double)dmx + (double)dmy * (double)dmy;
+                double* mr = G.m_red + g * 5;
+                mr[0] = Fx;
+                mr[1] = Fy;
+                mr[2] = (S.mX[mi] - Bd.xc[0]) * Fy - (S.mY[mi] - Bd.xc[1]) * Fx;
+                mr[3] = r2;
+                mr[4] = sqrt(r2) / (double)rs;
+#pragma unroll
+                for (int c = 0; c < 5; ++c) B.wt[g * 5 + c] = T(ds * (double)acc[q][c]);
+            }
         }
         __syncthreads();
         // final spread of sum_n delta f (Eq. 28 is linear in dm and dPi) and correction (Eq. 27)
         for (int k = tid; k < nband; k += NT) {
             T t5[5];
-            spread_node<T, 5>(G.ent, entD, wt, 5, run[k], run[k + 1], t5);
+            spread_node<T, 5>(B, 5, B.run[k], B.run[k + 1], t5);
             const int cell = G.node_cell[k];
             const int x = cell % S.nx, y = cell / S.nx;
             const T trB = T(1.5) * (t5[2] + t5[4]);
@@ -621,10 +737,9 @@ __global__ void __launch_bounds__(NT)
         }
         __syncthreads();
         // FP64 reductions per body (order fixed by the marker index)
-        int base = 0;
         for (int b = 0; b < G.nbody; ++b) {
-            const int nb = S.bodies[G.body[b]].n;
-            const double* mr = G.m_red + base * 5;
+            const int nb = L.gbase[b + 1] - L.gbase[b];
+            const double* mr = G.m_red + L.gbase[b] * 5;
             double fx = det_sum<NT>(nb, [&](int l) { return mr[l * 5 + 0]; }, red);
             double fy = det_sum<NT>(nb, [&](int l) { return mr[l * 5 + 1]; }, red);
             double tq = det_sum<NT>(nb, [&](int l) { return mr[l * 5 + 2]; }, red);
@@ -637,68 +752,71 @@ __global__ void __launch_bounds__(NT)
                 body_out[b][3] = sqrt(r2 / nb);
                 body_out[b][4] = mx;
             }
-            base += nb;
         }
         __syncthreads();
-        // outputs and the rigid-body update of free circles (Eqs. 37, 39-42)
-        if (tid == 0) {
-            BodyDev* bodies = S.bodies;
-            for (int b = 0; b < G.nbody; ++b) {
-                BodyDev& B = bodies[G.body[b]];
-                B.F[0] = body_out[b][0];
-                B.F[1] = body_out[b][1];
-                B.T = body_out[b][2];
-                B.resid = body_out[b][3];
-                B.maxslip = body_out[b][4];
-            }
-            double Fc[8][2];
-            const double gmag = sqrt(S.gravity[0] * S.gravity[0] + S.gravity[1] * S.gravity[1]);
-            const double rho_f = S.rho0;
-            for (int b = 0; b < G.nbody; ++b) {
-                Fc[b][0] = Fc[b][1] = 0.0;
-                const BodyDev& B = bodies[G.body[b]];
-                if (B.kind != BODY_FREE) continue;
-                const double V = M_PI * B.R * B.R;
-                const double cij = (B.rho_s * V - rho_f * V) * gmag;
-                const double gap = 0.1 * B.R;
+        // outputs, then the rigid-body update of free circles (Eqs. 37, 39-42):
+        // collision forces from the positions before any body moves, one body per thread
+        BodyDev* bodies = S.bodies;
+        if (tid < G.nbody) {
+            BodyDev& Bd = bodies[G.body[tid]];
+            Bd.F[0] = body_out[tid][0];
+            Bd.F[1] = body_out[tid][1];
+            Bd.T = body_out[tid][2];
+            Bd.resid = body_out[tid][3];
+            Bd.maxslip = body_out[tid][4];
+            double fx = 0.0, fy = 0.0;
+            if (Bd.kind == BODY_FREE) {
+                const double gmag = sqrt(S.gravity[0] * S.gravity[0] + S.gravity[1] * S.gravity[1]);
+                const double V = M_PI * Bd.R * Bd.R;
+                const double cij = (Bd.rho_s * V - S.rho0 * V) * gmag;  // buoyancy-reduced weight
+                const double gap = 0.1 * Bd.R;                          // xi = 0.05 D
                 for (int c = 0; c < G.nbody; ++c) {
                     const BodyDev& O = bodies[G.body[c]];
-                    if (c == b || O.kind != BODY_FREE) continue;
-                    collision_force(B.xc[0], B.xc[1], O.xc[0], O.xc[1], B.R, O.R, cij, gap, Fc[b][0], Fc[b][1]);
+                    if (c == tid || O.kind != BODY_FREE) continue;
+                    collision_force(Bd.xc[0], Bd.xc[1], O.xc[0], O.xc[1], Bd.R, O.R, cij, gap, fx, fy);
                 }
-                const double mir[4][2] = {{-1.0 - B.xc[0], B.xc[1]},
-                                          {2.0 * S.nx - 1.0 - B.xc[0], B.xc[1]},
-                                          {B.xc[0], -1.0 - B.xc[1]},
-                                          {B.xc[0], 2.0 * S.ny - 1.0 - B.xc[1]}};
-                for (int w = 0; w < 4; ++w) {
-                    if (S.bc[w] != BC_WALL && S.bc[w] != BC_FREESLIP) continue;
-                    collision_force(B.xc[0], B.xc[1], mir[w][0], mir[w][1], B.R, B.R, cij, gap, Fc[b][0],
-                                    Fc[b][1]);
-                }
+                // walls act through mirror particles of the same radius; walls sit half
+                // a spacing outside the first and last nodes
+                if (S.bc[SIDE_W] == BC_WALL || S.bc[SIDE_W] == BC_FREESLIP)
+                    collision_force(Bd.xc[0], Bd.xc[1], -1.0 - Bd.xc[0], Bd.xc[1], Bd.R, Bd.R, cij, gap, fx, fy);
+                if (S.bc[SIDE_E] == BC_WALL || S.bc[SIDE_E] == BC_FREESLIP)
+                    collision_force(Bd.xc[0], Bd.xc[1], 2.0 * S.nx - 1.0 - Bd.xc[0], Bd.xc[1], Bd.R, Bd.R, cij, gap,
+                                    fx, fy);
+                if (S.bc[SIDE_S] == BC_WALL || S.bc[SIDE_S] == BC_FREESLIP)
+                    collision_force(Bd.xc[0], Bd.xc[1], Bd.xc[0], -1.0 - Bd.xc[1], Bd.R, Bd.R, cij, gap, fx, fy);
+                if (S.bc[SIDE_N] == BC_WALL || S.bc[SIDE_N] == BC_FREESLIP)
+                    collision_force(Bd.xc[0], Bd.xc[1], Bd.xc[0], 2.0 * S.ny - 1.0 - Bd.xc[1], Bd.R, Bd.R, cij, gap,
+                                    fx, fy);
             }
-            for (int b = 0; b < G.nbody; ++b) {
-                BodyDev& B = bodies[G.body[b]];
-                if (B.kind != BODY_FREE) continue;
-                const double V = M_PI * B.R * B.R, Ms = B.rho_s * V, Is = 0.5 * Ms * B.R * B.R;
-                const double Ftx = B.F[0] + rho_f * V * (B.U[0] - B.Uprev[0]) + Fc[b][0] + (Ms - rho_f * V) * S.gravity[0];
-                const double Fty = B.F[1] + rho_f * V * (B.U[1] - B.Uprev[1]) + Fc[b][1] + (Ms - rho_f * V) * S.gravity[1];
-                const double Tt = B.T + (rho_f / B.rho_s) * Is * (B.omega - B.omega_prev);
-                B.xc[0] += B.U[0] + 0.5 * Ftx / Ms;
-                B.xc[1] += B.U[1] + 0.5 * Fty / Ms;
-                B.theta += B.omega + 0.5 * Tt / Is;
-                B.Uprev[0] = B.U[0];
-                B.Uprev[1] = B.U[1];
-                B.omega_prev = B.omega;
-                B.U[0] += Ftx / Ms;
-                B.U[1] += Fty / Ms;
-                B.omega += Tt / Is;
+            body_out[tid][0] = fx;
+            body_out[tid][1] = fy;
+        }
+        __syncthreads();
+        if (tid < G.nbody) {
+            BodyDev& Bd = bodies[G.body[tid]];
+            if (Bd.kind == BODY_FREE) {
+                const double rho_f = S.rho0;
+                const double V = M_PI * Bd.R * Bd.R, Ms = Bd.rho_s * V, Is = 0.5 * Ms * Bd.R * Bd.R;
+                const double Ftx = Bd.F[0] + rho_f * V * (Bd.U[0] - Bd.Uprev[0]) + body_out[tid][0] + (Ms - rho_f * V) * S.gravity[0];
+                const double Fty = Bd.F[1] + rho_f * V * (Bd.U[1] - Bd.Uprev[1]) + body_out[tid][1] + (Ms - rho_f * V) * S.gravity[1];
+                const double Tt = Bd.T + (rho_f / Bd.rho_s) * Is * (Bd.omega - Bd.omega_prev);
+                // Eq. 42 advances positions with the level-n velocities, Eq. 41 the velocities
+                Bd.xc[0] += Bd.U[0] + 0.5 * Ftx / Ms;
+                Bd.xc[1] += Bd.U[1] + 0.5 * Fty / Ms;
+                Bd.theta += Bd.omega + 0.5 * Tt / Is;
+                Bd.Uprev[0] = Bd.U[0];
+                Bd.Uprev[1] = Bd.U[1];
+                Bd.omega_prev = Bd.omega;
+                Bd.U[0] += Ftx / Ms;
+                Bd.U[1] += Fty / Ms;
+                Bd.omega += Tt / Is;
             }
         }
         __syncthreads();
         // regenerate the markers of free circles for the next step
         for (int g = tid; g < M; g += NT) {
             int body;
-            const int mi = marker_index(S, G, g, body);
+            const int mi = lookup(L, g, body);
             const BodyDev& B = S.bodies[body];
             if (B.kind != BODY_FREE) continue;
             const int l = mi - B.m0;
@@ -786,10 +904,10 @@ __global__ void k_set_eq(const SimDev* sim, int sw, const double* rho, const dou
 
 // ---------------------------------------------------------------- launchers
 
-template <typename T, int TX, int TY, int RPT>
+template <typename T, int TX, int TY, int RPT, bool NTMP>
 static hipError_t sweep_t(const SimDev* sims, const int4* tiles, const BatchHeader* hdr, int ntiles, int grid,
                           int parity, hipStream_t st) {
-    hipLaunchKernelGGL((k_sweep<T, TX, TY, RPT>), dim3(grid), dim3(TX, TY), 0, st, sims, tiles, hdr, ntiles,
+    hipLaunchKernelGGL((k_sweep<T, TX, TY, RPT, NTMP>), dim3(grid), dim3(TX, TY), 0, st, sims, tiles, hdr, ntiles,
                        parity);
     return hipGetLastError();
 }
@@ -798,12 +916,18 @@ template <typename T>
 static hipError_t sweep_tt(int tiling, const SimDev* sims, const int4* tiles, const BatchHeader* hdr, int ntiles,
                            int grid, int parity, hipStream_t st) {
     switch (tiling) {
-        case 0: return sweep_t<T, 64, 4, 1>(sims, tiles, hdr, ntiles, grid, parity, st);
-        case 1: return sweep_t<T, 64, 4, 2>(sims, tiles, hdr, ntiles, grid, parity, st);
-        case 2: return sweep_t<T, 128, 2, 2>(sims, tiles, hdr, ntiles, grid, parity, st);
-        case 3: return sweep_t<T, 256, 1, 2>(sims, tiles, hdr, ntiles, grid, parity, st);
-        case 4: return sweep_t<T, 256, 1, 4>(sims, tiles, hdr, ntiles, grid, parity, st);
-        case 5: return sweep_t<T, 64, 4, 4>(sims, tiles, hdr, ntiles, grid, parity, st);
+        case 0: return sweep_t<T, 64, 4, 1, false>(sims, tiles, hdr, ntiles, grid, parity, st);
+        case 1: return sweep_t<T, 64, 4, 2, false>(sims, tiles, hdr, ntiles, grid, parity, st);
+        case 2: return sweep_t<T, 128, 2, 2, false>(sims, tiles, hdr, ntiles, grid, parity, st);
+        case 3: return sweep_t<T, 256, 1, 2, false>(sims, tiles, hdr, ntiles, grid, parity, st);
+        case 4: return sweep_t<T, 256, 1, 4, false>(sims, tiles, hdr, ntiles, grid, parity, st);
+        case 5: return sweep_t<T, 64, 4, 4, false>(sims, tiles, hdr, ntiles, grid, parity, st);
+        case 6: return sweep_t<T, 64, 4, 1, true>(sims, tiles, hdr, ntiles, grid, parity, st);
+        case 7: return sweep_t<T, 64, 4, 2, true>(sims, tiles, hdr, ntiles, grid, parity, st);
+        case 8: return sweep_t<T, 128, 2, 2, true>(sims, tiles, hdr, ntiles, grid, parity, st);
+        case 9: return sweep_t<T, 256, 1, 2, true>(sims, tiles, hdr, ntiles, grid, parity, st);
+        case 10: return sweep_t<T, 256, 1, 4, true>(sims, tiles, hdr, ntiles, grid, parity, st);
+        case 11: return sweep_t<T, 64, 4, 4, true>(sims, tiles, hdr, ntiles, grid, parity, st);
         default: return hipErrorInvalidValue;
     }
 }
@@ -825,16 +949,23 @@ hipError_t launch_boundary(bool f64, const SimDev* sims, const int2* items, cons
     return hipGetLastError();
 }
 
-hipError_t launch_ib(bool f64, const SimDev* sims, GroupDev* groups, const BatchHeader* hdr, int ngroups, int grid,
-                     int parity, hipStream_t stream) {
-    if (grid <= 0) return hipSuccess;
-    if (f64)
-        hipLaunchKernelGGL((k_ib<double, kIbThreads>), dim3(grid), dim3(kIbThreads), 0, stream, sims, groups, hdr,
-                           ngroups, parity);
-    else
-        hipLaunchKernelGGL((k_ib<float, kIbThreads>), dim3(grid), dim3(kIbThreads), 0, stream, sims, groups, hdr,
-                           ngroups, parity);
+template <typename T, int NT, int MPT>
+static hipError_t ib_t(const SimDev* sims, GroupDev* groups, const BatchHeader* hdr, int ngroups, int grid,
+                       int parity, hipStream_t stream) {
+    hipLaunchKernelGGL((k_ib<T, NT, MPT>), dim3(grid), dim3(NT), 0, stream, sims, groups, hdr, ngroups, parity);
     return hipGetLastError();
+}
+
+hipError_t launch_ib(bool f64, int max_markers, const SimDev* sims, GroupDev* groups, const BatchHeader* hdr,
+                     int ngroups, int grid, int parity, hipStream_t stream) {
+    if (grid <= 0) return hipSuccess;
+    if (max_markers > kMaxGroupMarkers) return hipErrorInvalidValue;
+    // each thread keeps up to MPT markers' running sums in registers
+    if (f64)
+        return max_markers <= 4 * 512 ? ib_t<double, 512, 4>(sims, groups, hdr, ngroups, grid, parity, stream)
+                                      : ib_t<double, 512, 8>(sims, groups, hdr, ngroups, grid, parity, stream);
+    return max_markers <= 2 * 1024 ? ib_t<float, 1024, 2>(sims, groups, hdr, ngroups, grid, parity, stream)
+                                   : ib_t<float, 1024, 4>(sims, groups, hdr, ngroups, grid, parity, stream);
 }
 
 hipError_t launch_advance(SimDev* sims, const BatchHeader* hdr, int nsims, hipStream_t stream) {

@@ -9,13 +9,11 @@ namespace lbmib {
 
 // Sweep tilings: threads along x, thread rows per block, lattice rows per thread.
 struct Tiling {
-    int tx, ty, rpt;
+    int tx, ty, rpt, nontemporal;
 };
-constexpr int kNumTilings = 6;
+constexpr int kNumTilings = 12;
 extern const Tiling kTilings[kNumTilings];
 
-// Threads per correction workgroup (the results do not depend on it).
-constexpr int kIbThreads = 1024;
 // Entries sorted in LDS when a plan is rebuilt on the device (16 per marker).
 constexpr int kMaxDynEntries = 8192;
 constexpr int kMaxGroupMarkers = 4096;
@@ -29,7 +27,9 @@ hipError_t launch_sweep(bool f64, int tiling, const SimDev* sims, const int4* ti
                         hipStream_t stream);
 hipError_t launch_boundary(bool f64, const SimDev* sims, const int2* items, const BatchHeader* hdr,
                            int nitems, int grid, int parity, hipStream_t stream);
-hipError_t launch_ib(bool f64, const SimDev* sims, GroupDev* groups, const BatchHeader* hdr,
+// max_markers: the largest group's marker count (selects how many markers
+// each thread carries; the results do not depend on it).
+hipError_t launch_ib(bool f64, int max_markers, const SimDev* sims, GroupDev* groups, const BatchHeader* hdr,
                      int ngroups, int grid, int parity, hipStream_t stream);
 hipError_t launch_advance(SimDev* sims, const BatchHeader* hdr, int nsims, hipStream_t stream);
 // Field and population I/O of one simulation (state `sw` = AA state now).

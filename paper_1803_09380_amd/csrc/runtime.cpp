@@ -93,6 +93,7 @@ struct lbm_sim {
     int tiling = kTileDefault;
     int64_t steps = 0;
     int mcount = 0;
+    int max_group = 0;  // markers of the largest body group
     lbm_batch* batch = nullptr;
     ~lbm_sim() {
         for (Group* g : grp) delete g;
@@ -110,6 +111,7 @@ struct lbm_batch {
     DevBuf d_sims, d_tiles, d_bc, d_groups, d_hdr;
     size_t cap_sims = 0, cap_tiles = 0, cap_bc = 0, cap_groups = 0;
     int ntiles = 0, nbc = 0, ngroups = 0;
+    int max_group = 0;
     int tiling = kTileDefault;
     int grid_sweep = 0, grid_bc = 0, grid_ib = 0;
     hipGraphExec_t graph1 = nullptr, graphK = nullptr;
@@ -388,7 +390,11 @@ lbm_status rebuild_ib(lbm_sim* s) {
         }
     }
     std::vector<GroupDev> gd;
-    for (Group* g : s->grp) gd.push_back(g->d);
+    s->max_group = 0;
+    for (Group* g : s->grp) {
+        gd.push_back(g->d);
+        s->max_group = std::max(s->max_group, g->d.M);
+    }
     HIPS(s, upload(s->groups, gd, st));
     HIPS(s, hipMemcpyAsync(s->desc.p, &s->h, sizeof(SimDev), hipMemcpyHostToDevice, st));
     HIPS(s, hipStreamSynchronize(st));
@@ -591,7 +597,7 @@ lbm_status lbm_step(lbm_sim* s, int32_t nsteps) {
         const int parity = s->h.swapped;
         HIPS(s, launch_sweep(s->f64, s->tiling, d, (const int4*)s->tiles.p, nullptr, ntiles, ntiles, parity, s->stream));
         if (nbc) HIPS(s, launch_boundary(s->f64, d, (const int2*)s->bcitems.p, nullptr, nbc, nbc, parity, s->stream));
-        if (ng) HIPS(s, launch_ib(s->f64, d, (GroupDev*)s->groups.p, nullptr, ng, ng, parity, s->stream));
+        if (ng) HIPS(s, launch_ib(s->f64, s->max_group, d, (GroupDev*)s->groups.p, nullptr, ng, ng, parity, s->stream));
         s->h.swapped ^= 1;
         s->h.steps_done += 1;
         ++s->steps;
@@ -817,6 +823,11 @@ lbm_status upload_tables(lbm_batch* b) {
             groups.push_back(d);
         }
     }
+    // largest groups first: the persistent correction kernel starts the long ones early
+    std::stable_sort(groups.begin(), groups.end(), [](const GroupDev& a, const GroupDev& c) { return a.M > c.M; });
+    int max_group = groups.empty() ? 0 : groups.front().M;
+    bool variant_changed = (max_group > 2048) != (b->max_group > 2048);
+    b->max_group = max_group;
     BatchHeader h{};
     h.nsims = (int)sims.size();
     h.nbc = (int)bc.size();
@@ -836,7 +847,7 @@ lbm_status upload_tables(lbm_batch* b) {
         HIPB(b, b->d_hdr.alloc(sizeof(BatchHeader)));
         grew = true;
     }
-    if (grew) drop_graphs(b);
+    if (grew || variant_changed) drop_graphs(b);
     if (!sims.empty()) HIPB(b, hipMemcpyAsync(b->d_sims.p, sims.data(), sizeof(SimDev) * sims.size(), hipMemcpyHostToDevice, b->stream));
     if (!tiles.empty()) HIPB(b, hipMemcpyAsync(b->d_tiles.p, tiles.data(), sizeof(int4) * tiles.size(), hipMemcpyHostToDevice, b->stream));
     if (!bc.empty()) HIPB(b, hipMemcpyAsync(b->d_bc.p, bc.data(), sizeof(int2) * bc.size(), hipMemcpyHostToDevice, b->stream));
@@ -855,7 +866,7 @@ hipError_t enqueue_steps(lbm_batch* b, int n) {
     for (int t = 0; t < n; ++t) {
         hipError_t e = launch_sweep(b->f64, b->tiling, sims, (const int4*)b->d_tiles.p, hdr, 0, b->grid_sweep, -1, b->stream);
         if (e == hipSuccess) e = launch_boundary(b->f64, sims, (const int2*)b->d_bc.p, hdr, 0, b->grid_bc, -1, b->stream);
-        if (e == hipSuccess) e = launch_ib(b->f64, sims, (GroupDev*)b->d_groups.p, hdr, 0, b->grid_ib, -1, b->stream);
+        if (e == hipSuccess) e = launch_ib(b->f64, b->max_group, sims, (GroupDev*)b->d_groups.p, hdr, 0, b->grid_ib, -1, b->stream);
         if (e == hipSuccess) e = launch_advance((SimDev*)b->d_sims.p, hdr, 0, b->stream);
         if (e != hipSuccess) return e;
     }
@@ -900,7 +911,7 @@ lbm_status lbm_batch_create(int32_t precision, size_t budget, void* hip_stream, 
     }
     const int ncu = num_cus(b->device);
     b->grid_sweep = ncu * 8;
-    b->grid_bc = ncu;
+    b->grid_bc = ncu * 8;
     b->grid_ib = ncu * 2;
     if (upload_tables(b) != LBM_OK) {
         lbm_batch_destroy(b);
@@ -1096,7 +1107,7 @@ lbm_status lbm_batch_profile(lbm_batch* b, int32_t nsteps, double ms[4], int64_t
         HIPB(b, hipEventRecord(ev[1], b->stream));
         HIPB(b, launch_boundary(b->f64, sims, (const int2*)b->d_bc.p, hdr, 0, b->grid_bc, -1, b->stream));
         HIPB(b, hipEventRecord(ev[2], b->stream));
-        HIPB(b, launch_ib(b->f64, sims, (GroupDev*)b->d_groups.p, hdr, 0, b->grid_ib, -1, b->stream));
+        HIPB(b, launch_ib(b->f64, b->max_group, sims, (GroupDev*)b->d_groups.p, hdr, 0, b->grid_ib, -1, b->stream));
         HIPB(b, hipEventRecord(ev[3], b->stream));
         HIPB(b, launch_advance((SimDev*)b->d_sims.p, hdr, 0, b->stream));
         HIPB(b, hipEventRecord(ev[4], b->stream));
