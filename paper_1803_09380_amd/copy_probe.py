@@ -19,10 +19,17 @@ def main():
     n = args.mib * (1 << 20) // 4
     x = torch.ones(n, dtype=torch.float32, device="cuda")
     y = torch.empty_like(x)
+    y.copy_(x)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
     for _ in range(args.reps):
         y.copy_(x)
+    e1.record()
     torch.cuda.synchronize()
-    print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4, "reps": args.reps}))
+    ms = e0.elapsed_time(e1) / args.reps
+    print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4, "reps": args.reps,
+                      "ms_per_copy": ms, "gbs_read_plus_write": 2 * n * 4 / (ms * 1e-3) / 1e9}))
 
 
 if __name__ == "__main__":

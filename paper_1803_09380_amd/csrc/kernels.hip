@@ -358,40 +358,154 @@ __device__ void build_plan(const SimDev& S, const GroupDev& G, unsigned long lon
     __syncthreads();
 }
 
-// Deterministic FP64 sum over [0, n) of v(i) for any block size: fixed
-// 256-wide tree per chunk, chunks added in order by thread 0.
-template <int NT, typename F>
-__device__ double det_sum(int n, F v, double* red) {
+// Faster rebuild for groups whose stencils fit a small bounding box (the usual
+// case for moving particles): count stencil entries per box cell in LDS, scan
+// the counts into band-node indices and entry offsets, drop each entry into
+// its cell's run, and order every run by marker (insertion sort of a handful of
+// entries) so the plan is the same whatever order the atomics came in.
+// Returns false, without touching the plan, when the box is too large.
+constexpr int kBinCells = 16384;
+
+template <int NT>
+__device__ bool build_plan_binned(const SimDev& S, const GroupDev& G, int* lds, int* scan_tmp, int* bbox,
+                                  int& nband_out, int& nent_out) {
     const int tid = threadIdx.x;
-    double acc = 0.0;
-    for (int c0 = 0; c0 < n; c0 += 256) {
-        if (tid < 256) red[tid] = (c0 + tid < n) ? v(c0 + tid) : 0.0;
-        __syncthreads();
-        for (int s = 128; s > 0; s >>= 1) {
-            if (tid < s) red[tid] += red[tid + s];
-            __syncthreads();
-        }
-        if (tid == 0) acc += red[0];
-        __syncthreads();
+    const int M = G.M, NE = 16 * M;
+    if (tid == 0) {
+        bbox[0] = 0x7fffffff;
+        bbox[1] = 0x7fffffff;
+        bbox[2] = -0x7fffffff;
+        bbox[3] = -0x7fffffff;
     }
-    return acc;  // valid on thread 0
+    __syncthreads();
+    int lx = 0x7fffffff, ly = 0x7fffffff, hx = -0x7fffffff, hy = -0x7fffffff;
+    for (int g = tid; g < M; g += NT) {
+        int body;
+        const int mi = marker_index(S, G, g, body);
+        const int fx = (int)floor(S.mX[mi]) - 1, fy = (int)floor(S.mY[mi]) - 1;
+        lx = min(lx, fx);
+        ly = min(ly, fy);
+        hx = max(hx, fx + 3);
+        hy = max(hy, fy + 3);
+    }
+    if (lx <= hx) {
+        atomicMin(&bbox[0], lx);
+        atomicMin(&bbox[1], ly);
+        atomicMax(&bbox[2], hx);
+        atomicMax(&bbox[3], hy);
+    }
+    __syncthreads();
+    const int x0 = bbox[0], y0 = bbox[1];
+    const long W = (long)bbox[2] - x0 + 1, H = (long)bbox[3] - y0 + 1;
+    if (M == 0 || W * H > kBinCells || (S.px && W >= S.nx) || (S.py && H >= S.ny)) return false;
+    const int ncell = (int)(W * H);
+    int* count = lds;              // per box cell: entries, then band-node index
+    int* start = lds + kBinCells;  // per box cell: first entry, then fill position
+    for (int c = tid; c < ncell; c += NT) count[c] = 0;
+    for (int e = tid; e < NE; e += NT) G.mnode[e] = -1;
+    __syncthreads();
+    for (int e = tid; e < NE; e += NT) {
+        const int g = e >> 4, sl = e & 15;
+        int body;
+        const int mi = marker_index(S, G, g, body);
+        const int ux = (int)floor(S.mX[mi]) - 1 + (sl & 3), uy = (int)floor(S.mY[mi]) - 1 + (sl >> 2);
+        const int x = wrap(ux, S.nx, S.px), y = wrap(uy, S.ny, S.py);
+        if (x < 0 || x >= S.nx || y < 0 || y >= S.ny) continue;
+        atomicAdd(&count[(uy - y0) * (int)W + (ux - x0)], 1);
+    }
+    __syncthreads();
+    // scan cells (contiguous segment per thread): entry offsets and band-node indices
+    const int per = (ncell + NT - 1) / NT;
+    const int c0 = tid * per, c1 = min(ncell, c0 + per);
+    int ecnt = 0, ncnt = 0;
+    for (int c = c0; c < c1; ++c) {
+        ecnt += count[c];
+        ncnt += count[c] > 0;
+    }
+    int etotal, ntotal;
+    int ebase = block_scan<NT>(ecnt, scan_tmp, &etotal);
+    int nbase = block_scan<NT>(ncnt, scan_tmp, &ntotal);
+    for (int c = c0; c < c1; ++c) {
+        const int n = count[c];
+        start[c] = ebase;
+        if (n > 0) {
+            const int ux = x0 + c % (int)W, uy = y0 + c / (int)W;
+            const int x = wrap(ux, S.nx, S.px), y = wrap(uy, S.ny, S.py);
+            G.node_cell[nbase] = y * S.nx + x;
+            G.node_run[nbase] = ebase;
+            count[c] = nbase;
+            ++nbase;
+        }
+        ebase += n;
+    }
+    if (tid == 0) G.node_run[ntotal] = etotal;
+    __syncthreads();
+    for (int e = tid; e < NE; e += NT) {
+        const int g = e >> 4, sl = e & 15;
+        int body;
+        const int mi = marker_index(S, G, g, body);
+        const int ux = (int)floor(S.mX[mi]) - 1 + (sl & 3), uy = (int)floor(S.mY[mi]) - 1 + (sl >> 2);
+        const int x = wrap(ux, S.nx, S.px), y = wrap(uy, S.ny, S.py);
+        if (x < 0 || x >= S.nx || y < 0 || y >= S.ny) continue;
+        const int slot = atomicAdd(&start[(uy - y0) * (int)W + (ux - x0)], 1);
+        G.ent[slot] = e;  // e = 16 * marker + (ky << 2 | kx)
+    }
+    __syncthreads();
+    for (int k = tid; k < ntotal; k += NT) {
+        const int e0 = G.node_run[k], e1 = G.node_run[k + 1];
+        for (int a = e0 + 1; a < e1; ++a) {
+            const int v = G.ent[a];
+            int b = a - 1;
+            while (b >= e0 && G.ent[b] > v) {
+                G.ent[b + 1] = G.ent[b];
+                --b;
+            }
+            G.ent[b + 1] = v;
+        }
+        for (int e = e0; e < e1; ++e) G.mnode[G.ent[e]] = k;
+    }
+    nband_out = ntotal;
+    nent_out = etotal;
+    __syncthreads();
+    return true;
 }
 
-template <int NT, typename F>
-__device__ double det_max(int n, F v, double* red) {
+// Deterministic FP64 reduction over markers [0, n) of a body: five sums and
+// one maximum of per-marker values v[l * 5 + c] (c = 0..3 summed, c = 4 maxed
+// with the |dm|^2 slot kept at index 3).  Markers are taken 256 at a time; each
+// 64-marker slice is reduced by a fixed xor-shuffle tree, the four slices and
+// the chunks are added in order by thread 0.  The order depends only on the
+// marker index, never on the workgroup size.
+__device__ void body_reduce(int n, const double* v, double* part, double out[5]) {
     const int tid = threadIdx.x;
-    double acc = 0.0;
+    double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     for (int c0 = 0; c0 < n; c0 += 256) {
-        if (tid < 256) red[tid] = (c0 + tid < n) ? v(c0 + tid) : 0.0;
-        __syncthreads();
-        for (int s = 128; s > 0; s >>= 1) {
-            if (tid < s) red[tid] = fmax(red[tid], red[tid + s]);
-            __syncthreads();
+        if (tid < 256) {
+            const int l = c0 + tid;
+            double x[5];
+#pragma unroll
+            for (int c = 0; c < 5; ++c) x[c] = l < n ? v[l * 5 + c] : 0.0;
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) {
+#pragma unroll
+                for (int c = 0; c < 4; ++c) x[c] += __shfl_xor(x[c], off, 64);
+                x[4] = fmax(x[4], __shfl_xor(x[4], off, 64));
+            }
+            if ((tid & 63) == 0)
+#pragma unroll
+                for (int c = 0; c < 5; ++c) part[(tid >> 6) * 5 + c] = x[c];
         }
-        if (tid == 0) acc = fmax(acc, red[0]);
+        __syncthreads();
+        if (tid == 0)
+            for (int w = 0; w < 4; ++w) {
+#pragma unroll
+                for (int c = 0; c < 4; ++c) acc[c] += part[w * 5 + c];
+                acc[4] = fmax(acc[4], part[w * 5 + 4]);
+            }
         __syncthreads();
     }
-    return acc;
+#pragma unroll
+    for (int c = 0; c < 5; ++c) out[c] = acc[c];  // valid on thread 0
 }
 
 // Eq. 39 with the numerator gap read as xi.
@@ -412,7 +526,7 @@ __device__ void collision_force(double xi0, double xi1, double xj0, double xj1, 
 // placed here while they fit; the rest stay in the group's global scratch
 // (generic pointers serve both).  A plan rebuilt on the device first uses the
 // arena for its sort keys.
-constexpr int kIbArenaBytes = 144 * 1024;
+constexpr int kIbArenaBytes = 148 * 1024;
 
 struct Bump {
     char* base;
@@ -445,52 +559,108 @@ __device__ __forceinline__ int lookup(const GroupLookup& L, int g, int& body) {
     return L.m0[b] + g - L.gbase[b];
 }
 
+// Typed accessors: LDS-resident arrays are read with ds_read, the others with
+// global loads (never the slower flat path of generic pointers).
+#define LBM_AS3 __attribute__((address_space(3)))
+#define LBM_AS1 __attribute__((address_space(1)))
+template <bool LDS, typename T>
+__device__ __forceinline__ T ldm(const T* p) {
+    if constexpr (LDS)
+        return *(const LBM_AS3 T*)(p);
+    else
+        return *(const LBM_AS1 T*)(p);
+}
+template <bool LDS, typename T>
+__device__ __forceinline__ void stm(T* p, T v) {
+    if constexpr (LDS)
+        *(LBM_AS3 T*)(p) = v;
+    else
+        *(LBM_AS1 T*)(p) = v;
+}
+
+// native vectors for 8- and 16-byte LDS/global accesses
 template <typename T>
-struct BandView {
-    T *rho, *jx, *jy;          // band (rho, j)
-    T* wt;                     // per-marker weights
-    const int* run;            // band run offsets
-    const unsigned short* mn16;  // stencil node indices in LDS (0xFFFF: dropped), or null
-    const int* mn32;           // the same in global memory
-    const T* phi;              // per-marker phi_x[4], phi_y[4]
-    const unsigned short* ent16;  // stencil entry -> marker in LDS, or null
-    const int* ent32;          // packed entries in global memory
-    const T* entD;             // delta weight of every entry
+using nv2 = T __attribute__((ext_vector_type(2)));
+template <typename T>
+using nv4 = T __attribute__((ext_vector_type(4)));
+
+// Where a group's working arrays live for one step.  CORE (band (rho, j),
+// per-marker weights, run offsets, 16-bit stencil indices) in LDS or global;
+// EXTRA (phi, 16-bit entries, entry weights) in LDS or global.
+template <typename T>
+struct Band {
+    T* node;                 // band records rho, 1/rho, j_x, j_y (rho is fixed during the sweeps)
+    T* wt;                   // per-marker weights ds * dm of the current sweep (2 per marker)
+    T* tot;                  // per-marker totals of the sweeps for the final spread (5 per marker)
+    unsigned short* run16;   // band run offsets (LDS) ...
+    const int* run32;        // ... or global
+    unsigned short* mn16;
+    const int* mn32;
+    T* phi;
+    unsigned short* ent16;
+    const int* ent32;
+    T* entD;
 };
 
 // marker pass: interpolate (rho, j, jj/rho) at marker g from the band,
 // deviation dm = rho* U - j*, dPi = rho* U U - Pi*
-template <typename T>
-__device__ __forceinline__ void interp_marker(const BandView<T>& B, int g, T U, T V, T& dmx, T& dmy, T& dpxx,
+template <typename T, bool CORE, bool EXTRA>
+__device__ __forceinline__ void interp_marker(const Band<T> B, int g, T U, T V, T& dmx, T& dmy, T& dpxx,
                                               T& dpxy, T& dpyy, T& rs) {
+    // stencil node indices and weights: vector reads, no branches, so all
+    // sixteen band records below are requested at once (a dropped node reads
+    // record 0 with weight 0, which adds exact zeros)
     int k[16];
-    T px[4], py[4];
-    if (B.mn16) {
+    if constexpr (CORE) {
+        const nv4<unsigned>* m = reinterpret_cast<const nv4<unsigned>*>(B.mn16 + g * 16);
+        const nv4<unsigned> a = ldm<true>(m), c = ldm<true>(m + 1);
+        const unsigned w[8] = {a.x, a.y, a.z, a.w, c.x, c.y, c.z, c.w};
 #pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            const int v = B.mn16[g * 16 + q];
-            k[q] = v == 0xFFFF ? -1 : v;
+        for (int q = 0; q < 8; ++q) {
+            const int lo = (int)(w[q] & 0xffffu), hi = (int)(w[q] >> 16);
+            k[2 * q] = lo == 0xFFFF ? -1 : lo;
+            k[2 * q + 1] = hi == 0xFFFF ? -1 : hi;
         }
     } else {
+        const nv4<int>* m = reinterpret_cast<const nv4<int>*>(B.mn32 + g * 16);
 #pragma unroll
-        for (int q = 0; q < 16; ++q) k[q] = B.mn32[g * 16 + q];
+        for (int q = 0; q < 4; ++q) {
+            const nv4<int> v = ldm<false>(m + q);
+            k[4 * q] = v.x;
+            k[4 * q + 1] = v.y;
+            k[4 * q + 2] = v.z;
+            k[4 * q + 3] = v.w;
+        }
     }
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        px[q] = B.phi[g * 8 + q];
-        py[q] = B.phi[g * 8 + 4 + q];
+    T px[4], py[4];
+    {
+        const nv4<T>* ph = reinterpret_cast<const nv4<T>*>(B.phi + g * 8);
+        const nv4<T> a = ldm<EXTRA>(ph), c = ldm<EXTRA>(ph + 1);
+        px[0] = a.x;
+        px[1] = a.y;
+        px[2] = a.z;
+        px[3] = a.w;
+        py[0] = c.x;
+        py[1] = c.y;
+        py[2] = c.z;
+        py[3] = c.w;
     }
+    const nv4<T>* node = reinterpret_cast<const nv4<T>*>(B.node);
     T r = 0, jx = 0, jy = 0, pxx = 0, pxy = 0, pyy = 0;
+    // two stencil rows at a time: eight band records requested together
 #pragma unroll
-    for (int ky = 0; ky < 4; ++ky) {
-        if (ky == 2) __builtin_amdgcn_sched_barrier(0);
+    for (int half = 0; half < 2; ++half) {
+        nv4<T> nd[8];
 #pragma unroll
-        for (int kx = 0; kx < 4; ++kx) {
-            const int n = k[ky * 4 + kx];
-            if (n < 0) continue;
-            const T D = px[kx] * py[ky];
-            const T nr = B.rho[n], nx = B.jx[n], ny = B.jy[n];
-            const T inv = T(1) / nr;
+        for (int q = 0; q < 8; ++q) {
+            const int kk = k[half * 8 + q];
+            nd[q] = ldm<CORE>(node + (kk < 0 ? 0 : kk));
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int kx = q & 3, ky = half * 2 + (q >> 2);
+            const T D = k[half * 8 + q] < 0 ? T(0) : px[kx] * py[ky];
+            const T nr = nd[q].x, inv = nd[q].y, nx = nd[q].z, ny = nd[q].w;
             r += D * nr;
             jx += D * nx;
             jy += D * ny;
@@ -498,6 +668,7 @@ __device__ __forceinline__ void interp_marker(const BandView<T>& B, int g, T U, 
             pxy += D * nx * ny * inv;
             pyy += D * ny * ny * inv;
         }
+        __builtin_amdgcn_sched_barrier(0);
     }
     dmx = r * U - jx;
     dmy = r * V - jy;
@@ -509,30 +680,248 @@ __device__ __forceinline__ void interp_marker(const BandView<T>& B, int g, T U, 
 
 // node pass: sum over the node's stencil entries (ascending marker) of
 // D * w[stride * g + c] for C components
-template <typename T, int C>
-__device__ __forceinline__ void spread_node(const BandView<T>& B, int stride, int e0, int e1, T out[C]) {
+template <typename T, bool CORE, bool EXTRA, int C>
+__device__ __forceinline__ void spread_node(const Band<T> B, const T* w, int stride, int e0, int e1, T out[C]) {
 #pragma unroll
     for (int c = 0; c < C; ++c) out[c] = T(0);
-    const T* w = B.wt;
     int e = e0;
     for (; e + 4 <= e1; e += 4) {
         int g[4];
         T d[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            g[q] = B.ent16 ? (int)B.ent16[e + q] : (B.ent32[e + q] >> 4);
-            d[q] = B.entD[e + q];
+            if constexpr (EXTRA)
+                g[q] = ldm<true>(B.ent16 + e + q);
+            else
+                g[q] = ldm<false>(B.ent32 + e + q) >> 4;
+            d[q] = ldm<EXTRA>(B.entD + e + q);
         }
+        T wv[4][C];
 #pragma unroll
         for (int q = 0; q < 4; ++q)
 #pragma unroll
-            for (int c = 0; c < C; ++c) out[c] += d[q] * w[stride * g[q] + c];
+            for (int c = 0; c < C; ++c) wv[q][c] = ldm<CORE>(w + stride * g[q] + c);
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int c = 0; c < C; ++c) out[c] += d[q] * wv[q][c];
     }
     for (; e < e1; ++e) {
-        const int g = B.ent16 ? (int)B.ent16[e] : (B.ent32[e] >> 4);
-        const T d = B.entD[e];
+        int g;
+        if constexpr (EXTRA)
+            g = ldm<true>(B.ent16 + e);
+        else
+            g = ldm<false>(B.ent32 + e) >> 4;
+        const T d = ldm<EXTRA>(B.entD + e);
 #pragma unroll
-        for (int c = 0; c < C; ++c) out[c] += d * w[stride * g + c];
+        for (int c = 0; c < C; ++c) out[c] += d * ldm<CORE>(w + stride * g + c);
+    }
+}
+
+#ifdef LBMIB_TRACE_IB
+// phase timestamps (100 MHz wall clock) of the first group, for profiling builds only
+__device__ long long lbmib_ib_trace[64];
+#define IB_MARK(k)                                  \
+    do {                                            \
+        if (gi == 0 && tid == 0) {                  \
+            lbmib_ib_trace[(k)] = wall_clock64();   \
+            lbmib_ib_trace[32 + (k)] = clock64();   \
+        }                                           \
+    } while (0)
+#else
+#define IB_MARK(k) \
+    do {           \
+    } while (0)
+#endif
+
+template <typename T, bool CORE>
+__device__ __forceinline__ int run_at(const Band<T>& B, int k) {
+    if constexpr (CORE)
+        return ldm<true>(B.run16 + k);
+    else
+        return ldm<false>(B.run32 + k);
+}
+
+// Steps 2-6 of a group's correction (gather, N sweeps on (rho, j), final
+// spread and correction of the nine populations) for one placement of its
+// working arrays.
+template <typename T, int NT, int MPT, bool CORE, bool EXTRA>
+__device__ __forceinline__ void correct_group(const SimDev& S, const GroupDev& G, const GroupLookup& L, Band<T> B,
+                                              const T* phi_g, const T* entD_g, int M, int nband, int nent, int sw,
+                                              int gi) {
+    const int tid = threadIdx.x;
+    if constexpr (CORE) {
+        // one pass issues every copy's loads together
+        const int len = max(max(nband + 1, 16 * M), EXTRA ? max(8 * M, nent) : 0);
+        for (int i = tid; i < len; i += NT) {
+            if (i <= nband) stm<true>(B.run16 + i, (unsigned short)G.node_run[i]);
+            if (i < 16 * M) {
+                const int v = G.mnode[i];
+                stm<true>(B.mn16 + i, v < 0 ? (unsigned short)0xFFFF : (unsigned short)v);
+            }
+            if constexpr (EXTRA) {
+                if (i < 8 * M) stm<true>(B.phi + i, phi_g[i]);
+                if (i < nent) {
+                    stm<true>(B.ent16 + i, (unsigned short)(G.ent[i] >> 4));
+                    stm<true>(B.entD + i, entD_g[i]);
+                }
+            }
+        }
+    }
+    IB_MARK(2);
+    // gather (rho, j) of the band from the post-stream populations, four nodes
+    // per thread in flight
+    const T rho_base = T(S.rho_base);
+    for (int k0 = tid; k0 < nband; k0 += 4 * NT) {
+        T h[4][9];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int k = k0 + u * NT;
+            if (k < nband) {
+                const int cell = G.node_cell[k];
+                const int x = cell % S.nx, y = cell / S.nx;
+#pragma unroll
+                for (int i = 0; i < 9; ++i) h[u][i] = *loc<T>(S, i, x, y, sw);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int k = k0 + u * NT;
+            if (k < nband) {
+                const T* f = h[u];
+                const T Ssum = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
+                const T rho = rho_base + Ssum;
+                nv4<T> rec;
+                rec.x = rho;
+                rec.y = T(1) / rho;
+                rec.z = (f[1] + f[5] + f[8]) - (f[3] + f[6] + f[7]);
+                rec.w = (f[2] + f[5] + f[6]) - (f[4] + f[7] + f[8]);
+                stm<CORE>(reinterpret_cast<nv4<T>*>(B.node) + k, rec);
+            }
+        }
+    }
+    // per-thread markers: velocities, arc lengths and running sums over the
+    // sweeps in registers (storage precision; the reductions over markers are FP64)
+    T mu[MPT], mv[MPT], mds[MPT];
+    T acc[MPT][5];
+#pragma unroll
+    for (int q = 0; q < MPT; ++q) {
+        const int g = tid + q * NT;
+        mu[q] = mv[q] = mds[q] = T(0);
+        if (g < M) {
+            int body;
+            const int mi = lookup(L, g, body);
+            mu[q] = T(S.mU[mi]);
+            mv[q] = T(S.mV[mi]);
+            mds[q] = T(S.mds[mi]);
+        }
+#pragma unroll
+        for (int c = 0; c < 5; ++c) acc[q][c] = T(0);
+    }
+    __syncthreads();
+    IB_MARK(3);
+    const int iters = S.ib_iters;
+    for (int n = 0; n < iters; ++n) {
+#pragma unroll
+        for (int q = 0; q < MPT; ++q) {
+            const int g = tid + q * NT;
+            if (g < M) {
+                T dmx, dmy, dpxx, dpxy, dpyy, rs;
+                interp_marker<T, CORE, EXTRA>(B, g, mu[q], mv[q], dmx, dmy, dpxx, dpxy, dpyy, rs);
+                acc[q][0] += dmx;
+                acc[q][1] += dmy;
+                acc[q][2] += dpxx;
+                acc[q][3] += dpxy;
+                acc[q][4] += dpyy;
+                stm<CORE>(B.wt + 2 * g, mds[q] * dmx);
+                stm<CORE>(B.wt + 2 * g + 1, mds[q] * dmy);
+            }
+        }
+        __syncthreads();
+        if (n < 2) IB_MARK(28 + n);
+        // Eqs. 26-27 on the momentum: j(x) += sum_l D(x - X_l) ds_l dm_l, ascending l
+        for (int k = tid; k < nband; k += NT) {
+            T inc[2];
+            spread_node<T, CORE, EXTRA, 2>(B, B.wt, 2, run_at<T, CORE>(B, k), run_at<T, CORE>(B, k + 1), inc);
+            nv2<T>* jp = reinterpret_cast<nv2<T>*>(B.node + 4 * k + 2);
+            nv2<T> j = ldm<CORE>(jp);
+            j.x += inc[0];
+            j.y += inc[1];
+            stm<CORE>(jp, j);
+        }
+        __syncthreads();
+        IB_MARK(4 + (n < 20 ? n : 19));
+    }
+    // mismatch left after the sweeps, per-marker force and torque
+#pragma unroll
+    for (int q = 0; q < MPT; ++q) {
+        const int g = tid + q * NT;
+        if (g < M) {
+            int body;
+            const int mi = lookup(L, g, body);
+            T dmx, dmy, dpxx, dpxy, dpyy, rs;
+            interp_marker<T, CORE, EXTRA>(B, g, mu[q], mv[q], dmx, dmy, dpxx, dpxy, dpyy, rs);
+            const double ds = S.mds[mi];
+            const BodyDev& Bd = S.bodies[body];
+            const double Fx = -ds * (double)acc[q][0], Fy = -ds * (double)acc[q][1];
+            const double r2 = (double)dmx * (double)dmx + (double)dmy * (double)dmy;
+            double* mr = G.m_red + g * 5;
+            mr[0] = Fx;
+            mr[1] = Fy;
+            mr[2] = (S.mX[mi] - Bd.xc[0]) * Fy - (S.mY[mi] - Bd.xc[1]) * Fx;
+            mr[3] = r2;
+            mr[4] = sqrt(r2) / (double)rs;
+        }
+    }
+    // totals of the sweeps for the final spread (they may reuse the band's LDS)
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < MPT; ++q) {
+        const int g = tid + q * NT;
+        if (g < M) {
+            int body;
+            const double ds = S.mds[lookup(L, g, body)];
+#pragma unroll
+            for (int c = 0; c < 5; ++c) stm<CORE>(B.tot + g * 5 + c, T(ds * (double)acc[q][c]));
+        }
+    }
+    __syncthreads();
+    IB_MARK(24);
+    // final spread of sum_n delta f (Eq. 28 is linear in dm and dPi) and correction
+    // (Eq. 27), two nodes per thread in flight
+    for (int k0 = tid; k0 < nband; k0 += 2 * NT) {
+        T t5[2][5];
+        T* p[2][9];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int k = k0 + u * NT;
+            if (k < nband) {
+                spread_node<T, CORE, EXTRA, 5>(B, B.tot, 5, run_at<T, CORE>(B, k), run_at<T, CORE>(B, k + 1), t5[u]);
+                const int cell = G.node_cell[k];
+                const int x = cell % S.nx, y = cell / S.nx;
+#pragma unroll
+                for (int i = 0; i < 9; ++i) p[u][i] = loc<T>(S, i, x, y, sw);
+            }
+        }
+        T f[2][9];
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+            if (k0 + u * NT < nband)
+#pragma unroll
+                for (int i = 0; i < 9; ++i) f[u][i] = *p[u][i];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            if (k0 + u * NT >= nband) continue;
+            const T* t = t5[u];
+            const T trB = T(1.5) * (t[2] + t[4]);
+#pragma unroll
+            for (int i = 0; i < 9; ++i) {
+                const T ex = T(ex_of(i)), ey = T(ey_of(i));
+                const T d = weight_of<T>(i) *
+                            (T(3) * (ex * t[0] + ey * t[1]) + T(4.5) * (ex * ex * t[2] + T(2) * ex * ey * t[3] + ey * ey * t[4]) - trB);
+                *p[u][i] = f[u][i] + d;
+            }
+        }
     }
 }
 
@@ -541,10 +930,11 @@ __global__ void __launch_bounds__(NT)
     k_ib(const SimDev* __restrict__ sims, GroupDev* __restrict__ groups, const BatchHeader* __restrict__ hdr,
          int ngroups_arg, int parity) {
     __shared__ __align__(16) char arena[kIbArenaBytes];
-    __shared__ double red[256];
+    __shared__ double part[4 * 5];
     __shared__ int scan_tmp[NT];
     __shared__ double body_out[8][5];
     __shared__ GroupLookup L;
+    __shared__ int bbox[4];
     const int ngroups = hdr ? hdr->ngroups : ngroups_arg;
     const int tid = threadIdx.x;
     for (int gi = blockIdx.x; gi < ngroups; gi += gridDim.x) {
@@ -554,7 +944,9 @@ __global__ void __launch_bounds__(NT)
         const int sw = 1 - (parity >= 0 ? parity : S.swapped);
         const int M = G.M;
         int nband = G.nband, nent = G.nent;
-        if (G.dynamic) build_plan<NT>(S, G, reinterpret_cast<unsigned long long*>(arena), scan_tmp, nband, nent);
+        IB_MARK(0);
+        if (G.dynamic && !build_plan_binned<NT>(S, G, reinterpret_cast<int*>(arena), scan_tmp, bbox, nband, nent))
+            build_plan<NT>(S, G, reinterpret_cast<unsigned long long*>(arena), scan_tmp, nband, nent);
         if (tid == 0) {
             int base = 0;
             L.nb = G.nbody;
@@ -593,167 +985,71 @@ __global__ void __launch_bounds__(NT)
             __syncthreads();
             if (tid == 0 && !G.dynamic) G.flags[0] = 1;
         }
-        // LDS placement (the same decisions on every thread)
-        Bump bump{arena, 0};
-        BandView<T> B;
-        B.rho = reinterpret_cast<T*>(bump.take((long)nband * sizeof(T)));
-        B.jx = reinterpret_cast<T*>(bump.take((long)nband * sizeof(T)));
-        B.jy = reinterpret_cast<T*>(bump.take((long)nband * sizeof(T)));
-        if (!B.rho || !B.jx || !B.jy) {
-            B.rho = reinterpret_cast<T*>(G.node_rho);
-            B.jx = reinterpret_cast<T*>(G.node_jx);
-            B.jy = reinterpret_cast<T*>(G.node_jy);
-        }
-        T* wt_l = reinterpret_cast<T*>(bump.take(5L * M * sizeof(T)));
-        B.wt = wt_l ? wt_l : reinterpret_cast<T*>(G.m_wtot);
-        int* run_l = reinterpret_cast<int*>(bump.take(4L * (nband + 1)));
-        B.run = run_l ? run_l : G.node_run;
-        unsigned short* mn_l =
-            nband < 0xFFFF ? reinterpret_cast<unsigned short*>(bump.take(2L * 16 * M)) : nullptr;
-        B.mn16 = mn_l;
+        IB_MARK(1);
+        // placement of the working arrays (the same decision on every thread)
+        Bump bump;
+        bump.base = arena;
+        bump.off = 0;
+        Band<T> B;
+        T* lnode = reinterpret_cast<T*>(bump.take(4L * nband * sizeof(T)));
+        T* lwt = reinterpret_cast<T*>(bump.take(2L * M * sizeof(T)));
+        // the totals of the final spread reuse the band records when they fit there
+        T* ltot = 5L * M <= 4L * nband ? lnode : reinterpret_cast<T*>(bump.take(5L * M * sizeof(T)));
+        unsigned short* lrun = reinterpret_cast<unsigned short*>(bump.take(2L * (nband + 1)));
+        unsigned short* lmn = reinterpret_cast<unsigned short*>(bump.take(2L * 16 * M));
+        const bool core = nband < 0xFFFF && nent < 0xFFFF && lnode && lwt && ltot && lrun && lmn;
+        T* lphi = core ? reinterpret_cast<T*>(bump.take(8L * M * sizeof(T))) : nullptr;
+        unsigned short* lent = core ? reinterpret_cast<unsigned short*>(bump.take(2L * nent)) : nullptr;
+        T* lentD = core ? reinterpret_cast<T*>(bump.take((long)nent * sizeof(T))) : nullptr;
+        const bool extra = core && lphi && lent && lentD;
         B.mn32 = G.mnode;
-        T* phi_l = reinterpret_cast<T*>(bump.take(8L * M * sizeof(T)));
-        B.phi = phi_l ? phi_l : phi_g;
-        unsigned short* ent_l = reinterpret_cast<unsigned short*>(bump.take(2L * nent));
-        T* entD_l = ent_l ? reinterpret_cast<T*>(bump.take((long)nent * sizeof(T))) : nullptr;
-        if (!entD_l) ent_l = nullptr;
-        B.ent16 = ent_l;
         B.ent32 = G.ent;
-        B.entD = entD_l ? entD_l : entD_g;
-        if (run_l)
-            for (int k = tid; k <= nband; k += NT) run_l[k] = G.node_run[k];
-        if (mn_l)
-            for (int e = tid; e < 16 * M; e += NT) {
-                const int v = G.mnode[e];
-                mn_l[e] = v < 0 ? (unsigned short)0xFFFF : (unsigned short)v;
-            }
-        if (phi_l)
-            for (int e = tid; e < 8 * M; e += NT) phi_l[e] = phi_g[e];
-        if (ent_l)
-            for (int e = tid; e < nent; e += NT) {
-                ent_l[e] = (unsigned short)(G.ent[e] >> 4);
-                entD_l[e] = entD_g[e];
-            }
-        // gather (rho, j) of the band from the post-stream populations
-        const T rho_base = T(S.rho_base);
-        for (int k = tid; k < nband; k += NT) {
-            const int cell = G.node_cell[k];
-            const int x = cell % S.nx, y = cell / S.nx;
-            T h[9];
-#pragma unroll
-            for (int i = 0; i < 9; ++i) h[i] = *loc<T>(S, i, x, y, sw);
-            const T Ssum = ((h[0] + h[1]) + (h[2] + h[3])) + ((h[4] + h[5]) + (h[6] + h[7])) + h[8];
-            B.rho[k] = rho_base + Ssum;
-            B.jx[k] = (h[1] + h[5] + h[8]) - (h[3] + h[6] + h[7]);
-            B.jy[k] = (h[2] + h[5] + h[6]) - (h[4] + h[7] + h[8]);
+        B.run32 = G.node_run;
+        if (core) {
+            B.node = lnode;
+            B.wt = lwt;
+            B.tot = ltot;
+            B.run16 = lrun;
+            B.mn16 = lmn;
+        } else {
+            B.node = reinterpret_cast<T*>(G.node4);
+            B.wt = reinterpret_cast<T*>(G.m_wtot);
+            B.tot = reinterpret_cast<T*>(G.m_wtot);
+            B.run16 = nullptr;
+            B.mn16 = nullptr;
         }
-        // per-thread markers: velocities, arc lengths and running sums over the
-        // sweeps in registers (storage precision; the reductions over markers are FP64)
-        T mu[MPT], mv[MPT], mds[MPT];
-        T acc[MPT][5];
-#pragma unroll
-        for (int q = 0; q < MPT; ++q) {
-            const int g = tid + q * NT;
-            mu[q] = mv[q] = mds[q] = T(0);
-            if (g < M) {
-                int body;
-                const int mi = lookup(L, g, body);
-                mu[q] = T(S.mU[mi]);
-                mv[q] = T(S.mV[mi]);
-                mds[q] = T(S.mds[mi]);
-            }
-#pragma unroll
-            for (int c = 0; c < 5; ++c) acc[q][c] = T(0);
+        if (extra) {
+            B.phi = lphi;
+            B.ent16 = lent;
+            B.entD = lentD;
+        } else {
+            B.phi = phi_g;
+            B.ent16 = nullptr;
+            B.entD = entD_g;
         }
+        if (extra)
+            correct_group<T, NT, MPT, true, true>(S, G, L, B, phi_g, entD_g, M, nband, nent, sw, gi);
+        else if (core)
+            correct_group<T, NT, MPT, true, false>(S, G, L, B, phi_g, entD_g, M, nband, nent, sw, gi);
+        else
+            correct_group<T, NT, MPT, false, false>(S, G, L, B, phi_g, entD_g, M, nband, nent, sw, gi);
         __syncthreads();
-        const int iters = S.ib_iters;
-        for (int n = 0; n < iters; ++n) {
-#pragma unroll
-            for (int q = 0; q < MPT; ++q) {
-                const int g = tid + q * NT;
-                if (g < M) {
-                    T dmx, dmy, dpxx, dpxy, dpyy, rs;
-                    interp_marker<T>(B, g, mu[q], mv[q], dmx, dmy, dpxx, dpxy, dpyy, rs);
-                    acc[q][0] += dmx;
-                    acc[q][1] += dmy;
-                    acc[q][2] += dpxx;
-                    acc[q][3] += dpxy;
-                    acc[q][4] += dpyy;
-                    B.wt[2 * g] = mds[q] * dmx;
-                    B.wt[2 * g + 1] = mds[q] * dmy;
-                }
-                // keep the markers' loads from piling up in registers
-                __builtin_amdgcn_sched_barrier(0);
-            }
-            __syncthreads();
-            // Eqs. 26-27 on the momentum: j(x) += sum_l D(x - X_l) ds_l dm_l, ascending l
-            for (int k = tid; k < nband; k += NT) {
-                T inc[2];
-                spread_node<T, 2>(B, 2, B.run[k], B.run[k + 1], inc);
-                B.jx[k] += inc[0];
-                B.jy[k] += inc[1];
-            }
-            __syncthreads();
-        }
-        // mismatch left after the sweeps, per-marker force and torque; totals for the final spread
-#pragma unroll
-        for (int q = 0; q < MPT; ++q) {
-            const int g = tid + q * NT;
-            if (g < M) {
-                int body;
-                const int mi = lookup(L, g, body);
-                T dmx, dmy, dpxx, dpxy, dpyy, rs;
-                interp_marker<T>(B, g, mu[q], mv[q], dmx, dmy, dpxx, dpxy, dpyy, rs);
-                const double ds = S.mds[mi];
-                const BodyDev& Bd = S.bodies[body];
-                const double Fx = -ds * (double)acc[q][0], Fy = -ds * (double)acc[q][1];
-                const double r2 = (double)dmx * (double)dmx + (double)dmy * (double)dmy;
-                double* mr = G.m_red + g * 5;
-                mr[0] = Fx;
-                mr[1] = Fy;
-                mr[2] = (S.mX[mi] - Bd.xc[0]) * Fy - (S.mY[mi] - Bd.xc[1]) * Fx;
-                mr[3] = r2;
-                mr[4] = sqrt(r2) / (double)rs;
-#pragma unroll
-                for (int c = 0; c < 5; ++c) B.wt[g * 5 + c] = T(ds * (double)acc[q][c]);
-            }
-        }
-        __syncthreads();
-        // final spread of sum_n delta f (Eq. 28 is linear in dm and dPi) and correction (Eq. 27)
-        for (int k = tid; k < nband; k += NT) {
-            T t5[5];
-            spread_node<T, 5>(B, 5, B.run[k], B.run[k + 1], t5);
-            const int cell = G.node_cell[k];
-            const int x = cell % S.nx, y = cell / S.nx;
-            const T trB = T(1.5) * (t5[2] + t5[4]);
-#pragma unroll
-            for (int i = 0; i < 9; ++i) {
-                const T ex = T(ex_of(i)), ey = T(ey_of(i));
-                const T d = weight_of<T>(i) * (T(3) * (ex * t5[0] + ey * t5[1]) +
-                                               T(4.5) * (ex * ex * t5[2] + T(2) * ex * ey * t5[3] + ey * ey * t5[4]) - trB);
-                T* p = loc<T>(S, i, x, y, sw);
-                *p = *p + d;
-            }
-        }
-        __syncthreads();
+        IB_MARK(25);
         // FP64 reductions per body (order fixed by the marker index)
         for (int b = 0; b < G.nbody; ++b) {
             const int nb = L.gbase[b + 1] - L.gbase[b];
-            const double* mr = G.m_red + L.gbase[b] * 5;
-            double fx = det_sum<NT>(nb, [&](int l) { return mr[l * 5 + 0]; }, red);
-            double fy = det_sum<NT>(nb, [&](int l) { return mr[l * 5 + 1]; }, red);
-            double tq = det_sum<NT>(nb, [&](int l) { return mr[l * 5 + 2]; }, red);
-            double r2 = det_sum<NT>(nb, [&](int l) { return mr[l * 5 + 3]; }, red);
-            double mx = det_max<NT>(nb, [&](int l) { return mr[l * 5 + 4]; }, red);
+            double o[5];
+            body_reduce(nb, G.m_red + L.gbase[b] * 5, part, o);
             if (tid == 0) {
-                body_out[b][0] = fx;
-                body_out[b][1] = fy;
-                body_out[b][2] = tq;
-                body_out[b][3] = sqrt(r2 / nb);
-                body_out[b][4] = mx;
+                body_out[b][0] = o[0];
+                body_out[b][1] = o[1];
+                body_out[b][2] = o[2];
+                body_out[b][3] = sqrt(o[3] / nb);
+                body_out[b][4] = o[4];
             }
         }
         __syncthreads();
+        IB_MARK(26);
         // outputs, then the rigid-body update of free circles (Eqs. 37, 39-42):
         // collision forces from the positions before any body moves, one body per thread
         BodyDev* bodies = S.bodies;
@@ -828,6 +1124,7 @@ __global__ void __launch_bounds__(NT)
             S.mV[mi] = B.U[1] + B.omega * (X - B.xc[0]);
         }
         __syncthreads();
+        IB_MARK(27);
     }
 }
 
@@ -962,10 +1259,10 @@ hipError_t launch_ib(bool f64, int max_markers, const SimDev* sims, GroupDev* gr
     if (max_markers > kMaxGroupMarkers) return hipErrorInvalidValue;
     // each thread keeps up to MPT markers' running sums in registers
     if (f64)
-        return max_markers <= 4 * 512 ? ib_t<double, 512, 4>(sims, groups, hdr, ngroups, grid, parity, stream)
-                                      : ib_t<double, 512, 8>(sims, groups, hdr, ngroups, grid, parity, stream);
-    return max_markers <= 2 * 1024 ? ib_t<float, 1024, 2>(sims, groups, hdr, ngroups, grid, parity, stream)
-                                   : ib_t<float, 1024, 4>(sims, groups, hdr, ngroups, grid, parity, stream);
+        return max_markers <= 8 * 256 ? ib_t<double, 256, 8>(sims, groups, hdr, ngroups, grid, parity, stream)
+                                      : ib_t<double, 256, 16>(sims, groups, hdr, ngroups, grid, parity, stream);
+    return max_markers <= 4 * 512 ? ib_t<float, 512, 4>(sims, groups, hdr, ngroups, grid, parity, stream)
+                                  : ib_t<float, 512, 8>(sims, groups, hdr, ngroups, grid, parity, stream);
 }
 
 hipError_t launch_advance(SimDev* sims, const BatchHeader* hdr, int nsims, hipStream_t stream) {

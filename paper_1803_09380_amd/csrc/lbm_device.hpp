@@ -99,9 +99,8 @@ struct GroupDev {
     int32_t* ent;             // [cap_ent] (group marker << 4) | (ky << 2) | kx
     int32_t* mnode;           // [M * 16] band node of each stencil slot, -1 if dropped
     int32_t* flags;           // [1] device flag: stencil weights of a static plan are current
-    void* node_rho;           // T [cap_nodes] (used when the band does not fit in LDS)
-    void* node_jx;            // T [cap_nodes]
-    void* node_jy;            // T [cap_nodes]
+    void* node4;              // T [cap_nodes * 4]: rho, 1/rho, j_x, j_y of each band node
+                              // (used when the band does not fit in LDS)
     void* ent_D;              // T [cap_ent] delta weight D of every stencil entry
     void* m_phi;              // T [M * 8]: phi_x[4], phi_y[4]
     void* m_wtot;             // T [M * 5]: per-sweep ds*dm (first 2M), then ds * (sum dm, sum dPi)

@@ -72,7 +72,7 @@ struct HostBody {
 // One group's plan and scratch on the device plus its host descriptor.
 struct Group {
     GroupDev d{};
-    DevBuf node_cell, node_run, ent, mnode, flags, node_rho, node_jx, node_jy, ent_D, m_phi, m_wtot, m_acc, m_red;
+    DevBuf node_cell, node_run, ent, mnode, flags, node4, ent_D, m_phi, m_wtot, m_acc, m_red;
 };
 
 }  // namespace
@@ -360,9 +360,7 @@ lbm_status rebuild_ib(lbm_sim* s) {
         HIPS(s, G->mnode.alloc(sizeof(int) * std::max(1, 16 * M)));
         HIPS(s, G->flags.alloc(sizeof(int) * 4));
         HIPS(s, hipMemsetAsync(G->flags.p, 0, sizeof(int) * 4, st));
-        HIPS(s, G->node_rho.alloc(tsz * d.cap_nodes));
-        HIPS(s, G->node_jx.alloc(tsz * d.cap_nodes));
-        HIPS(s, G->node_jy.alloc(tsz * d.cap_nodes));
+        HIPS(s, G->node4.alloc(tsz * 4 * d.cap_nodes));
         HIPS(s, G->ent_D.alloc(tsz * std::max(1, d.cap_ent)));
         HIPS(s, G->m_phi.alloc(tsz * 8 * std::max(1, M)));
         HIPS(s, G->m_wtot.alloc(tsz * 5 * std::max(1, M)));
@@ -373,9 +371,7 @@ lbm_status rebuild_ib(lbm_sim* s) {
         d.ent = (int*)G->ent.p;
         d.mnode = (int*)G->mnode.p;
         d.flags = (int*)G->flags.p;
-        d.node_rho = G->node_rho.p;
-        d.node_jx = G->node_jx.p;
-        d.node_jy = G->node_jy.p;
+        d.node4 = G->node4.p;
         d.ent_D = G->ent_D.p;
         d.m_phi = G->m_phi.p;
         d.m_wtot = G->m_wtot.p;
@@ -729,7 +725,7 @@ size_t lbm_device_bytes(const lbm_sim* s) {
                s->bcitems.bytes + s->groups.bytes;
     for (const Group* g : s->grp)
         b += g->node_cell.bytes + g->node_run.bytes + g->ent.bytes + g->mnode.bytes + g->flags.bytes +
-             g->node_rho.bytes + g->node_jx.bytes + g->node_jy.bytes + g->ent_D.bytes + g->m_phi.bytes +
+             g->node4.bytes + g->ent_D.bytes + g->m_phi.bytes +
              g->m_wtot.bytes + g->m_acc.bytes + g->m_red.bytes;
     return b;
 }
@@ -1121,5 +1117,19 @@ lbm_status lbm_batch_profile(lbm_batch* b, int32_t nsteps, double ms[4], int64_t
     for (int k = 0; k < 5; ++k) (void)hipEventDestroy(ev[k]);
     return LBM_OK;
 }
+
+#ifdef LBMIB_TRACE_IB
+}  // extern "C"
+namespace lbmib {
+extern __device__ long long lbmib_ib_trace[64];
+}
+extern "C" {
+// profiling builds only: phase timestamps of the first body group's last step
+lbm_status lbm_debug_ib_trace(long long* out) {
+    return hipMemcpyFromSymbol(out, HIP_SYMBOL(lbmib::lbmib_ib_trace), sizeof(long long) * 64) == hipSuccess
+               ? LBM_OK
+               : LBM_ERR_DEVICE;
+}
+#endif
 
 }  // extern "C"
