@@ -594,12 +594,13 @@ struct Band {
     T* tot;                  // per-marker totals of the sweeps for the final spread (5 per marker)
     unsigned short* run16;   // band run offsets (LDS) ...
     const int* run32;        // ... or global
-    unsigned short* mn16;
-    const int* mn32;
+    unsigned short* rows;    // per marker: first band node of each stencil row (LDS);
+                             // 0xFFFF when the row's nodes are not 4 consecutive band nodes
+    const int* mn32;         // per marker: band node of each of the 16 stencil slots (global)
     T* phi;
-    unsigned short* ent16;
-    const int* ent32;
-    T* entD;
+    unsigned short* ent16;   // packed entries (marker << 4 | ky << 2 | kx) in LDS; D from phi
+    const int* ent32;        // the same in global memory ...
+    T* entD;                 // ... with the weights D in global memory
 };
 
 // marker pass: interpolate (rho, j, jj/rho) at marker g from the band,
@@ -612,14 +613,17 @@ __device__ __forceinline__ void interp_marker(const Band<T> B, int g, T U, T V, 
     // record 0 with weight 0, which adds exact zeros)
     int k[16];
     if constexpr (CORE) {
-        const nv4<unsigned>* m = reinterpret_cast<const nv4<unsigned>*>(B.mn16 + g * 16);
-        const nv4<unsigned> a = ldm<true>(m), c = ldm<true>(m + 1);
-        const unsigned w[8] = {a.x, a.y, a.z, a.w, c.x, c.y, c.z, c.w};
+        const nv2<unsigned> rv = ldm<true>(reinterpret_cast<const nv2<unsigned>*>(B.rows + g * 4));
+        const int rs[4] = {(int)(rv.x & 0xffffu), (int)(rv.x >> 16), (int)(rv.y & 0xffffu), (int)(rv.y >> 16)};
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const int lo = (int)(w[q] & 0xffffu), hi = (int)(w[q] >> 16);
-            k[2 * q] = lo == 0xFFFF ? -1 : lo;
-            k[2 * q + 1] = hi == 0xFFFF ? -1 : hi;
+        for (int ky = 0; ky < 4; ++ky) {
+            if (rs[ky] != 0xFFFF) {
+#pragma unroll
+                for (int kx = 0; kx < 4; ++kx) k[ky * 4 + kx] = rs[ky] + kx;
+            } else {  // a row cut by a lattice edge or wrapped across a periodic one
+#pragma unroll
+                for (int kx = 0; kx < 4; ++kx) k[ky * 4 + kx] = ldm<false>(B.mn32 + g * 16 + ky * 4 + kx);
+            }
         }
     } else {
         const nv4<int>* m = reinterpret_cast<const nv4<int>*>(B.mn32 + g * 16);
@@ -690,11 +694,14 @@ __device__ __forceinline__ void spread_node(const Band<T> B, const T* w, int str
         T d[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            if constexpr (EXTRA)
-                g[q] = ldm<true>(B.ent16 + e + q);
-            else
+            if constexpr (EXTRA) {
+                const int p = ldm<true>(B.ent16 + e + q);
+                g[q] = p >> 4;
+                d[q] = ldm<true>(B.phi + g[q] * 8 + (p & 3)) * ldm<true>(B.phi + g[q] * 8 + 4 + ((p >> 2) & 3));
+            } else {
                 g[q] = ldm<false>(B.ent32 + e + q) >> 4;
-            d[q] = ldm<EXTRA>(B.entD + e + q);
+                d[q] = ldm<false>(B.entD + e + q);
+            }
         }
         T wv[4][C];
 #pragma unroll
@@ -708,11 +715,15 @@ __device__ __forceinline__ void spread_node(const Band<T> B, const T* w, int str
     }
     for (; e < e1; ++e) {
         int g;
-        if constexpr (EXTRA)
-            g = ldm<true>(B.ent16 + e);
-        else
+        T d;
+        if constexpr (EXTRA) {
+            const int p = ldm<true>(B.ent16 + e);
+            g = p >> 4;
+            d = ldm<true>(B.phi + g * 8 + (p & 3)) * ldm<true>(B.phi + g * 8 + 4 + ((p >> 2) & 3));
+        } else {
             g = ldm<false>(B.ent32 + e) >> 4;
-        const T d = ldm<EXTRA>(B.entD + e);
+            d = ldm<false>(B.entD + e);
+        }
 #pragma unroll
         for (int c = 0; c < C; ++c) out[c] += d * ldm<CORE>(w + stride * g + c);
     }
@@ -752,19 +763,28 @@ __device__ __forceinline__ void correct_group(const SimDev& S, const GroupDev& G
     const int tid = threadIdx.x;
     if constexpr (CORE) {
         // one pass issues every copy's loads together
-        const int len = max(max(nband + 1, 16 * M), EXTRA ? max(8 * M, nent) : 0);
+        const int len = max(max(nband + 1, M), EXTRA ? max(8 * M, nent) : 0);
         for (int i = tid; i < len; i += NT) {
             if (i <= nband) stm<true>(B.run16 + i, (unsigned short)G.node_run[i]);
-            if (i < 16 * M) {
-                const int v = G.mnode[i];
-                stm<true>(B.mn16 + i, v < 0 ? (unsigned short)0xFFFF : (unsigned short)v);
+            if (i < M) {
+                int m[16];
+#pragma unroll
+                for (int q = 0; q < 16; ++q) m[q] = G.mnode[i * 16 + q];
+                unsigned short r[4];
+#pragma unroll
+                for (int ky = 0; ky < 4; ++ky) {
+                    const int a = m[ky * 4];
+                    const bool reg = a >= 0 && m[ky * 4 + 1] == a + 1 && m[ky * 4 + 2] == a + 2 && m[ky * 4 + 3] == a + 3;
+                    r[ky] = reg ? (unsigned short)a : (unsigned short)0xFFFF;
+                }
+                nv2<unsigned> rv;
+                rv.x = (unsigned)r[0] | ((unsigned)r[1] << 16);
+                rv.y = (unsigned)r[2] | ((unsigned)r[3] << 16);
+                stm<true>(reinterpret_cast<nv2<unsigned>*>(B.rows + i * 4), rv);
             }
             if constexpr (EXTRA) {
                 if (i < 8 * M) stm<true>(B.phi + i, phi_g[i]);
-                if (i < nent) {
-                    stm<true>(B.ent16 + i, (unsigned short)(G.ent[i] >> 4));
-                    stm<true>(B.entD + i, entD_g[i]);
-                }
+                if (i < nent) stm<true>(B.ent16 + i, (unsigned short)G.ent[i]);
             }
         }
     }
@@ -996,12 +1016,11 @@ __global__ void __launch_bounds__(NT)
         // the totals of the final spread reuse the band records when they fit there
         T* ltot = 5L * M <= 4L * nband ? lnode : reinterpret_cast<T*>(bump.take(5L * M * sizeof(T)));
         unsigned short* lrun = reinterpret_cast<unsigned short*>(bump.take(2L * (nband + 1)));
-        unsigned short* lmn = reinterpret_cast<unsigned short*>(bump.take(2L * 16 * M));
-        const bool core = nband < 0xFFFF && nent < 0xFFFF && lnode && lwt && ltot && lrun && lmn;
+        unsigned short* lrows = reinterpret_cast<unsigned short*>(bump.take(2L * 4 * M));
+        const bool core = nband < 0xFFFF && nent < 0xFFFF && lnode && lwt && ltot && lrun && lrows;
         T* lphi = core ? reinterpret_cast<T*>(bump.take(8L * M * sizeof(T))) : nullptr;
         unsigned short* lent = core ? reinterpret_cast<unsigned short*>(bump.take(2L * nent)) : nullptr;
-        T* lentD = core ? reinterpret_cast<T*>(bump.take((long)nent * sizeof(T))) : nullptr;
-        const bool extra = core && lphi && lent && lentD;
+        const bool extra = core && lphi && lent && M < 4096;
         B.mn32 = G.mnode;
         B.ent32 = G.ent;
         B.run32 = G.node_run;
@@ -1010,18 +1029,18 @@ __global__ void __launch_bounds__(NT)
             B.wt = lwt;
             B.tot = ltot;
             B.run16 = lrun;
-            B.mn16 = lmn;
+            B.rows = lrows;
         } else {
             B.node = reinterpret_cast<T*>(G.node4);
             B.wt = reinterpret_cast<T*>(G.m_wtot);
             B.tot = reinterpret_cast<T*>(G.m_wtot);
             B.run16 = nullptr;
-            B.mn16 = nullptr;
+            B.rows = nullptr;
         }
         if (extra) {
             B.phi = lphi;
             B.ent16 = lent;
-            B.entD = lentD;
+            B.entD = nullptr;
         } else {
             B.phi = phi_g;
             B.ent16 = nullptr;
