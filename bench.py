@@ -28,6 +28,37 @@ METRIC = "D2Q9+IB MLUPS (FP32 batched vs FP64 plain) at stated error; p50/p99 so
 HBM_PEAK_GBS = 8000.0
 SWEEP_BYTES_F32 = 72  # 9 loads + 9 stores of 4 bytes per cell update
 SWEEP_BYTES_F64 = 144
+# HBM counter figures of the sweep on this set, per tiling, from two
+# `rocprofv3 --pmc` passes (FETCH_SIZE, WRITE_SIZE) scaled by the same
+# counters' reading for a plain copy of known size; they hold only for the
+# kernel source they were taken on (its SHA-256 is recorded with them).
+PMC_FILE = os.path.join(ROOT, "profiles", "k_sweep_f32_batched256_pmc.txt")
+KERNEL_SRC = os.path.join(ROOT, "paper_1803_09380_amd", "csrc", "kernels.hip")
+
+
+def sweep_traffic(tiling):
+    """HBM bytes per sweep launch for `tiling` from the committed counter
+    summary, or None when there is none for this tiling or the kernel source
+    has changed since the counters were taken."""
+    import hashlib
+    try:
+        lines = open(PMC_FILE).read().splitlines()
+        sha = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    rec, rows = {}, {}
+    for ln in lines:
+        f = ln.split()
+        if not f or f[0].startswith("#") or f[0].startswith("|"):
+            continue
+        if f[0] == "tiling" and len(f) >= 6:
+            rows[int(f[1])] = (float(f[3]), float(f[5]))
+        elif len(f) == 2:
+            rec[f[0]] = f[1]
+    if rec.get("kernel_source_sha256") != sha or tiling not in rows:
+        return None
+    fk, wk = rows[tiling]
+    return (fk * float(rec["fetch_factor"]) + wk * float(rec["write_factor"])) * 1024.0
 
 
 def _oracle_from_case(po, case):
@@ -117,6 +148,32 @@ def fp64_leg(args, cases, lbmib, wl, torch, np):
     return f64_mlups, f32_sample_mlups, err
 
 
+def mrt_leg(args, cases, lbmib, wl, torch, tiling):
+    """The same set with the MRT collision (rates of the validation cases) in
+    every member: batched throughput and the sweep's per-launch duration."""
+    sims = [lbmib.Sim.from_case(c, precision=lbmib.F32_SHIFTED, mrt_s=wl.mrt_rates(c["tau"])) for c in cases]
+    b = lbmib.Batch(lbmib.F32_SHIFTED)
+    for s in sims:
+        assert b.admit(s)
+    b.set_tiling(tiling)
+    b.step(10)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.step(args.mrt_steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms, pcells = b.profile(10)
+    b.close()
+    del sims
+    cells = sum(c["nx"] * c["ny"] for c in cases)
+    sweep_ms = ms[0] / 10
+    ach = SWEEP_BYTES_F32 * pcells / (sweep_ms * 1e-3) / 1e9
+    return {"value": round(cells * args.mrt_steps / wall / 1e6, 1), "unit": "MLUPS", "steps": args.mrt_steps,
+            "sweep_launch_ms": round(sweep_ms, 4), "sweep_achieved_gbs": round(ach, 1),
+            "sweep_frac": round(ach / HBM_PEAK_GBS, 4), "tiling": tiling,
+            "rates": "s_e 1.1, s_eps 1.25, s_q 1.8, s_nu 1/tau"}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -132,6 +189,8 @@ def main():
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default sweep tiling instead of timing the candidates on the set")
     ap.add_argument("--tiling", type=int, default=-1)
+    ap.add_argument("--mrt-steps", type=int, default=100,
+                    help="timed steps of the same set with the MRT collision (0: skip)")
     ap.add_argument("--serve-requests", type=int, default=24)
     ap.add_argument("--serve-steps", type=int, default=2000)
     ap.add_argument("--only-batch", action="store_true",
@@ -151,6 +210,7 @@ def main():
         args.no_cpu = True
         args.fp64_sample = 0
         args.serve_requests = 0
+        args.mrt_steps = 0
     cpu = None
     if not args.no_cpu:
         cpu = run_cpu_baseline(cases, args.cpu_seconds)
@@ -186,6 +246,8 @@ def main():
     ms, pcells = batch.profile(args.profile_steps)
     sweep_ms = ms[0] / args.profile_steps
     achieved = SWEEP_BYTES_F32 * pcells / (sweep_ms * 1e-3) / 1e9
+    in_use = tiling if tiling >= 0 else batch.tiling
+    traffic = sweep_traffic(in_use)
     unstable = 0
     for s in sims:
         try:
@@ -199,13 +261,17 @@ def main():
     del sims
     torch.cuda.synchronize()
 
+    # ---- the same set with the MRT collision
+    mrt = None
+    if args.mrt_steps > 0:
+        mrt = mrt_leg(args, cases, lbmib, wl, torch, in_use)
+
     # ---- FP64 plain path: members of the same set one at a time, direct launches
     f64_mlups = f32_sample_mlups = err = None
     f64_updates, f64_time = 0, 0.0
     if args.fp64_sample > 0:
         f64_mlups, f32_sample_mlups, err = fp64_leg(args, cases, lbmib, wl, torch, np)
 
-    # ---- served stream: Poisson arrivals of settling requests, continuous batching
     # ---- served stream: Poisson arrivals of settling requests, continuous batching
     serving = None
     if args.serve_requests > 0:
@@ -240,11 +306,13 @@ def main():
                         "channel 20Dx10D with D 16..64, Re 10..100), FP32 shifted populations, "
                         "10 correction sweeps per step" % args.sims,
             "seed": args.seed, "sims": args.sims, "cells": cells, "markers": markers,
-            "tiling": tiling,
+            "tiling": in_use,
         },
         "roofline": {
             "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": None if traffic is None else int(traffic),
+            "traffic_over_algorithmic": None if traffic is None else round(traffic / (SWEEP_BYTES_F32 * pcells), 3),
             "kernel": "k_sweep<float>", "launch_ms": round(sweep_ms, 4),
             "bytes_per_cell": SWEEP_BYTES_F32, "cells_per_launch": pcells,
             "step_split_ms": {"sweep": round(ms[0] / args.profile_steps, 4),
@@ -258,6 +326,7 @@ def main():
             "fp32_batched_same_sample": round(f32_sample_mlups, 1),
             "speedup_fp32_batched": round(f32_sample_mlups / f64_mlups, 2)},
         "accuracy": None if err is None else {"fp32_vs_fp64_velocity_rel_l2": err, "case": "couette64, 2000 steps"},
+        "mrt": mrt,
         "unstable_members": unstable,
         "serving": serving,
         "cpu_baseline": cpu,

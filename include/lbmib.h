@@ -4,8 +4,8 @@
  * of Tao, He, Chen and Huang (arXiv:1803.09380).
  *
  * One time step of a simulation, all on the GPU:
- *   1. fused D2Q9 BGK collision and streaming (Eqs. 1, 3, 7; BGK is the MRT
- *      operator of Eq. 2 with S = I/tau), in place with the AA access pattern;
+ *   1. fused D2Q9 collision (BGK, or the MRT operator of Eq. 2) and streaming
+ *      (Eqs. 1, 3, 7), in place with the AA access pattern;
  *   2. boundary rules for populations entering through the lattice edge
  *      (half-way bounce-back as in Fig. 2, specular free slip, velocity inlet by
  *      non-equilibrium extrapolation as in Sec. 3.2, zero-gradient outflow);
@@ -79,7 +79,17 @@ typedef struct {
     double u_init[2];     /* initial uniform velocity: f = f^eq(rho0, u_init)      */
     int32_t ib_iters;     /* correction sweeps per step, N >= 0 (about 10)         */
     double gravity[2];    /* gravitational acceleration acting on free bodies      */
+    int32_t collision;    /* lbm_collision                                         */
+    double mrt_s[9];      /* LBM_MRT: relaxation rates of Eq. 6 in the moment order
+                             of Eq. 5 (rho, e, epsilon, j_x, q_x, j_y, q_y, p_xx,
+                             p_xy); the conserved ones (0, 3, 5) are not used      */
 } lbm_params;
+
+typedef enum {
+    LBM_BGK = 0, /* f' = f - (f - f^eq)/tau                                      */
+    LBM_MRT = 1  /* Eq. 2 with the moment matrix of Eq. 5 and the rates of Eq. 6;
+                    with every rate 1/tau it equals LBM_BGK                        */
+} lbm_collision;
 
 typedef enum {
     IB_FIXED = 0, /* markers at given positions with given (or rigid-motion) velocities */
@@ -189,6 +199,8 @@ size_t lbm_batch_bytes(const lbm_batch* b);
 lbm_status lbm_batch_autotune(lbm_batch* b, int32_t trials, int32_t* chosen);
 /* Force a tiling index (0 .. lbm_tiling_count()-1). */
 lbm_status lbm_batch_set_tiling(lbm_batch* b, int32_t tiling);
+/* Index of the tiling the batch launches with now. */
+int32_t lbm_batch_get_tiling(const lbm_batch* b);
 int32_t lbm_tiling_count(void);
 /* Describe tiling k: threads along x, rows per block, rows per thread. */
 lbm_status lbm_tiling_info(int32_t k, int32_t* tx, int32_t* ty, int32_t* rows_per_thread);

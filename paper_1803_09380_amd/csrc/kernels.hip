@@ -61,6 +61,66 @@ __device__ __forceinline__ void bgk(T h[9], T rho_base, T omega, uint32_t& bad) 
     }
 }
 
+// MRT collision of Eq. 2 with the moment matrix M of Eq. 5 (rows: rho, e,
+// epsilon, j_x, q_x, j_y, q_y, p_xx, p_xy) and the diagonal rates of Eq. 6.
+// The rows of M are orthogonal, so M^-1 = M^T diag(1/|row|^2).  Shifting f by
+// w rho_base moves only the equilibrium of e and epsilon by the same amount as
+// the moments themselves, so m - m^eq is formed directly from h.
+__host__ __device__ constexpr int mrt_row(int k, int i) {
+    // rows of Eq. 5
+    return k == 0   ? 1
+           : k == 1 ? (i == 0 ? -4 : (i <= 4 ? -1 : 2))
+           : k == 2 ? (i == 0 ? 4 : (i <= 4 ? -2 : 1))
+           : k == 3 ? ex_of(i)
+           : k == 4 ? (i == 0 ? 0 : (i <= 4 ? -2 * ex_of(i) : ex_of(i)))
+           : k == 5 ? ey_of(i)
+           : k == 6 ? (i == 0 ? 0 : (i <= 4 ? -2 * ey_of(i) : ey_of(i)))
+           : k == 7 ? (i == 1 || i == 3 ? 1 : (i == 2 || i == 4 ? -1 : 0))
+                    : (i == 5 || i == 7 ? 1 : (i == 6 || i == 8 ? -1 : 0));
+}
+__host__ __device__ constexpr int mrt_norm2(int k) {
+    return k == 0 ? 9 : k == 1 || k == 2 ? 36 : k == 3 || k == 5 ? 6 : k == 4 || k == 6 ? 12 : 4;
+}
+
+template <typename T>
+__device__ __forceinline__ void mrt(T h[9], T rho_base, const T rate[9], uint32_t& bad) {
+    const T S = ((h[0] + h[1]) + (h[2] + h[3])) + ((h[4] + h[5]) + (h[6] + h[7])) + h[8];
+    const T jx = (h[1] + h[5] + h[8]) - (h[3] + h[6] + h[7]);
+    const T jy = (h[2] + h[5] + h[6]) - (h[4] + h[7] + h[8]);
+    const T rho = rho_base + S;
+    if (!(rho > T(0)) || !isfinite(jx + jy)) bad = 1u;
+    const T inv = T(1) / rho;
+    const T jj = (jx * jx + jy * jy) * inv;
+    // equilibrium moments of h (Eq. 3 in moment space)
+    T meq[9];
+    meq[0] = S;
+    meq[1] = T(-2) * S + T(3) * jj;
+    meq[2] = S - T(3) * jj;
+    meq[3] = jx;
+    meq[4] = -jx;
+    meq[5] = jy;
+    meq[6] = -jy;
+    meq[7] = (jx * jx - jy * jy) * inv;
+    meq[8] = jx * jy * inv;
+    T d[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        T m = T(0);
+#pragma unroll
+        for (int i = 0; i < 9; ++i)
+            if (mrt_row(k, i) != 0) m += T(mrt_row(k, i)) * h[i];
+        d[k] = (k == 0 || k == 3 || k == 5) ? T(0) : rate[k] * (m - meq[k]) / T(mrt_norm2(k));
+    }
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        T c = T(0);
+#pragma unroll
+        for (int k = 0; k < 9; ++k)
+            if (mrt_row(k, i) != 0 && k != 0 && k != 3 && k != 5) c += T(mrt_row(k, i)) * d[k];
+        h[i] = h[i] - c;
+    }
+}
+
 // ---------------------------------------------------------------- sweep
 
 template <typename T, int TX, int TY, int RPT, bool NTMP>
@@ -84,6 +144,10 @@ __global__ void __launch_bounds__(TX* TY)
         const int pitch = S.pitch;
         T* __restrict__ P = reinterpret_cast<T*>(S.pop) + S.xoff + pitch;  // (x=0, y=0)
         const T rho_base = T(S.rho_base), omega = T(S.omega);
+        const bool use_mrt = S.collision != 0;
+        T rate[9];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) rate[k] = T(S.mrt_s[k]);
         const int x = tile.y + threadIdx.x;
         uint32_t bad = 0;
         if (x < nx) {
@@ -99,7 +163,10 @@ __global__ void __launch_bounds__(TX* TY)
                     // natural state: own slots; write f*_i into slot opp(i)
 #pragma unroll
                     for (int i = 0; i < 9; ++i) h[i] = ldg<NTMP>(&P[i * pl + r0 + x]);
-                    bgk<T>(h, rho_base, omega, bad);
+                    if (use_mrt)
+                        mrt<T>(h, rho_base, rate, bad);
+                    else
+                        bgk<T>(h, rho_base, omega, bad);
 #pragma unroll
                     for (int i = 0; i < 9; ++i) stg<NTMP>(&P[opp_of(i) * pl + r0 + x], h[i]);
                 } else {
@@ -113,7 +180,10 @@ __global__ void __launch_bounds__(TX* TY)
                     h[6] = ldg<NTMP>(&P[8 * pl + rm + xp]);
                     h[7] = ldg<NTMP>(&P[5 * pl + rp + xp]);
                     h[8] = ldg<NTMP>(&P[6 * pl + rp + xm]);
-                    bgk<T>(h, rho_base, omega, bad);
+                    if (use_mrt)
+                        mrt<T>(h, rho_base, rate, bad);
+                    else
+                        bgk<T>(h, rho_base, omega, bad);
                     // f*_i goes to slot i of x + e_i
                     stg<NTMP>(&P[0 * pl + r0 + x], h[0]);
                     stg<NTMP>(&P[1 * pl + r0 + xp], h[1]);

@@ -69,6 +69,9 @@ struct SimDev {
     double rho_base;     // 0 (FP64 stores f) or rho0 (FP32 stores f - w rho0)
     double u_in[2];
     double gravity[2];
+    int32_t collision;   // 0 BGK, 1 MRT
+    int32_t pad2_;
+    double mrt_s[9];     // MRT relaxation rates in the order of the moment matrix
     int32_t swapped;     // AA state of the populations (see above)
     int32_t active;      // batch: still stepping
     int64_t steps_left;  // batch: < 0 means unlimited

@@ -426,6 +426,7 @@ lbm_status lbm_create(const lbm_params* p, void* hip_stream, lbm_sim** out) {
     *out = nullptr;
     if (!p || p->nx < 4 || p->ny < 4 || !(p->tau > 0.5) || p->ib_iters < 0 || p->ib_iters > 1000 ||
         !(p->rho0 > 0) || (p->precision != LBM_F64 && p->precision != LBM_F32_SHIFTED) || !bc_valid(p) ||
+        (p->collision != LBM_BGK && p->collision != LBM_MRT) ||
         (int64_t)p->nx * p->ny > (int64_t)1 << 30)
         return LBM_ERR_INVALID;
     lbm_sim* s = new (std::nothrow) lbm_sim();
@@ -469,6 +470,8 @@ lbm_status lbm_create(const lbm_params* p, void* hip_stream, lbm_sim** out) {
     h.u_in[1] = p->u_in[1];
     h.gravity[0] = p->gravity[0];
     h.gravity[1] = p->gravity[1];
+    h.collision = p->collision;
+    for (int k = 0; k < 9; ++k) h.mrt_s[k] = p->collision == LBM_MRT ? p->mrt_s[k] : 1.0 / p->tau;
     h.swapped = 0;
     h.active = 1;
     h.steps_left = -1;
@@ -1016,6 +1019,8 @@ lbm_status lbm_batch_set_tiling(lbm_batch* b, int32_t tiling) {
     drop_graphs(b);
     return upload_tables(b);
 }
+
+int32_t lbm_batch_get_tiling(const lbm_batch* b) { return b ? b->tiling : -1; }
 
 lbm_status lbm_batch_autotune(lbm_batch* b, int32_t trials, int32_t* chosen) {
     if (!b || trials <= 0) return LBM_ERR_INVALID;

@@ -16,6 +16,7 @@ OK, ERR_INVALID, ERR_NOMEM, ERR_DEVICE, ERR_UNSTABLE, ERR_STATE = range(6)
 F64, F32_SHIFTED = 0, 1
 PERIODIC, WALL, FREESLIP, VELOCITY, OUTFLOW = range(5)
 FIXED, FREE = 0, 1
+BGK, MRT = 0, 1
 MAX_BODIES = 8
 
 _NAMES = {0: "LBM_OK", 1: "LBM_ERR_INVALID", 2: "LBM_ERR_NOMEM", 3: "LBM_ERR_DEVICE",
@@ -34,7 +35,8 @@ class Params(ctypes.Structure):
                 ("bc_west", ctypes.c_int32), ("bc_east", ctypes.c_int32),
                 ("bc_south", ctypes.c_int32), ("bc_north", ctypes.c_int32),
                 ("u_in", ctypes.c_double * 2), ("u_init", ctypes.c_double * 2),
-                ("ib_iters", ctypes.c_int32), ("gravity", ctypes.c_double * 2)]
+                ("ib_iters", ctypes.c_int32), ("gravity", ctypes.c_double * 2),
+                ("collision", ctypes.c_int32), ("mrt_s", ctypes.c_double * 9)]
 
 
 class Body(ctypes.Structure):
@@ -72,6 +74,7 @@ SIGNATURES = [
     ("lbm_batch_bytes", _SZ, [_P]),
     ("lbm_batch_autotune", _ST, [_P, _I32, ctypes.POINTER(_I32)]),
     ("lbm_batch_set_tiling", _ST, [_P, _I32]),
+    ("lbm_batch_get_tiling", _I32, [_P]),
     ("lbm_tiling_count", _I32, []),
     ("lbm_tiling_info", _ST, [_I32, ctypes.POINTER(_I32), ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
     ("lbm_batch_profile", _ST, [_P, _I32, _DP, ctypes.POINTER(_I64)]),
@@ -130,7 +133,8 @@ class Sim:
     """One simulation (lbm_sim)."""
 
     def __init__(self, nx, ny, tau, rho0=1.0, precision=F64, bc=(PERIODIC,) * 4, u_in=(0.0, 0.0),
-                 u_init=(0.0, 0.0), ib_iters=10, gravity=(0.0, 0.0), stream=None):
+                 u_init=(0.0, 0.0), ib_iters=10, gravity=(0.0, 0.0), stream=None, collision=BGK,
+                 mrt_s=None):
         L = load()
         p = Params()
         p.nx, p.ny, p.tau, p.rho0, p.precision = nx, ny, tau, rho0, precision
@@ -139,6 +143,8 @@ class Sim:
         p.u_init[:] = u_init
         p.ib_iters = ib_iters
         p.gravity[:] = gravity
+        p.collision = collision
+        p.mrt_s[:] = mrt_s if mrt_s is not None else [1.0 / tau] * 9
         h = _P()
         rc = L.lbm_create(ctypes.byref(p), _stream_handle(stream), ctypes.byref(h))
         if rc != OK:
@@ -147,12 +153,16 @@ class Sim:
         self.nx, self.ny, self.precision = nx, ny, precision
 
     @classmethod
-    def from_case(cls, case, precision=None, stream=None):
-        """Create from a workloads.py case dict and set its bodies."""
+    def from_case(cls, case, precision=None, stream=None, collision=None, mrt_s=None):
+        """Create from a workloads.py case dict and set its bodies.  The
+        collision follows the case's "mrt_s" unless given."""
+        if collision is None:
+            mrt_s = case.get("mrt_s") if mrt_s is None else mrt_s
+            collision = BGK if mrt_s is None else MRT
         s = cls(case["nx"], case["ny"], case["tau"], rho0=case["rho0"],
                 precision=case["precision"] if precision is None else precision, bc=case["bc"],
                 u_in=case["u_in"], u_init=case["u_init"], ib_iters=case["ib_iters"],
-                gravity=case["gravity"], stream=stream)
+                gravity=case["gravity"], stream=stream, collision=collision, mrt_s=mrt_s)
         for k, b in enumerate(case["bodies"]):
             s.set_body(k, b["kind"], b["n"], xy=b["xy"], uv=b["uv"], ds=b["ds"], xc=b["xc"], U=b["U"],
                        omega=b["omega"], theta=b["theta"], radius=b["radius"], rho_s=b["rho_s"])
@@ -319,6 +329,11 @@ class Batch:
         rc = load().lbm_batch_set_tiling(self._h, k)
         if rc != OK:
             raise LbmError(rc, "lbm_batch_set_tiling")
+
+    @property
+    def tiling(self):
+        """Index of the sweep tiling in use."""
+        return load().lbm_batch_get_tiling(self._h)
 
 
 def tilings():

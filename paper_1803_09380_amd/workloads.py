@@ -13,7 +13,11 @@ Cases (lattice units):
   * flow past a fixed cylinder (Sec. 3.2): channel, uniform inflow U at the west
     side, zero-gradient outflow at the east side, free-slip south/north, tau from
     Re = U D / nu;
-  * settling particles (Sec. 3.3): closed box with walls, one or two free circles.
+  * settling particles (Sec. 3.3): closed box with walls, one or two free circles;
+  * the paper's own set-ups: Table 1's cylinder (Sec. 3.2), the single particle
+    in a channel (Sec. 3.3.1) and the DKT pair (Sec. 3.3.2).
+
+A case may carry "mrt_s", the nine MRT rates (absent or None: BGK).
 """
 import math
 
@@ -22,6 +26,13 @@ import numpy as np
 PERIODIC, WALL, FREESLIP, VELOCITY, OUTFLOW = range(5)
 FIXED, FREE = 0, 1
 F64, F32 = 0, 1
+
+
+def mrt_rates(tau):
+    """Relaxation rates of Eq. 6 in the moment order of Eq. 5 as chosen for the
+    validation cases of Sec. 4.1: s_e = 1.1, s_epsilon = 1.25, s_q = 1.8 and
+    s_s = 1/tau; the conserved moments' rates (rho, j) do not act and are 1."""
+    return [1.0, 1.1, 1.25, 1.0, 1.8, 1.0, 1.8, 1.0 / tau, 1.0 / tau]
 
 
 def circle_markers(xc, yc, R, n, phase=0.0):
@@ -88,6 +99,76 @@ def settling(nx=400, ny=4000, D=24.0, density_ratio=1.2, two=False, tau=0.8, u_r
                 nx=nx, ny=ny, tau=tau, rho0=1.0, bc=(WALL,) * 4, u_in=(0.0, 0.0),
                 u_init=(0.0, 0.0), ib_iters=ib_iters, precision=precision, gravity=(0.0, -g),
                 bodies=bodies, meta=dict(D=D, g=g, density_ratio=density_ratio))
+
+
+def table1_cylinder(Re, D=40.0, U0=0.1, precision=F32, collision_mrt=True, ib_iters=10):
+    """Flow past a fixed cylinder as set up for Table 1 (Sec. 3.2): domain
+    40D x 20D, cylinder centre at (10D, 10D), delta_x = D/40 (D = 40 lattice
+    units), inflow U0 = 0.1 by non-equilibrium extrapolation at the inlet,
+    zero-gradient outflow, free-slip sides, MRT with the rates of Sec. 4.1
+    (tau_s from Re = U0 D / nu).  The start is uniform flow at U0."""
+    nx, ny = int(round(40 * D)), int(round(20 * D))
+    case = cylinder(nx=nx, ny=ny, D=D, centre=(10.0 * D, 10.0 * D), U=U0, Re=Re, precision=precision,
+                    ib_iters=ib_iters)
+    case["name"] = "table1_Re%g_D%g" % (Re, D)
+    case["mrt_s"] = mrt_rates(case["tau"]) if collision_mrt else None
+    return case
+
+
+# Physical set-ups of the particle cases of Sec. 3.3 (CGS units) and their
+# lattice units: delta_x from the particle resolution, delta_t from
+# nu_lattice = (tau - 1/2)/3 = nu delta_t / delta_x^2, g_lattice = g delta_t^2 / delta_x.
+def lattice_units(dx_cm, tau, nu_cm2s=0.01, g_cms2=980.0):
+    nu_lu = (tau - 0.5) / 3.0
+    dt = nu_lu * dx_cm * dx_cm / nu_cm2s
+    return dict(dx=dx_cm, dt=dt, nu_lu=nu_lu, g_lu=g_cms2 * dt * dt / dx_cm)
+
+
+def single_particle_channel(density_ratio, precision=F32, ib_iters=10, start_below_inlet=None):
+    """A particle settling in a channel (Sec. 3.3.1): D = 0.1 cm resolved by 26
+    lattice units, width W = 4D, height H = 400/13 D, tau = 0.6, fluid density
+    1 g/cm^3, nu = 0.01 cm^2/s, |g| = 980 cm/s^2, released from rest 0.31 W from
+    the centre line.  Zero velocity at the inlet and a free-stream outlet.
+
+    Lattice orientation: the channel runs along x (gravity +x), inlet at the
+    west side (velocity rule with U = 0), outlet at the east side
+    (zero-gradient), side walls south/north.  The release height is not
+    given; the particle starts one channel width below the inlet by default."""
+    D = 26.0
+    W, H = int(round(4 * D)), int(round(400.0 / 13.0 * D))
+    lu = lattice_units(0.1 / D, 0.6)
+    R = D / 2.0
+    x0 = float(W) if start_below_inlet is None else float(start_below_inlet)
+    centre_line = (W - 1) / 2.0  # walls half a spacing outside nodes 0 and W-1
+    y0 = centre_line - 0.31 * W
+    n = int(round(math.pi * D))
+    body = dict(kind=FREE, n=n, xy=None, uv=None, ds=None, xc=(x0, y0), U=(0.0, 0.0), omega=0.0,
+                theta=0.0, radius=R, rho_s=density_ratio)
+    return dict(name="single_particle_r%g" % density_ratio, nx=H, ny=W, tau=0.6, rho0=1.0,
+                bc=(VELOCITY, OUTFLOW, WALL, WALL), u_in=(0.0, 0.0), u_init=(0.0, 0.0),
+                ib_iters=ib_iters, precision=precision, gravity=(lu["g_lu"], 0.0), bodies=[body],
+                mrt_s=None, meta=dict(D=D, W=W, H=H, centre_line=centre_line, units=lu,
+                                      density_ratio=density_ratio))
+
+
+def dkt_pair(precision=F32, ib_iters=10):
+    """Drafting-kissing-tumbling of two particles (Sec. 3.3.2): channel 2 cm x
+    8 cm on 200 x 800 nodes (D = 0.2 cm on 20 nodes), tau = 0.8, particle
+    density 1.01 g/cm^3, nu = 0.01 cm^2/s, |g| = 980 cm/s^2, closed box, lower
+    particle at (1.0, 6.8) cm, upper at (0.999, 7.2) cm.  Node i sits at
+    (i + 1/2) delta_x, so a position p cm is p/delta_x - 1/2 lattice units."""
+    nx, ny, D = 200, 800, 20.0
+    dx = 2.0 / nx
+    lu = lattice_units(dx, 0.8)
+    to_lu = lambda p: p / dx - 0.5
+    n = int(round(math.pi * D))
+    bodies = [dict(kind=FREE, n=n, xy=None, uv=None, ds=None, xc=(to_lu(1.0), to_lu(6.8)), U=(0.0, 0.0),
+                   omega=0.0, theta=0.0, radius=D / 2, rho_s=1.01),
+              dict(kind=FREE, n=n, xy=None, uv=None, ds=None, xc=(to_lu(0.999), to_lu(7.2)), U=(0.0, 0.0),
+                   omega=0.0, theta=0.0, radius=D / 2, rho_s=1.01)]
+    return dict(name="dkt_200x800", nx=nx, ny=ny, tau=0.8, rho0=1.0, bc=(WALL,) * 4, u_in=(0.0, 0.0),
+                u_init=(0.0, 0.0), ib_iters=ib_iters, precision=precision, gravity=(0.0, -lu["g_lu"]),
+                bodies=bodies, mrt_s=None, meta=dict(D=D, units=lu))
 
 
 def batch(seed=0, count=256, precision=F32):

@@ -7,9 +7,12 @@ from paper_1803_09380_amd import lbmib
 from paper_1803_09380_amd import workloads as wl
 
 
-def oracle_from_case(case, route=po.SIMPLIFIED):
+def oracle_from_case(case, route=po.SIMPLIFIED, mrt_s=None):
+    """mrt_s: None for the case's own collision, else the nine MRT rates."""
+    mrt_s = case.get("mrt_s") if mrt_s is None else mrt_s
     o = po.Oracle(case["nx"], case["ny"], case["tau"], rho0=case["rho0"], bc=case["bc"], u_in=case["u_in"],
-                  u_init=case["u_init"], ib_iters=case["ib_iters"], route=route, gravity=case["gravity"])
+                  u_init=case["u_init"], ib_iters=case["ib_iters"], route=route, gravity=case["gravity"],
+                  collision=po.BGK if mrt_s is None else po.MRT, mrt_s=mrt_s)
     for k, b in enumerate(case["bodies"]):
         if b["kind"] == wl.FREE:
             o.set_body(k, po.FREE, b["n"], xc=b["xc"], U=b["U"], omega=b["omega"], theta=b["theta"],
@@ -20,8 +23,9 @@ def oracle_from_case(case, route=po.SIMPLIFIED):
     return o
 
 
-def gpu_from_case(case, precision=None):
-    return lbmib.Sim.from_case(case, precision=precision)
+def gpu_from_case(case, precision=None, mrt_s=None):
+    """mrt_s: None for the case's own collision, else the nine MRT rates."""
+    return lbmib.Sim.from_case(case, precision=precision, mrt_s=mrt_s)
 
 
 def rel_max(a, b):

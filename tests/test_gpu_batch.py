@@ -58,6 +58,25 @@ def test_batch_equals_alone_bitwise(steps):
         _same(_state(s, len(c["bodies"])), ref)
 
 
+def test_batch_mixes_bgk_and_mrt_members():
+    _say("batch with BGK and MRT members")
+    cases = _cases()
+    rates = [None, wl.mrt_rates(cases[1]["tau"]), None, wl.mrt_rates(cases[3]["tau"])]
+    alone = []
+    for c, r in zip(cases, rates):
+        s = gpu_from_case(c, precision=lbmib.F32_SHIFTED, mrt_s=r)
+        s.step(11)
+        alone.append(_state(s, len(c["bodies"])))
+    sims = [gpu_from_case(c, precision=lbmib.F32_SHIFTED, mrt_s=r) for c, r in zip(cases, rates)]
+    b = lbmib.Batch(lbmib.F32_SHIFTED)
+    for s in sims:
+        assert b.admit(s)
+    b.step(11)
+    b.sync()
+    for s, c, ref in zip(sims, cases, alone):
+        _same(_state(s, len(c["bodies"])), ref)
+
+
 def test_batch_every_tiling_same_bits():
     _say("tilings")
     cases = _cases()[:3]
@@ -68,6 +87,7 @@ def test_batch_every_tiling_same_bits():
         for s in sims:
             b.admit(s)
         b.set_tiling(k)
+        assert b.tiling == k
         b.step(9)
         st = [_state(s, len(c["bodies"])) for s, c in zip(sims, cases)]
         if ref is None:

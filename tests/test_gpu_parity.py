@@ -25,11 +25,12 @@ def _say(msg):
     sys.stdout.flush()
 
 
-def _pair_random(nx, ny, tau, bc, seed, u_in=(0.0, 0.0), precision=lbmib.F64):
+def _pair_random(nx, ny, tau, bc, seed, u_in=(0.0, 0.0), precision=lbmib.F64, mrt_s=None):
     f = wl.random_populations(seed, nx, ny, REST, amp=0.05)
-    o = po.Oracle(nx, ny, tau, bc=bc, u_in=u_in)
+    o = po.Oracle(nx, ny, tau, bc=bc, u_in=u_in, collision=po.BGK if mrt_s is None else po.MRT, mrt_s=mrt_s)
     o.set_populations(f)
-    g = lbmib.Sim(nx, ny, tau, bc=bc, u_in=u_in, precision=precision)
+    g = lbmib.Sim(nx, ny, tau, bc=bc, u_in=u_in, precision=precision,
+                  collision=lbmib.BGK if mrt_s is None else lbmib.MRT, mrt_s=mrt_s)
     g.set_populations(f)
     return o, g
 
@@ -88,13 +89,13 @@ def test_single_marker_sweeps_f64():
     assert rel_max(g.populations(), o.populations()) < 1e-12
 
 
-def _compare_case(case, steps, tol_f=1e-12, tol_force=1e-12, check_state=False):
+def _compare_case(case, steps, tol_f=1e-12, tol_force=1e-12, check_state=False, mrt_s=None):
     """Fields within tol_f (max-norm relative).  Force and torque are sums over
     N sweeps and all markers whose terms largely cancel on closed bodies, so
     their bound is relative to the body's force scale S = |F| + |T|/R (a
     summation error bound), not to the net value."""
-    o = oracle_from_case(case)
-    g = gpu_from_case(case)
+    o = oracle_from_case(case, mrt_s=mrt_s)
+    g = gpu_from_case(case, mrt_s=mrt_s)
     o.step(steps)
     g.step(steps)
     fo, fg = o.fields(), g.fields()
@@ -193,3 +194,70 @@ def test_unstable_state_is_reported():
     with pytest.raises(lbmib.LbmError) as e:
         g.sync()
     assert e.value.code == lbmib.ERR_UNSTABLE
+
+
+# ---------------------------------------------------------------- MRT (Eqs. 2, 5, 6)
+
+@pytest.mark.parametrize("steps", [1, 3])
+def test_mrt_periodic_random_state_f64(steps):
+    _say("mrt periodic 150x70 steps=%d" % steps)
+    o, g = _pair_random(150, 70, 0.77, (lbmib.PERIODIC,) * 4, seed=40 + steps, mrt_s=wl.mrt_rates(0.77))
+    o.step(steps)
+    g.step(steps)
+    assert rel_max(g.populations(), o.populations()) < 1e-12
+
+
+@pytest.mark.parametrize("name,bc", [
+    ("box_walls", (lbmib.WALL,) * 4),
+    ("channel", (lbmib.VELOCITY, lbmib.OUTFLOW, lbmib.FREESLIP, lbmib.FREESLIP)),
+    ("periodic_y_walls_x", (lbmib.WALL, lbmib.WALL, lbmib.PERIODIC, lbmib.PERIODIC)),
+])
+def test_mrt_boundary_rules_f64(name, bc):
+    _say("mrt bc %s" % name)
+    o, g = _pair_random(70, 45, 0.81, bc, seed=9, u_in=(0.04, 0.01), mrt_s=wl.mrt_rates(0.81))
+    o.step(5)
+    g.step(5)
+    assert rel_max(g.populations(), o.populations()) < 1e-12
+
+
+def test_mrt_with_equal_rates_is_bgk_f64():
+    """Every rate 1/tau makes Eq. 2 the BGK operator: the GPU's MRT branch with
+    those rates must give the oracle's BGK result."""
+    _say("mrt equal rates == bgk")
+    tau = 0.83
+    f = wl.random_populations(17, 64, 48, REST, amp=0.05)
+    o = po.Oracle(64, 48, tau, bc=(lbmib.WALL,) * 4)
+    o.set_populations(f)
+    g = lbmib.Sim(64, 48, tau, bc=(lbmib.WALL,) * 4, collision=lbmib.MRT, mrt_s=[1.0 / tau] * 9)
+    g.set_populations(f)
+    o.step(6)
+    g.step(6)
+    assert rel_max(g.populations(), o.populations()) < 1e-12
+
+
+def test_mrt_cylinder_channel_f64():
+    _say("mrt cylinder channel 160x80 f64, 200 steps")
+    case = wl.cylinder(nx=160, ny=80, D=16.0, centre=(40.0, 40.0), U=0.05, Re=20.0, precision=wl.F64)
+    _compare_case(case, 200, mrt_s=wl.mrt_rates(case["tau"]))
+
+
+def test_mrt_couette_f64():
+    _say("mrt couette 48 f64, 300 steps")
+    case = wl.couette(48)
+    _compare_case(case, 300, mrt_s=wl.mrt_rates(case["tau"]))
+
+
+def test_mrt_fp32_couette_velocity_within_1e5():
+    _say("mrt couette 64 f32 vs oracle, 2000 steps")
+    case = wl.couette(64)
+    rates = wl.mrt_rates(case["tau"])
+    o = oracle_from_case(case, mrt_s=rates)
+    g = gpu_from_case(case, precision=lbmib.F32_SHIFTED, mrt_s=rates)
+    o.step(2000)
+    g.step(2000)
+    assert velocity_rel(g.fields(), o.fields()) < 1e-5
+
+
+def test_unknown_collision_is_rejected():
+    with pytest.raises(lbmib.LbmError):
+        lbmib.Sim(16, 16, 0.8, collision=7)

@@ -3,6 +3,8 @@ point that include/lbmib.h declares, and the binding knows each of them."""
 import ctypes
 import os
 import re
+import shutil
+import subprocess
 
 import pytest
 
@@ -39,9 +41,37 @@ def test_binding_covers_the_header():
 
 
 def test_binding_struct_layouts():
-    # lbm_params: 2 int32, 2 double, 5 int32 (+pad), 4 double, int32 (+pad), 2 double
-    assert ctypes.sizeof(lbmib.Params) == 104
+    # lbm_params: 2 int32, 2 double, 5 int32 (+pad), 4 double, int32 (+pad),
+    # 2 double, int32 (+pad), 9 double
+    assert ctypes.sizeof(lbmib.Params) == 184
     assert ctypes.sizeof(lbmib.Body) == 72
+
+
+def _c_layout(struct, fields, tmp_path):
+    """sizeof and offsetof of a header struct, printed by a program that gcc
+    builds against include/lbmib.h."""
+    src = tmp_path / "layout.c"
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "lbmib.h"', "int main(void) {",
+             '  printf("%%zu\\n", sizeof(%s));' % struct]
+    lines += ['  printf("%%zu\\n", offsetof(%s, %s));' % (struct, f) for f in fields]
+    lines += ["  return 0;", "}"]
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()
+    return int(out[0]), [int(v) for v in out[1:]]
+
+
+@pytest.mark.parametrize("struct,cls", [("lbm_params", "Params"), ("ib_body", "Body")])
+def test_binding_layout_matches_the_c_header(struct, cls, tmp_path):
+    if shutil.which("gcc") is None:
+        pytest.skip("no C compiler")
+    ct = getattr(lbmib, cls)
+    names = [f[0] for f in ct._fields_]
+    size, offs = _c_layout(struct, names, tmp_path)
+    assert size == ctypes.sizeof(ct)
+    assert offs == [getattr(ct, n).offset for n in names]
 
 
 def test_version_string():
