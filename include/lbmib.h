@@ -62,8 +62,11 @@ typedef enum {
     LBM_BC_FREESLIP = 2, /* south/north only: specular reflection                   */
     LBM_BC_VELOCITY = 3, /* west only: every population of column 0 is set to
                             f^eq(rho(1), u_in) + f(1) - f^eq(rho(1), u(1))           */
-    LBM_BC_OUTFLOW = 4   /* east only: populations entering from the east copy the
+    LBM_BC_OUTFLOW = 4,  /* east only: populations entering from the east copy the
                             post-stream values of column nx-2                        */
+    LBM_BC_PRESSURE = 5  /* east only, nx >= 5: every population of column nx-1 is set
+                            to f^eq(rho0, u(nx-2)) + f(nx-2) - f^eq(rho(nx-2), u(nx-2))
+                            (non-equilibrium extrapolation at fixed density, Sec. 3.2) */
 } lbm_bc;
 
 /* A population entering a corner node through both an west/east and a
@@ -117,7 +120,7 @@ typedef struct lbm_batch lbm_batch;
  * f^eq(rho0, u_init).  hip_stream is a hipStream_t (NULL: a stream the handle
  * creates and owns).  Errors: LBM_ERR_INVALID (sizes, tau, boundary pairing:
  * periodic sides come in pairs, FREESLIP only south/north, VELOCITY only west,
- * OUTFLOW only east), LBM_ERR_NOMEM. */
+ * OUTFLOW/PRESSURE only east, PRESSURE with nx < 5), LBM_ERR_NOMEM. */
 lbm_status lbm_create(const lbm_params* p, void* hip_stream, lbm_sim** out);
 void lbm_destroy(lbm_sim* s);
 const char* lbm_last_error(const lbm_sim* s);

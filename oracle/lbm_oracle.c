@@ -198,7 +198,10 @@ static int bc_ok(const or_params* p) {
     if ((p->bc_west == OR_PERIODIC) != (p->bc_east == OR_PERIODIC)) return 0;
     if ((p->bc_south == OR_PERIODIC) != (p->bc_north == OR_PERIODIC)) return 0;
     if (p->bc_west != OR_PERIODIC && p->bc_west != OR_WALL && p->bc_west != OR_VELOCITY) return 0;
-    if (p->bc_east != OR_PERIODIC && p->bc_east != OR_WALL && p->bc_east != OR_OUTFLOW) return 0;
+    if (p->bc_east != OR_PERIODIC && p->bc_east != OR_WALL && p->bc_east != OR_OUTFLOW &&
+        p->bc_east != OR_PRESSURE)
+        return 0;
+    if (p->bc_east == OR_PRESSURE && p->nx < 5) return 0;
     if (p->bc_south != OR_PERIODIC && p->bc_south != OR_WALL && p->bc_south != OR_FREESLIP) return 0;
     if (p->bc_north != OR_PERIODIC && p->bc_north != OR_WALL && p->bc_north != OR_FREESLIP) return 0;
     return 1;
@@ -428,6 +431,17 @@ static void stream_all(or_sim* s) {
         for (int y = 0; y < ny; ++y)
             for (int i = 0; i < Q; ++i)
                 if (EX[i] == -1) s->f[IDX(s, i, nx - 1, y)] = s->f[IDX(s, i, nx - 2, y)];
+    /* pressure outlet by non-equilibrium extrapolation (Sec. 3.2): every
+     * population of column nx-1 is f^eq(rho0, u(nx-2)) + f^neq(nx-2) */
+    if (be == OR_PRESSURE)
+        for (int y = 0; y < ny; ++y) {
+            double f2[9], rho2, u2, v2, eqb[9], eq2[9];
+            node_f(s, nx - 2, y, f2);
+            moments(f2, &rho2, &u2, &v2);
+            or_feq(s->p.rho0, u2, v2, eqb);
+            or_feq(rho2, u2, v2, eq2);
+            for (int i = 0; i < Q; ++i) s->f[IDX(s, i, nx - 1, y)] = eqb[i] + (f2[i] - eq2[i]);
+        }
     /* velocity inlet by non-equilibrium extrapolation: every population of
      * column 0 is f^eq(rho(1), U_in) + f^neq(1) */
     if (bw == OR_VELOCITY)

@@ -22,7 +22,7 @@
 extern "C" {
 #endif
 
-enum { OR_PERIODIC = 0, OR_WALL = 1, OR_FREESLIP = 2, OR_VELOCITY = 3, OR_OUTFLOW = 4 };
+enum { OR_PERIODIC = 0, OR_WALL = 1, OR_FREESLIP = 2, OR_VELOCITY = 3, OR_OUTFLOW = 4, OR_PRESSURE = 5 };
 enum { OR_BGK = 0, OR_MRT = 1 };
 enum { OR_ROUTE_LITERAL = 0, OR_ROUTE_SIMPLIFIED = 1 };
 enum { OR_FIXED = 0, OR_FREE = 1 };

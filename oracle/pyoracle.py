@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB = os.path.join(HERE, "liboracle.so")
 SRC = os.path.join(HERE, "lbm_oracle.c")
 
-PERIODIC, WALL, FREESLIP, VELOCITY, OUTFLOW = range(5)
+PERIODIC, WALL, FREESLIP, VELOCITY, OUTFLOW, PRESSURE = range(6)
 BGK, MRT = 0, 1
 LITERAL, SIMPLIFIED = 0, 1
 FIXED, FREE = 0, 1

@@ -280,6 +280,24 @@ __global__ void __launch_bounds__(256)
             }
             continue;
         }
+        if (x == nx - 1 && S.bc[SIDE_E] == BC_PRESSURE) {
+            // non-equilibrium extrapolation from column nx-2 at density rho0
+            T f2[9];
+#pragma unroll
+            for (int i = 0; i < 9; ++i) f2[i] = post_stream<T>(S, i, nx - 2, y, sw);
+            const T S2 = ((f2[0] + f2[1]) + (f2[2] + f2[3])) + ((f2[4] + f2[5]) + (f2[6] + f2[7])) + f2[8];
+            const T jx2 = (f2[1] + f2[5] + f2[8]) - (f2[3] + f2[6] + f2[7]);
+            const T jy2 = (f2[2] + f2[5] + f2[6]) - (f2[4] + f2[7] + f2[8]);
+            const T rho2 = T(S.rho_base) + S2;
+            const T rhob = T(S.rho0), Sb = T(S.rho0 - S.rho_base);
+            const T jxb = rhob * (jx2 / rho2), jyb = rhob * (jy2 / rho2);
+#pragma unroll
+            for (int i = 0; i < 9; ++i) {
+                const T v = heq_i<T>(i, Sb, rhob, jxb, jyb) + (f2[i] - heq_i<T>(i, S2, rho2, jx2, jy2));
+                *loc<T>(S, i, nx - 1, y, sw) = v;
+            }
+            continue;
+        }
 #pragma unroll
         for (int i = 1; i < 9; ++i) {
             const int sx = wrap(x - ex_of(i), nx, S.px), sy = wrap(y - ey_of(i), ny, S.py);

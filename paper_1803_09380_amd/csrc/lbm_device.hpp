@@ -43,7 +43,7 @@ __host__ __device__ constexpr T weight_of(int i) {
     return i == 0 ? T(4) / T(9) : (i <= 4 ? T(1) / T(9) : T(1) / T(36));
 }
 
-enum : int32_t { BC_PERIODIC = 0, BC_WALL = 1, BC_FREESLIP = 2, BC_VELOCITY = 3, BC_OUTFLOW = 4 };
+enum : int32_t { BC_PERIODIC = 0, BC_WALL = 1, BC_FREESLIP = 2, BC_VELOCITY = 3, BC_OUTFLOW = 4, BC_PRESSURE = 5 };
 enum : int32_t { SIDE_W = 0, SIDE_E = 1, SIDE_S = 2, SIDE_N = 3 };
 enum : int32_t { BODY_FIXED = 0, BODY_FREE = 1 };
 

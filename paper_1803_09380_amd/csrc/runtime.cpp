@@ -152,14 +152,18 @@ int num_cus(int dev) {
 }
 
 bool bc_valid(const lbm_params* p) {
-    auto ok = [](int v) { return v >= LBM_BC_PERIODIC && v <= LBM_BC_OUTFLOW; };
+    auto ok = [](int v) { return v >= LBM_BC_PERIODIC && v <= LBM_BC_PRESSURE; };
     if (!ok(p->bc_west) || !ok(p->bc_east) || !ok(p->bc_south) || !ok(p->bc_north)) return false;
     if ((p->bc_west == LBM_BC_PERIODIC) != (p->bc_east == LBM_BC_PERIODIC)) return false;
     if ((p->bc_south == LBM_BC_PERIODIC) != (p->bc_north == LBM_BC_PERIODIC)) return false;
-    if (p->bc_west == LBM_BC_FREESLIP || p->bc_west == LBM_BC_OUTFLOW) return false;
+    if (p->bc_west == LBM_BC_FREESLIP || p->bc_west == LBM_BC_OUTFLOW || p->bc_west == LBM_BC_PRESSURE)
+        return false;
+    if (p->bc_east == LBM_BC_PRESSURE && p->nx < 5) return false;
     if (p->bc_east == LBM_BC_FREESLIP || p->bc_east == LBM_BC_VELOCITY) return false;
-    if (p->bc_south == LBM_BC_VELOCITY || p->bc_south == LBM_BC_OUTFLOW) return false;
-    if (p->bc_north == LBM_BC_VELOCITY || p->bc_north == LBM_BC_OUTFLOW) return false;
+    if (p->bc_south == LBM_BC_VELOCITY || p->bc_south == LBM_BC_OUTFLOW || p->bc_south == LBM_BC_PRESSURE)
+        return false;
+    if (p->bc_north == LBM_BC_VELOCITY || p->bc_north == LBM_BC_OUTFLOW || p->bc_north == LBM_BC_PRESSURE)
+        return false;
     return true;
 }
 

@@ -14,7 +14,7 @@ LIB_PATH = os.path.join(HERE, "liblbmib.so")
 
 OK, ERR_INVALID, ERR_NOMEM, ERR_DEVICE, ERR_UNSTABLE, ERR_STATE = range(6)
 F64, F32_SHIFTED = 0, 1
-PERIODIC, WALL, FREESLIP, VELOCITY, OUTFLOW = range(5)
+PERIODIC, WALL, FREESLIP, VELOCITY, OUTFLOW, PRESSURE = range(6)
 FIXED, FREE = 0, 1
 BGK, MRT = 0, 1
 MAX_BODIES = 8

@@ -23,7 +23,7 @@ import math
 
 import numpy as np
 
-PERIODIC, WALL, FREESLIP, VELOCITY, OUTFLOW = range(5)
+PERIODIC, WALL, FREESLIP, VELOCITY, OUTFLOW, PRESSURE = range(6)
 FIXED, FREE = 0, 1
 F64, F32 = 0, 1
 
@@ -101,17 +101,20 @@ def settling(nx=400, ny=4000, D=24.0, density_ratio=1.2, two=False, tau=0.8, u_r
                 bodies=bodies, meta=dict(D=D, g=g, density_ratio=density_ratio))
 
 
-def table1_cylinder(Re, D=40.0, U0=0.1, precision=F32, collision_mrt=True, ib_iters=10):
+def table1_cylinder(Re, D=40.0, U0=0.1, precision=F32, collision_mrt=True, ib_iters=10, sides=FREESLIP,
+                    outlet=PRESSURE):
     """Flow past a fixed cylinder as set up for Table 1 (Sec. 3.2): domain
     40D x 20D, cylinder centre at (10D, 10D), delta_x = D/40 (D = 40 lattice
-    units), inflow U0 = 0.1 by non-equilibrium extrapolation at the inlet,
-    zero-gradient outflow, free-slip sides, MRT with the rates of Sec. 4.1
-    (tau_s from Re = U0 D / nu).  The start is uniform flow at U0."""
+    units), inflow U0 = 0.1, inlet and outlet by non-equilibrium extrapolation
+    (velocity at the inlet, density rho0 at the outlet), free-slip sides (the
+    paper does not name them), MRT with the rates of Sec. 4.1 (tau_s from
+    Re = U0 D / nu).  The start is uniform flow at U0."""
     nx, ny = int(round(40 * D)), int(round(20 * D))
     case = cylinder(nx=nx, ny=ny, D=D, centre=(10.0 * D, 10.0 * D), U=U0, Re=Re, precision=precision,
                     ib_iters=ib_iters)
     case["name"] = "table1_Re%g_D%g" % (Re, D)
     case["mrt_s"] = mrt_rates(case["tau"]) if collision_mrt else None
+    case["bc"] = (case["bc"][0], outlet, sides, sides)
     return case
 
 

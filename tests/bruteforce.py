@@ -99,10 +99,10 @@ def dense_sweeps(f, markers, U, ds, iters):
     return g.reshape(9, ny, nx), F
 
 
-PERIODIC, WALL, FREESLIP, VELOCITY, OUTFLOW = range(5)
+PERIODIC, WALL, FREESLIP, VELOCITY, OUTFLOW, PRESSURE = range(6)
 
 
-def general_step(f, tau, bc, u_in=(0.0, 0.0)):
+def general_step(f, tau, bc, u_in=(0.0, 0.0), rho_out=1.0):
     """One BGK step written in push form with explicit loops (tiny grids only).
 
     bc = (west, east, south, north).  Each post-collision population moves to
@@ -114,7 +114,9 @@ def general_step(f, tau, bc, u_in=(0.0, 0.0)):
       VELOCITY / OUTFLOW -> dropped; the open columns are rebuilt afterwards:
       OUTFLOW (east): the populations with e_x = -1 at column nx-1 copy column nx-2;
       VELOCITY (west, non-equilibrium extrapolation): every population of column 0
-      becomes f^eq(rho(1), U_in) + f(1) - f^eq(rho(1), u(1))."""
+      becomes f^eq(rho(1), U_in) + f(1) - f^eq(rho(1), u(1));
+      PRESSURE (east, non-equilibrium extrapolation): every population of column
+      nx-1 becomes f^eq(rho_out, u(nx-2)) + f(nx-2) - f^eq(rho(nx-2), u(nx-2))."""
     rho, ux, uy = moments(f)
     fp = f - (f - equilibrium(rho, ux, uy)) / tau
     ny, nx = f.shape[1:]
@@ -148,6 +150,10 @@ def general_step(f, tau, bc, u_in=(0.0, 0.0)):
         for i in range(9):
             if E[i, 0] == -1:
                 out[i, :, nx - 1] = out[i, :, nx - 2]
+    if east == PRESSURE:
+        r2, u2, v2 = moments(out[:, :, nx - 2])
+        out[:, :, nx - 1] = (equilibrium(np.full_like(r2, rho_out), u2, v2)
+                             + out[:, :, nx - 2] - equilibrium(r2, u2, v2))
     if west == VELOCITY:
         r1, u1, v1 = moments(out[:, :, 1])
         out[:, :, 0] = (equilibrium(r1, np.full_like(r1, u_in[0]), np.full_like(r1, u_in[1]))

@@ -121,6 +121,9 @@ BC_CASES = [
     ("wall_inlet_mix", (bf.VELOCITY, bf.WALL, bf.WALL, bf.FREESLIP)),
     ("wall_outlet_mix", (bf.WALL, bf.OUTFLOW, bf.FREESLIP, bf.WALL)),
     ("periodic_y_walls_x", (bf.WALL, bf.WALL, bf.PERIODIC, bf.PERIODIC)),
+    ("channel_inlet_pressure_outlet", (bf.VELOCITY, bf.PRESSURE, bf.FREESLIP, bf.FREESLIP)),
+    ("wall_pressure_mix", (bf.WALL, bf.PRESSURE, bf.WALL, bf.FREESLIP)),
+    ("periodic_y_inlet_pressure", (bf.VELOCITY, bf.PRESSURE, bf.PERIODIC, bf.PERIODIC)),
 ]
 
 
@@ -138,6 +141,27 @@ def test_boundary_rules_match_push_bruteforce(po, name, bc):
     assert np.allclose(o.populations(), g, atol=1e-15, rtol=0)
 
 
+def test_pressure_outlet_fixes_density_and_copies_velocity(po):
+    """Non-equilibrium extrapolation at fixed density: the outlet column ends
+    each step with density rho0 and the velocity of column nx-2, because the
+    non-equilibrium parts carry no mass and no momentum."""
+    nx, ny = 12, 9
+    f = wl.random_populations(11, nx, ny, REST, amp=0.05)
+    o = po.Oracle(nx, ny, 0.7, rho0=1.0, bc=(po.VELOCITY, po.PRESSURE, po.FREESLIP, po.FREESLIP), u_in=(0.03, 0.0))
+    o.set_populations(f)
+    for _ in range(4):
+        o.step(1)
+        rho, u, v = o.fields()
+        assert np.allclose(rho[:, nx - 1], 1.0, atol=1e-14, rtol=0)
+        assert np.allclose(u[:, nx - 1], u[:, nx - 2], atol=1e-15, rtol=0)
+        assert np.allclose(v[:, nx - 1], v[:, nx - 2], atol=1e-15, rtol=0)
+
+
+def test_pressure_outlet_needs_five_columns(po):
+    with pytest.raises(Exception):
+        po.Oracle(4, 6, 0.8, bc=(po.WALL, po.PRESSURE, po.WALL, po.WALL))
+
+
 def test_walled_box_conserves_mass(po):
     f = wl.random_populations(8, 20, 15, REST, amp=0.05)
     o = po.Oracle(20, 15, 0.9, bc=(po.WALL,) * 4)
@@ -147,14 +171,17 @@ def test_walled_box_conserves_mass(po):
     assert abs(o.populations().sum() - m0) < 1e-12 * m0
 
 
-def test_uniform_channel_is_a_fixed_point(po):
+@pytest.mark.parametrize("outlet", ["outflow", "pressure"])
+def test_uniform_channel_is_a_fixed_point(po, outlet):
     """Uniform flow at the inlet speed satisfies inlet, outlet and free-slip rules."""
     U = (0.05, 0.0)
-    o = po.Oracle(24, 12, 0.62, bc=(po.VELOCITY, po.OUTFLOW, po.FREESLIP, po.FREESLIP), u_in=U,
+    east = po.OUTFLOW if outlet == "outflow" else po.PRESSURE
+    o = po.Oracle(24, 12, 0.62, bc=(po.VELOCITY, east, po.FREESLIP, po.FREESLIP), u_in=U,
                   u_init=U)
     o.step(50)
     r, u, v = o.fields()
-    assert np.abs(r - 1).max() < 1e-14 and np.abs(u - U[0]).max() < 1e-15 and np.abs(v).max() < 1e-15
+    # a fixed point up to rounding (a wrong rule moves it by O(U^2) ~ 1e-3)
+    assert np.abs(r - 1).max() < 1e-14 and np.abs(u - U[0]).max() < 1e-14 and np.abs(v).max() < 1e-14
 
 
 # ---------------------------------------------------------------- Sec. 2.3 sweeps
