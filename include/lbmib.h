@@ -64,9 +64,14 @@ typedef enum {
                             f^eq(rho(1), u_in) + f(1) - f^eq(rho(1), u(1))           */
     LBM_BC_OUTFLOW = 4,  /* east only: populations entering from the east copy the
                             post-stream values of column nx-2                        */
-    LBM_BC_PRESSURE = 5  /* east only, nx >= 5: every population of column nx-1 is set
+    LBM_BC_PRESSURE = 5, /* east only, nx >= 5: every population of column nx-1 is set
                             to f^eq(rho0, u(nx-2)) + f(nx-2) - f^eq(rho(nx-2), u(nx-2))
                             (non-equilibrium extrapolation at fixed density, Sec. 3.2) */
+    LBM_BC_DIRICHLET = 6 /* all four sides or none: prescribed velocity u_b of every
+                            boundary node (lbm_set_boundary_velocity); each population
+                            of a boundary node is f^eq(rho(n), u_b) + f(n) - f^eq(rho(n),
+                            u(n)) with n the inward neighbour, the diagonal one at
+                            corners (non-equilibrium extrapolation, Sec. 3.1.1)       */
 } lbm_bc;
 
 /* A population entering a corner node through both an west/east and a
@@ -86,6 +91,9 @@ typedef struct {
     double mrt_s[9];      /* LBM_MRT: relaxation rates of Eq. 6 in the moment order
                              of Eq. 5 (rho, e, epsilon, j_x, q_x, j_y, q_y, p_xx,
                              p_xy); the conserved ones (0, 3, 5) are not used      */
+    int32_t delta;        /* discrete delta function of Eq. 15 used by the
+                             correction: 2 (hat), 3 (three-point), 4 or 0 (cosine,
+                             the paper's choice)                                   */
 } lbm_params;
 
 typedef enum {
@@ -120,7 +128,8 @@ typedef struct lbm_batch lbm_batch;
  * f^eq(rho0, u_init).  hip_stream is a hipStream_t (NULL: a stream the handle
  * creates and owns).  Errors: LBM_ERR_INVALID (sizes, tau, boundary pairing:
  * periodic sides come in pairs, FREESLIP only south/north, VELOCITY only west,
- * OUTFLOW/PRESSURE only east, PRESSURE with nx < 5), LBM_ERR_NOMEM. */
+ * OUTFLOW/PRESSURE only east, PRESSURE with nx < 5, DIRICHLET not on all four
+ * sides), LBM_ERR_NOMEM. */
 lbm_status lbm_create(const lbm_params* p, void* hip_stream, lbm_sim** out);
 void lbm_destroy(lbm_sim* s);
 const char* lbm_last_error(const lbm_sim* s);
@@ -141,6 +150,22 @@ const char* lbm_last_error(const lbm_sim* s);
  * density), LBM_ERR_NOMEM. */
 lbm_status ib_set_markers(lbm_sim* s, int32_t body_id, int32_t n, const double* xy,
                           const double* uv, const double* ds, const ib_body* body);
+
+/* LBM_BC_DIRICHLET simulations: velocities of the boundary nodes for the
+ * following steps.  ub holds 2 doubles (u_x, u_y) per perimeter node in the
+ * order: south row x = 0..nx-1, north row x = 0..nx-1, west column
+ * y = 1..ny-2, east column y = 1..ny-2 (2 nx + 2 (ny - 2) nodes).  Host
+ * memory, copied before return, ordered after the work already enqueued for
+ * the simulation.  Errors: LBM_ERR_INVALID (null, not a DIRICHLET box),
+ * LBM_ERR_STATE (simulation in a batch), LBM_ERR_DEVICE. */
+lbm_status lbm_set_boundary_velocity(lbm_sim* s, const double* ub);
+
+/* Replace the marker velocities uv[n][2] of FIXED body `id` (positions and
+ * stencils unchanged; for boundaries whose velocity varies in time, such as
+ * the Taylor-Green case of Sec. 3.1.1).  Host memory, copied before return.
+ * Errors: LBM_ERR_INVALID (no such fixed body, null), LBM_ERR_STATE (in a
+ * batch), LBM_ERR_DEVICE. */
+lbm_status ib_set_marker_velocities(lbm_sim* s, int32_t id, const double* uv);
 
 /* Enqueue nsteps time steps on the handle's stream (no host synchronisation). */
 lbm_status lbm_step(lbm_sim* s, int32_t nsteps);

@@ -46,6 +46,7 @@ typedef struct {
 struct or_sim {
     or_params p;
     int px, py; /* periodic axes */
+    double* ub; /* OR_DIRICHLET: boundary velocities in perimeter order */
     double *f, *fp, *df;
     unsigned char* touched;
     double Minv[81], M[81];
@@ -195,6 +196,12 @@ void or_rigid_step(double st[6], double prev[3], const double Fs[2], double Ts, 
 
 static int bc_ok(const or_params* p) {
     if (p->nx < 4 || p->ny < 4) return 0;
+    {
+        int nd = (p->bc_west == OR_DIRICHLET) + (p->bc_east == OR_DIRICHLET) + (p->bc_south == OR_DIRICHLET) +
+                 (p->bc_north == OR_DIRICHLET);
+        if (nd == 4) return 1;
+        if (nd != 0) return 0;
+    }
     if ((p->bc_west == OR_PERIODIC) != (p->bc_east == OR_PERIODIC)) return 0;
     if ((p->bc_south == OR_PERIODIC) != (p->bc_north == OR_PERIODIC)) return 0;
     if (p->bc_west != OR_PERIODIC && p->bc_west != OR_WALL && p->bc_west != OR_VELOCITY) return 0;
@@ -221,6 +228,7 @@ or_sim* or_create(const or_params* p) {
     s->df = (double*)calloc(n, sizeof(double));
     s->touched = (unsigned char*)calloc((size_t)p->nx * p->ny, 1);
     or_mrt_matrix(s->M, s->Minv);
+    if (p->bc_west == OR_DIRICHLET) s->ub = (double*)calloc((size_t)4 * (p->nx + p->ny), sizeof(double));
     double feq[9];
     or_feq(p->rho0, p->u_init[0], p->u_init[1], feq);
     for (int i = 0; i < Q; ++i)
@@ -246,7 +254,25 @@ void or_destroy(or_sim* s) {
     free(s->fp);
     free(s->df);
     free(s->touched);
+    free(s->ub);
     free(s);
+}
+
+static int perimeter_count(const or_sim* s) { return 2 * s->p.nx + 2 * (s->p.ny - 2); }
+
+int or_set_boundary_velocity(or_sim* s, const double* ub) {
+    if (!s || !s->ub || !ub) return -1;
+    memcpy(s->ub, ub, sizeof(double) * 2 * perimeter_count(s));
+    return 0;
+}
+
+int or_set_marker_velocities(or_sim* s, int id, const double* uv) {
+    if (!s || id < 0 || id >= OR_MAX_BODIES || !s->b[id].used || s->b[id].kind != OR_FIXED || !uv) return -1;
+    for (int l = 0; l < s->b[id].n; ++l) {
+        s->b[id].U[l] = uv[2 * l];
+        s->b[id].V[l] = uv[2 * l + 1];
+    }
+    return 0;
 }
 
 void or_set_populations(or_sim* s, const double* f) {
@@ -413,7 +439,9 @@ static void stream_all(or_sim* s) {
                         v = NAN; /* inlet / outlet: filled below */
                 } else {
                     int side = sy < 0 ? bs : bn;
-                    if (side == OR_WALL) {
+                    if (side == OR_DIRICHLET) {
+                        v = NAN; /* rebuilt below */
+                    } else if (side == OR_WALL) {
                         v = fpost(s, OPP[i], x, y);
                     } else { /* free slip: specular reflection of the mirrored population */
                         int mirror = -1;
@@ -431,6 +459,27 @@ static void stream_all(or_sim* s) {
         for (int y = 0; y < ny; ++y)
             for (int i = 0; i < Q; ++i)
                 if (EX[i] == -1) s->f[IDX(s, i, nx - 1, y)] = s->f[IDX(s, i, nx - 2, y)];
+    /* prescribed velocities on a box (Sec. 3.1.1, non-equilibrium
+     * extrapolation): every population of a boundary node is
+     * f^eq(rho(n), u_b) + f(n) - f^eq(rho(n), u(n)) with n the inward neighbour */
+    if (bw == OR_DIRICHLET) {
+        int k = 0;
+        for (int pass = 0; pass < 4; ++pass) {
+            int cnt = pass < 2 ? nx : ny - 2;
+            for (int t = 0; t < cnt; ++t, ++k) {
+                int x = pass == 0 || pass == 1 ? t : (pass == 2 ? 0 : nx - 1);
+                int y = pass == 0 ? 0 : (pass == 1 ? ny - 1 : t + 1);
+                int xn = x < 1 ? 1 : (x > nx - 2 ? nx - 2 : x);
+                int yn = y < 1 ? 1 : (y > ny - 2 ? ny - 2 : y);
+                double fn[9], rn, un, vn, eqb[9], eqn[9];
+                node_f(s, xn, yn, fn);
+                moments(fn, &rn, &un, &vn);
+                or_feq(rn, s->ub[2 * k], s->ub[2 * k + 1], eqb);
+                or_feq(rn, un, vn, eqn);
+                for (int i = 0; i < Q; ++i) s->f[IDX(s, i, x, y)] = eqb[i] + (fn[i] - eqn[i]);
+            }
+        }
+    }
     /* pressure outlet by non-equilibrium extrapolation (Sec. 3.2): every
      * population of column nx-1 is f^eq(rho0, u(nx-2)) + f^neq(nx-2) */
     if (be == OR_PRESSURE)

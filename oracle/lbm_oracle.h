@@ -22,7 +22,8 @@
 extern "C" {
 #endif
 
-enum { OR_PERIODIC = 0, OR_WALL = 1, OR_FREESLIP = 2, OR_VELOCITY = 3, OR_OUTFLOW = 4, OR_PRESSURE = 5 };
+enum { OR_PERIODIC = 0, OR_WALL = 1, OR_FREESLIP = 2, OR_VELOCITY = 3, OR_OUTFLOW = 4, OR_PRESSURE = 5,
+       OR_DIRICHLET = 6 };
 enum { OR_BGK = 0, OR_MRT = 1 };
 enum { OR_ROUTE_LITERAL = 0, OR_ROUTE_SIMPLIFIED = 1 };
 enum { OR_FIXED = 0, OR_FREE = 1 };
@@ -63,6 +64,15 @@ int or_set_body(or_sim* s, int id, int kind, int n, const double* xy, const doub
                 const double* ds, const double xc[2], const double U[2], double omega,
                 double theta, double radius, double rho_s);
 int or_body_markers(const or_sim* s, int id, double* xy, double* uv, double* ds);
+
+/* OR_DIRICHLET box (all four sides): velocity of every boundary node, ub[k][2]
+ * in perimeter order (south row x = 0..nx-1, north row x = 0..nx-1, west column
+ * y = 1..ny-2, east column y = 1..ny-2); used by the following steps.  Each
+ * boundary node is rebuilt by non-equilibrium extrapolation from its inward
+ * neighbour (the diagonal one at corners). */
+int or_set_boundary_velocity(or_sim* s, const double* ub);
+/* replace the marker velocities of a FIXED body (positions unchanged) */
+int or_set_marker_velocities(or_sim* s, int id, const double* uv);
 
 /* advance nsteps: collide, stream, boundary rules, N correction sweeps, rigid update */
 void or_step(or_sim* s, int nsteps);

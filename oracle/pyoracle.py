@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB = os.path.join(HERE, "liboracle.so")
 SRC = os.path.join(HERE, "lbm_oracle.c")
 
-PERIODIC, WALL, FREESLIP, VELOCITY, OUTFLOW, PRESSURE = range(6)
+PERIODIC, WALL, FREESLIP, VELOCITY, OUTFLOW, PRESSURE, DIRICHLET = range(7)
 BGK, MRT = 0, 1
 LITERAL, SIMPLIFIED = 0, 1
 FIXED, FREE = 0, 1
@@ -66,6 +66,8 @@ def lib():
                                   D, D, D]
         L.or_body_markers.argtypes = [P, ctypes.c_int, dp, dp, dp]
         L.or_step.argtypes = [P, ctypes.c_int]
+        L.or_set_boundary_velocity.argtypes = [P, dp]
+        L.or_set_marker_velocities.argtypes = [P, ctypes.c_int, dp]
         L.or_ib_only.argtypes = [P]
         L.or_forces.argtypes = [P, ctypes.c_int, dp, dp, dp, dp]
         L.or_residual_history.argtypes = [P, dp, ctypes.c_int]
@@ -157,6 +159,18 @@ class Oracle:
         xy, uv, ds = np.empty((n, 2)), np.empty((n, 2)), np.empty(n)
         lib().or_body_markers(self._h, bid, _p(xy), _p(uv), _p(ds))
         return xy, uv, ds
+
+    def set_boundary_velocity(self, ub):
+        """ub[k] = (u, v) of perimeter node k (south row, north row, west
+        column, east column; see lbm_oracle.h)."""
+        ub = _f64(ub)
+        if lib().or_set_boundary_velocity(self._h, _p(ub)) != 0:
+            raise ValueError("not a prescribed-velocity box")
+
+    def set_marker_velocities(self, bid, uv):
+        uv = _f64(uv)
+        if lib().or_set_marker_velocities(self._h, bid, _p(uv)) != 0:
+            raise ValueError("not a fixed body")
 
     def step(self, n=1):
         lib().or_step(self._h, n)

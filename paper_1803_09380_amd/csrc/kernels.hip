@@ -263,6 +263,26 @@ __global__ void __launch_bounds__(256)
         int x, y;
         perim_node(S, k, x, y);
         const int nx = S.nx, ny = S.ny;
+        if (S.bc[SIDE_W] == BC_DIRICHLET) {
+            // prescribed velocity: non-equilibrium extrapolation from the inward
+            // neighbour (diagonal at corners), which is interior on both axes
+            const int xn = x < 1 ? 1 : (x > nx - 2 ? nx - 2 : x);
+            const int yn = y < 1 ? 1 : (y > ny - 2 ? ny - 2 : y);
+            T fn[9];
+#pragma unroll
+            for (int i = 0; i < 9; ++i) fn[i] = *pc<T>(S, i, xn - ex_of(i), yn - ey_of(i), sw);
+            const T Sn = ((fn[0] + fn[1]) + (fn[2] + fn[3])) + ((fn[4] + fn[5]) + (fn[6] + fn[7])) + fn[8];
+            const T jxn = (fn[1] + fn[5] + fn[8]) - (fn[3] + fn[6] + fn[7]);
+            const T jyn = (fn[2] + fn[5] + fn[6]) - (fn[4] + fn[7] + fn[8]);
+            const T rhon = T(S.rho_base) + Sn;
+            const T jxb = rhon * T(S.ubound[2 * k]), jyb = rhon * T(S.ubound[2 * k + 1]);
+#pragma unroll
+            for (int i = 0; i < 9; ++i) {
+                const T v = heq_i<T>(i, Sn, rhon, jxb, jyb) + (fn[i] - heq_i<T>(i, Sn, rhon, jxn, jyn));
+                *loc<T>(S, i, x, y, sw) = v;
+            }
+            continue;
+        }
         if (x == 0 && S.bc[SIDE_W] == BC_VELOCITY) {
             // non-equilibrium extrapolation from column 1 (every population)
             T f1[9];
@@ -324,9 +344,18 @@ __global__ void __launch_bounds__(256)
 
 // ---------------------------------------------------------------- correction sweeps
 
+// One-dimensional discrete delta functions of Eq. 15: (a) two-point hat,
+// (b) three-point, (c) four-point cosine.  All three vanish outside the 4 x 4
+// stencil floor(X)-1 .. floor(X)+2, so one stencil layout serves every kernel.
 template <typename T>
-__device__ __forceinline__ T phi4(T r) {
+__device__ __forceinline__ T delta_w(int kind, T r) {
     const T a = fabs(r);
+    if (kind == 2) return a <= T(1) ? T(1) - a : T(0);
+    if (kind == 3) {
+        if (a < T(0.5)) return (T(1) + sqrt(T(1) - T(3) * a * a)) / T(3);
+        if (a < T(1.5)) return (T(5) - T(3) * a - sqrt(T(1) - T(3) * (T(1) - a) * (T(1) - a))) / T(6);
+        return T(0);
+    }
     return a <= T(2) ? T(0.25) * (T(1) + cos(T(M_PI) * a * T(0.5))) : T(0);
 }
 
@@ -1069,7 +1098,7 @@ __global__ void __launch_bounds__(NT)
         }
         T* phi_g = reinterpret_cast<T*>(G.m_phi);
         T* entD_g = reinterpret_cast<T*>(G.ent_D);
-        // stencil weights of Eq. 15(c): phi per marker, D per stencil entry (static plans: once)
+        // stencil weights of Eq. 15: phi per marker, D per stencil entry (static plans: once)
         const bool fresh = G.dynamic || G.flags[0] == 0;
         __syncthreads();
         if (fresh) {
@@ -1080,8 +1109,8 @@ __global__ void __launch_bounds__(NT)
                 const double fx = floor(X) - 1.0, fy = floor(Y) - 1.0;
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
-                    phi_g[g * 8 + q] = phi4<T>(T(fx + q - X));
-                    phi_g[g * 8 + 4 + q] = phi4<T>(T(fy + q - Y));
+                    phi_g[g * 8 + q] = delta_w<T>(S.delta, T(fx + q - X));
+                    phi_g[g * 8 + 4 + q] = delta_w<T>(S.delta, T(fy + q - Y));
                 }
             }
             __syncthreads();

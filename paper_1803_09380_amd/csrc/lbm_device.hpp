@@ -43,7 +43,15 @@ __host__ __device__ constexpr T weight_of(int i) {
     return i == 0 ? T(4) / T(9) : (i <= 4 ? T(1) / T(9) : T(1) / T(36));
 }
 
-enum : int32_t { BC_PERIODIC = 0, BC_WALL = 1, BC_FREESLIP = 2, BC_VELOCITY = 3, BC_OUTFLOW = 4, BC_PRESSURE = 5 };
+enum : int32_t {
+    BC_PERIODIC = 0,
+    BC_WALL = 1,
+    BC_FREESLIP = 2,
+    BC_VELOCITY = 3,
+    BC_OUTFLOW = 4,
+    BC_PRESSURE = 5,
+    BC_DIRICHLET = 6
+};
 enum : int32_t { SIDE_W = 0, SIDE_E = 1, SIDE_S = 2, SIDE_N = 3 };
 enum : int32_t { BODY_FIXED = 0, BODY_FREE = 1 };
 
@@ -70,8 +78,9 @@ struct SimDev {
     double u_in[2];
     double gravity[2];
     int32_t collision;   // 0 BGK, 1 MRT
-    int32_t pad2_;
+    int32_t delta;       // 2, 3 or 4: discrete delta function
     double mrt_s[9];     // MRT relaxation rates in the order of the moment matrix
+    const double* ubound;  // DIRICHLET box: (u, v) per perimeter node
     int32_t swapped;     // AA state of the populations (see above)
     int32_t active;      // batch: still stepping
     int64_t steps_left;  // batch: < 0 means unlimited

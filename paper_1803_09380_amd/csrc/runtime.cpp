@@ -84,7 +84,7 @@ struct lbm_sim {
     hipStream_t stream = nullptr;
     bool own_stream = false;
     std::string err;
-    DevBuf pop, desc, status, bodies, markers, tiles, bcitems, groups;
+    DevBuf pop, desc, status, bodies, markers, tiles, bcitems, groups, ubound;
     SimDev h{};                // host mirror of the descriptor
     HostBody body[LBM_MAX_BODIES];
     std::vector<Group*> grp;
@@ -152,6 +152,10 @@ int num_cus(int dev) {
 }
 
 bool bc_valid(const lbm_params* p) {
+    const int nd = (p->bc_west == LBM_BC_DIRICHLET) + (p->bc_east == LBM_BC_DIRICHLET) +
+                   (p->bc_south == LBM_BC_DIRICHLET) + (p->bc_north == LBM_BC_DIRICHLET);
+    if (nd == 4) return p->nx >= 4 && p->ny >= 4;
+    if (nd != 0) return false;
     auto ok = [](int v) { return v >= LBM_BC_PERIODIC && v <= LBM_BC_PRESSURE; };
     if (!ok(p->bc_west) || !ok(p->bc_east) || !ok(p->bc_south) || !ok(p->bc_north)) return false;
     if ((p->bc_west == LBM_BC_PERIODIC) != (p->bc_east == LBM_BC_PERIODIC)) return false;
@@ -431,6 +435,7 @@ lbm_status lbm_create(const lbm_params* p, void* hip_stream, lbm_sim** out) {
     if (!p || p->nx < 4 || p->ny < 4 || !(p->tau > 0.5) || p->ib_iters < 0 || p->ib_iters > 1000 ||
         !(p->rho0 > 0) || (p->precision != LBM_F64 && p->precision != LBM_F32_SHIFTED) || !bc_valid(p) ||
         (p->collision != LBM_BGK && p->collision != LBM_MRT) ||
+        (p->delta != 0 && p->delta != 2 && p->delta != 3 && p->delta != 4) ||
         (int64_t)p->nx * p->ny > (int64_t)1 << 30)
         return LBM_ERR_INVALID;
     lbm_sim* s = new (std::nothrow) lbm_sim();
@@ -475,6 +480,7 @@ lbm_status lbm_create(const lbm_params* p, void* hip_stream, lbm_sim** out) {
     h.gravity[0] = p->gravity[0];
     h.gravity[1] = p->gravity[1];
     h.collision = p->collision;
+    h.delta = p->delta == 0 ? 4 : p->delta;
     for (int k = 0; k < 9; ++k) h.mrt_s[k] = p->collision == LBM_MRT ? p->mrt_s[k] : 1.0 / p->tau;
     h.swapped = 0;
     h.active = 1;
@@ -494,6 +500,11 @@ lbm_status lbm_create(const lbm_params* p, void* hip_stream, lbm_sim** out) {
         return bail(LBM_ERR_DEVICE);
     h.pop = s->pop.p;
     h.status = (uint32_t*)s->status.p;
+    if (p->bc_west == LBM_BC_DIRICHLET) {
+        if (s->ubound.alloc(sizeof(double) * 2 * h.nperim) != hipSuccess) return bail(LBM_ERR_NOMEM);
+        if (hipMemsetAsync(s->ubound.p, 0, s->ubound.bytes, s->stream) != hipSuccess) return bail(LBM_ERR_DEVICE);
+        h.ubound = static_cast<const double*>(s->ubound.p);
+    }
     rc = rebuild_ib(s);
     if (rc != LBM_OK) return bail(rc);
     build_tiles(s, 0, s->tiling, s->h_tiles);
@@ -589,6 +600,33 @@ lbm_status ib_set_markers(lbm_sim* s, int32_t id, int32_t n, const double* xy, c
         s->err = msg;
     }
     return rc;
+}
+
+lbm_status lbm_set_boundary_velocity(lbm_sim* s, const double* ub) {
+    if (!s || !ub) return LBM_ERR_INVALID;
+    if (!s->ubound.p) return fail(s, LBM_ERR_INVALID, "not a prescribed-velocity box");
+    if (s->batch) return fail(s, LBM_ERR_STATE, "boundary velocities cannot change while in a batch");
+    HIPS(s, hipMemcpyAsync(s->ubound.p, ub, s->ubound.bytes, hipMemcpyHostToDevice, s->stream));
+    HIPS(s, hipStreamSynchronize(s->stream));
+    return LBM_OK;
+}
+
+lbm_status ib_set_marker_velocities(lbm_sim* s, int32_t id, const double* uv) {
+    if (!s || !uv || id < 0 || id >= LBM_MAX_BODIES) return LBM_ERR_INVALID;
+    HostBody& B = s->body[id];
+    if (!B.used || B.kind != IB_FIXED) return fail(s, LBM_ERR_INVALID, "no such fixed body");
+    if (s->batch) return fail(s, LBM_ERR_STATE, "markers cannot change while the simulation is in a batch");
+    int m0 = 0;
+    for (int b = 0; b < id; ++b)
+        if (s->body[b].used) m0 += s->body[b].n;
+    for (int l = 0; l < B.n; ++l) {
+        B.U[l] = uv[2 * l];
+        B.V[l] = uv[2 * l + 1];
+    }
+    HIPS(s, hipMemcpyAsync(s->h.mU + m0, B.U.data(), sizeof(double) * B.n, hipMemcpyHostToDevice, s->stream));
+    HIPS(s, hipMemcpyAsync(s->h.mV + m0, B.V.data(), sizeof(double) * B.n, hipMemcpyHostToDevice, s->stream));
+    HIPS(s, hipStreamSynchronize(s->stream));
+    return LBM_OK;
 }
 
 lbm_status lbm_step(lbm_sim* s, int32_t nsteps) {
@@ -729,7 +767,7 @@ lbm_status lbm_set_fields(lbm_sim* s, const double* rho, const double* ux, const
 size_t lbm_device_bytes(const lbm_sim* s) {
     if (!s) return 0;
     size_t b = s->pop.bytes + s->desc.bytes + s->status.bytes + s->bodies.bytes + s->markers.bytes + s->tiles.bytes +
-               s->bcitems.bytes + s->groups.bytes;
+               s->bcitems.bytes + s->groups.bytes + s->ubound.bytes;
     for (const Group* g : s->grp)
         b += g->node_cell.bytes + g->node_run.bytes + g->ent.bytes + g->mnode.bytes + g->flags.bytes +
              g->node4.bytes + g->ent_D.bytes + g->m_phi.bytes +

@@ -14,7 +14,7 @@ LIB_PATH = os.path.join(HERE, "liblbmib.so")
 
 OK, ERR_INVALID, ERR_NOMEM, ERR_DEVICE, ERR_UNSTABLE, ERR_STATE = range(6)
 F64, F32_SHIFTED = 0, 1
-PERIODIC, WALL, FREESLIP, VELOCITY, OUTFLOW, PRESSURE = range(6)
+PERIODIC, WALL, FREESLIP, VELOCITY, OUTFLOW, PRESSURE, DIRICHLET = range(7)
 FIXED, FREE = 0, 1
 BGK, MRT = 0, 1
 MAX_BODIES = 8
@@ -36,7 +36,7 @@ class Params(ctypes.Structure):
                 ("bc_south", ctypes.c_int32), ("bc_north", ctypes.c_int32),
                 ("u_in", ctypes.c_double * 2), ("u_init", ctypes.c_double * 2),
                 ("ib_iters", ctypes.c_int32), ("gravity", ctypes.c_double * 2),
-                ("collision", ctypes.c_int32), ("mrt_s", ctypes.c_double * 9)]
+                ("collision", ctypes.c_int32), ("mrt_s", ctypes.c_double * 9), ("delta", ctypes.c_int32)]
 
 
 class Body(ctypes.Structure):
@@ -54,6 +54,8 @@ SIGNATURES = [
     ("lbm_destroy", None, [_P]),
     ("lbm_last_error", ctypes.c_char_p, [_P]),
     ("ib_set_markers", _ST, [_P, _I32, _I32, _DP, _DP, _DP, ctypes.POINTER(Body)]),
+    ("lbm_set_boundary_velocity", _ST, [_P, _DP]),
+    ("ib_set_marker_velocities", _ST, [_P, _I32, _DP]),
     ("lbm_step", _ST, [_P, _I32]),
     ("lbm_sync", _ST, [_P]),
     ("lbm_step_count", _I64, [_P]),
@@ -134,7 +136,7 @@ class Sim:
 
     def __init__(self, nx, ny, tau, rho0=1.0, precision=F64, bc=(PERIODIC,) * 4, u_in=(0.0, 0.0),
                  u_init=(0.0, 0.0), ib_iters=10, gravity=(0.0, 0.0), stream=None, collision=BGK,
-                 mrt_s=None):
+                 mrt_s=None, delta=4):
         L = load()
         p = Params()
         p.nx, p.ny, p.tau, p.rho0, p.precision = nx, ny, tau, rho0, precision
@@ -145,6 +147,7 @@ class Sim:
         p.gravity[:] = gravity
         p.collision = collision
         p.mrt_s[:] = mrt_s if mrt_s is not None else [1.0 / tau] * 9
+        p.delta = delta
         h = _P()
         rc = L.lbm_create(ctypes.byref(p), _stream_handle(stream), ctypes.byref(h))
         if rc != OK:
@@ -153,16 +156,18 @@ class Sim:
         self.nx, self.ny, self.precision = nx, ny, precision
 
     @classmethod
-    def from_case(cls, case, precision=None, stream=None, collision=None, mrt_s=None):
+    def from_case(cls, case, precision=None, stream=None, collision=None, mrt_s=None, delta=None):
         """Create from a workloads.py case dict and set its bodies.  The
-        collision follows the case's "mrt_s" unless given."""
+        collision follows the case's "mrt_s" and the delta function the
+        case's "delta" (default 4) unless given."""
         if collision is None:
             mrt_s = case.get("mrt_s") if mrt_s is None else mrt_s
             collision = BGK if mrt_s is None else MRT
         s = cls(case["nx"], case["ny"], case["tau"], rho0=case["rho0"],
                 precision=case["precision"] if precision is None else precision, bc=case["bc"],
                 u_in=case["u_in"], u_init=case["u_init"], ib_iters=case["ib_iters"],
-                gravity=case["gravity"], stream=stream, collision=collision, mrt_s=mrt_s)
+                gravity=case["gravity"], stream=stream, collision=collision, mrt_s=mrt_s,
+                delta=case.get("delta", 4) if delta is None else delta)
         for k, b in enumerate(case["bodies"]):
             s.set_body(k, b["kind"], b["n"], xy=b["xy"], uv=b["uv"], ds=b["ds"], xc=b["xc"], U=b["U"],
                        omega=b["omega"], theta=b["theta"], radius=b["radius"], rho_s=b["rho_s"])
@@ -200,6 +205,17 @@ class Sim:
         ds = _f64(ds)
         self._check(load().ib_set_markers(self._h, bid, n, _dp(xy), _dp(uv), _dp(ds), ctypes.byref(b)),
                     "ib_set_markers")
+
+    def set_boundary_velocity(self, ub):
+        """(u, v) of every perimeter node of a DIRICHLET box, shape (2 nx + 2 (ny - 2), 2)
+        in the order south row, north row, west column, east column."""
+        ub = _f64(ub)
+        assert ub.size == 2 * (2 * self.nx + 2 * (self.ny - 2))
+        self._check(load().lbm_set_boundary_velocity(self._h, _dp(ub)), "lbm_set_boundary_velocity")
+
+    def set_marker_velocities(self, bid, uv):
+        uv = _f64(uv)
+        self._check(load().ib_set_marker_velocities(self._h, bid, _dp(uv)), "ib_set_marker_velocities")
 
     def step(self, n=1):
         self._check(load().lbm_step(self._h, n), "lbm_step")

@@ -4,6 +4,7 @@ the paper prints next to its values.
   python -m paper_1803_09380_amd.validate table1 [--re 20 40 100 200]
   python -m paper_1803_09380_amd.validate dkt
   python -m paper_1803_09380_amd.validate single [--ratios 1.0015 1.003 1.01 1.03]
+  python -m paper_1803_09380_amd.validate tgv [--sizes 10 20 40 80]
 
 Every case runs through the library (batched FP32 shifted populations unless
 --f64); diagnostics are host-side post-processing of the returned fields,
@@ -192,9 +193,50 @@ def single(lbmib, ratios, f64=False, seconds=2.0, sample=50):
             "wall_s": wall, "results": out}
 
 
+def tgv_run(sim, case, steps=None):
+    """Drive a Taylor-Green case (workloads.tgv_cylinder) on any simulation
+    object with set_fields / set_boundary_velocity / set_marker_velocities /
+    step / fields: start from the equilibrium of the analytic field at t = 0,
+    before step n + 1 set the box and marker velocities of t = n + 1, and
+    return the L2 velocity error of Eq. 31 over all nodes at the end
+    (t* = 1 by default)."""
+    steps = case["meta"]["steps"] if steps is None else steps
+    rho, ux, uy = wl.tgv_solution(case, 0.0)
+    sim.set_fields(rho, ux, uy)
+    has_body = len(case["bodies"]) > 0
+    for n in range(steps):
+        t = float(n + 1)
+        sim.set_boundary_velocity(wl.tgv_boundary(case, t))
+        if has_body:
+            sim.set_marker_velocities(0, wl.tgv_markers(case, t))
+        sim.step(1)
+    _, gx, gy = sim.fields()
+    _, ax, ay = wl.tgv_solution(case, float(steps))
+    return {"steps": steps, "l2": float(np.sqrt(np.mean((gx - ax) ** 2 + (gy - ay) ** 2))),
+            "u0": case["meta"]["u0"]}
+
+
+def tgv(lbmib, sizes, f64=True, cylinder=True):
+    """L2 error of the Taylor-Green vortex with a cylinder at t* = 1 (Sec. 3.1.1)
+    for box half-widths L (the cylinder's diameter), and the observed orders."""
+    out = {}
+    t0 = time.perf_counter()
+    for L in sizes:
+        case = wl.tgv_cylinder(L, precision=wl.F64 if f64 else wl.F32, cylinder=cylinder)
+        s = lbmib.Sim.from_case(case)
+        out[str(L)] = tgv_run(s, case)
+        s.close()
+    errs = [out[str(L)]["l2"] for L in sizes]
+    orders = [math.log(errs[k] / errs[k + 1]) / math.log(sizes[k + 1] / sizes[k]) for k in range(len(sizes) - 1)]
+    return {"case": "tgv", "cylinder": cylinder, "precision": "f64" if f64 else "f32_shifted",
+            "results": out, "orders": orders, "wall_s": time.perf_counter() - t0}
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
-    ap.add_argument("case", choices=["table1", "dkt", "single"])
+    ap.add_argument("case", choices=["table1", "dkt", "single", "tgv"])
+    ap.add_argument("--sizes", type=int, nargs="+", default=[10, 20, 40, 80])
+    ap.add_argument("--no-cylinder", action="store_true")
     ap.add_argument("--re", type=float, nargs="+", default=[20, 40, 100, 200])
     ap.add_argument("--ratios", type=float, nargs="+", default=[1.0015, 1.003, 1.01, 1.03])
     ap.add_argument("--f64", action="store_true")
@@ -217,8 +259,10 @@ def main(argv=None):
                      outlet={"pressure": wl.PRESSURE, "outflow": wl.OUTFLOW}[args.outlet])
     elif args.case == "dkt":
         out = dkt(lbmib, f64=args.f64, seconds=args.seconds or 4.0)
-    else:
+    elif args.case == "single":
         out = single(lbmib, args.ratios, f64=args.f64, seconds=args.seconds or 2.0)
+    else:
+        out = tgv(lbmib, args.sizes, f64=True, cylinder=not args.no_cylinder)
     print(json.dumps(out), flush=True)
     return 0
 

@@ -23,7 +23,7 @@ import math
 
 import numpy as np
 
-PERIODIC, WALL, FREESLIP, VELOCITY, OUTFLOW, PRESSURE = range(6)
+PERIODIC, WALL, FREESLIP, VELOCITY, OUTFLOW, PRESSURE, DIRICHLET = range(7)
 FIXED, FREE = 0, 1
 F64, F32 = 0, 1
 
@@ -172,6 +172,82 @@ def dkt_pair(precision=F32, ib_iters=10):
     return dict(name="dkt_200x800", nx=nx, ny=ny, tau=0.8, rho0=1.0, bc=(WALL,) * 4, u_in=(0.0, 0.0),
                 u_init=(0.0, 0.0), ib_iters=ib_iters, precision=precision, gravity=(0.0, -lu["g_lu"]),
                 bodies=bodies, mrt_s=None, meta=dict(D=D, units=lu))
+
+
+def perimeter_nodes(nx, ny):
+    """(x, y) of the perimeter nodes of a box in the order the prescribed
+    velocities are given: south row, north row, west column, east column."""
+    xs = list(range(nx))
+    pts = [(x, 0) for x in xs] + [(x, ny - 1) for x in xs]
+    pts += [(0, y) for y in range(1, ny - 1)] + [(nx - 1, y) for y in range(1, ny - 1)]
+    return np.array(pts, dtype=np.float64)
+
+
+def tgv_cylinder(L, precision=F64, tau=0.65, Re=10.0, ib_iters=10, cylinder=True):
+    """Taylor-Green vortex with an artificial cylinder (Sec. 3.1.1).
+
+    Box [-L, L]^2 with 2L + 1 nodes per side (node i at x = -L + i, the box
+    edges are boundary nodes), tau = 0.65, Re = u0 L / nu = 10, a cylinder of
+    diameter L at the centre whose markers move with the analytic velocity,
+    the box's nodes held at the analytic velocity by non-equilibrium
+    extrapolation.  The analytic solution is tgv_solution(); the run ends at
+    t* = t u0 / L = 1, i.e. after L / u0 steps."""
+    n = 2 * int(L) + 1
+    nu = (tau - 0.5) / 3.0
+    u0 = Re * nu / L
+    c = float(L)  # lattice coordinate of the centre
+    bodies = []
+    if cylinder:
+        R = L / 2.0
+        nm = int(round(math.pi * L))
+        xy = circle_markers(c, c, R, nm)
+        bodies.append(dict(kind=FIXED, n=nm, xy=xy, uv=tgv_velocity_at(xy - c, 0.0, u0, L, nu),
+                           ds=np.full(nm, 2 * math.pi * R / nm), xc=(c, c), U=(0.0, 0.0), omega=0.0,
+                           theta=0.0, radius=R, rho_s=0.0))
+    return dict(name="tgv_L%d" % L, nx=n, ny=n, tau=tau, rho0=1.0, bc=(DIRICHLET,) * 4, u_in=(0.0, 0.0),
+                u_init=(0.0, 0.0), ib_iters=ib_iters, precision=precision, gravity=(0.0, 0.0), bodies=bodies,
+                mrt_s=None, meta=dict(L=L, u0=u0, nu=nu, centre=c, steps=int(round(L / u0))))
+
+
+def tgv_velocity_at(p, t, u0, L, nu):
+    """Analytic TGV velocity (Eq. 30, with u_y of the sign that makes the
+    field divergence-free) at points p[:, 2] measured from the box centre."""
+    k = math.pi / L
+    dec = math.exp(-2.0 * nu * k * k * t)
+    x, y = p[:, 0], p[:, 1]
+    return np.stack([-u0 * np.cos(k * x) * np.sin(k * y) * dec, u0 * np.sin(k * x) * np.cos(k * y) * dec], axis=1)
+
+
+def tgv_solution(case, t):
+    """(rho, u_x, u_y) of the analytic TGV on the case's nodes at time t:
+    rho = rho0 - (3 u0^2 / 4)(cos 2kx + cos 2ky) exp(-4 nu k^2 t), the pressure
+    of the Taylor-Green flow over c_s^2 = 1/3."""
+    m = case["meta"]
+    L, u0, nu, c = m["L"], m["u0"], m["nu"], m["centre"]
+    n = case["nx"]
+    y, x = np.mgrid[0:n, 0:n].astype(np.float64)
+    x -= c
+    y -= c
+    k = math.pi / L
+    dec = math.exp(-2.0 * nu * k * k * t)
+    ux = -u0 * np.cos(k * x) * np.sin(k * y) * dec
+    uy = u0 * np.sin(k * x) * np.cos(k * y) * dec
+    rho = case["rho0"] - 0.75 * u0 * u0 * (np.cos(2 * k * x) + np.cos(2 * k * y)) * dec * dec
+    return rho, ux, uy
+
+
+def tgv_boundary(case, t):
+    """Analytic velocities of the perimeter nodes at time t."""
+    m = case["meta"]
+    p = perimeter_nodes(case["nx"], case["ny"]) - m["centre"]
+    return tgv_velocity_at(p, t, m["u0"], m["L"], m["nu"])
+
+
+def tgv_markers(case, t):
+    """Analytic velocities of the cylinder's markers at time t."""
+    m = case["meta"]
+    b = case["bodies"][0]
+    return tgv_velocity_at(b["xy"] - m["centre"], t, m["u0"], m["L"], m["nu"])
 
 
 def batch(seed=0, count=256, precision=F32):

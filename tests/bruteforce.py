@@ -99,10 +99,10 @@ def dense_sweeps(f, markers, U, ds, iters):
     return g.reshape(9, ny, nx), F
 
 
-PERIODIC, WALL, FREESLIP, VELOCITY, OUTFLOW, PRESSURE = range(6)
+PERIODIC, WALL, FREESLIP, VELOCITY, OUTFLOW, PRESSURE, DIRICHLET = range(7)
 
 
-def general_step(f, tau, bc, u_in=(0.0, 0.0), rho_out=1.0):
+def general_step(f, tau, bc, u_in=(0.0, 0.0), rho_out=1.0, ub=None):
     """One BGK step written in push form with explicit loops (tiny grids only).
 
     bc = (west, east, south, north).  Each post-collision population moves to
@@ -116,7 +116,10 @@ def general_step(f, tau, bc, u_in=(0.0, 0.0), rho_out=1.0):
       VELOCITY (west, non-equilibrium extrapolation): every population of column 0
       becomes f^eq(rho(1), U_in) + f(1) - f^eq(rho(1), u(1));
       PRESSURE (east, non-equilibrium extrapolation): every population of column
-      nx-1 becomes f^eq(rho_out, u(nx-2)) + f(nx-2) - f^eq(rho(nx-2), u(nx-2))."""
+      nx-1 becomes f^eq(rho_out, u(nx-2)) + f(nx-2) - f^eq(rho(nx-2), u(nx-2));
+      DIRICHLET (all four sides): every population of boundary node b becomes
+      f^eq(rho(n), ub[b]) + f(n) - f^eq(rho(n), u(n)), n = the nearest interior
+      node (diagonal at corners); ub is a dict {(x, y): (u, v)}."""
     rho, ux, uy = moments(f)
     fp = f - (f - equilibrium(rho, ux, uy)) / tau
     ny, nx = f.shape[1:]
@@ -146,10 +149,20 @@ def general_step(f, tau, bc, u_in=(0.0, 0.0), rho_out=1.0):
                         out[OPPOSITE[i], y, x] = v
                     elif side == FREESLIP:
                         out[mirror[i], y, tx] = v
+                    # DIRICHLET: dropped, the node is rebuilt below
     if east == OUTFLOW:
         for i in range(9):
             if E[i, 0] == -1:
                 out[i, :, nx - 1] = out[i, :, nx - 2]
+    if west == DIRICHLET:
+        new = {}
+        for (x, y), (bu, bv) in ub.items():
+            xn, yn = min(max(x, 1), nx - 2), min(max(y, 1), ny - 2)
+            fn = out[:, yn, xn]
+            r, u, v = moments(fn)
+            new[(x, y)] = equilibrium(r, bu, bv) + fn - equilibrium(r, u, v)
+        for (x, y), val in new.items():
+            out[:, y, x] = val
     if east == PRESSURE:
         r2, u2, v2 = moments(out[:, :, nx - 2])
         out[:, :, nx - 1] = (equilibrium(np.full_like(r2, rho_out), u2, v2)

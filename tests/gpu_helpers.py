@@ -7,12 +7,14 @@ from paper_1803_09380_amd import lbmib
 from paper_1803_09380_amd import workloads as wl
 
 
-def oracle_from_case(case, route=po.SIMPLIFIED, mrt_s=None):
-    """mrt_s: None for the case's own collision, else the nine MRT rates."""
+def oracle_from_case(case, route=po.SIMPLIFIED, mrt_s=None, delta=None):
+    """mrt_s: None for the case's own collision, else the nine MRT rates;
+    delta: None for the case's own delta function (default 4)."""
     mrt_s = case.get("mrt_s") if mrt_s is None else mrt_s
+    delta = case.get("delta", 4) if delta is None else delta
     o = po.Oracle(case["nx"], case["ny"], case["tau"], rho0=case["rho0"], bc=case["bc"], u_in=case["u_in"],
                   u_init=case["u_init"], ib_iters=case["ib_iters"], route=route, gravity=case["gravity"],
-                  collision=po.BGK if mrt_s is None else po.MRT, mrt_s=mrt_s)
+                  collision=po.BGK if mrt_s is None else po.MRT, mrt_s=mrt_s, delta=delta)
     for k, b in enumerate(case["bodies"]):
         if b["kind"] == wl.FREE:
             o.set_body(k, po.FREE, b["n"], xc=b["xc"], U=b["U"], omega=b["omega"], theta=b["theta"],
@@ -23,9 +25,10 @@ def oracle_from_case(case, route=po.SIMPLIFIED, mrt_s=None):
     return o
 
 
-def gpu_from_case(case, precision=None, mrt_s=None):
-    """mrt_s: None for the case's own collision, else the nine MRT rates."""
-    return lbmib.Sim.from_case(case, precision=precision, mrt_s=mrt_s)
+def gpu_from_case(case, precision=None, mrt_s=None, delta=None):
+    """mrt_s: None for the case's own collision, else the nine MRT rates;
+    delta: None for the case's own delta function."""
+    return lbmib.Sim.from_case(case, precision=precision, mrt_s=mrt_s, delta=delta)
 
 
 def rel_max(a, b):

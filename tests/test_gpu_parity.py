@@ -92,13 +92,13 @@ def test_single_marker_sweeps_f64():
     assert rel_max(g.populations(), o.populations()) < 1e-12
 
 
-def _compare_case(case, steps, tol_f=1e-12, tol_force=1e-12, check_state=False, mrt_s=None):
+def _compare_case(case, steps, tol_f=1e-12, tol_force=1e-12, check_state=False, mrt_s=None, delta=None):
     """Fields within tol_f (max-norm relative).  Force and torque are sums over
     N sweeps and all markers whose terms largely cancel on closed bodies, so
     their bound is relative to the body's force scale S = |F| + |T|/R (a
     summation error bound), not to the net value."""
-    o = oracle_from_case(case, mrt_s=mrt_s)
-    g = gpu_from_case(case, mrt_s=mrt_s)
+    o = oracle_from_case(case, mrt_s=mrt_s, delta=delta)
+    g = gpu_from_case(case, mrt_s=mrt_s, delta=delta)
     o.step(steps)
     g.step(steps)
     po_, pg_ = o.populations(), g.populations()
@@ -293,3 +293,71 @@ def test_dkt_pair_f64():
     """Sec. 3.3.2 geometry (200 x 800 box, two particles, strong gravity)."""
     _say("dkt pair f64, 120 steps")
     _compare_case(wl.dkt_pair(precision=wl.F64), 120, check_state=True)
+
+
+# ---------------------------------------------------------------- delta functions of Eq. 15
+
+@pytest.mark.parametrize("delta", [2, 3])
+def test_other_delta_functions_couette_f64(delta):
+    _say("couette 48 delta=%d f64, 200 steps" % delta)
+    _compare_case(wl.couette(48), 200, delta=delta)
+
+
+@pytest.mark.parametrize("delta", [2, 3])
+def test_other_delta_functions_free_particles_f64(delta):
+    _say("two settling particles delta=%d f64, 120 steps" % delta)
+    case = wl.settling(nx=60, ny=140, D=12.0, density_ratio=1.3, two=True, precision=wl.F64,
+                       lower=(30.0, 70.0), u_ref=0.05)
+    _compare_case(case, 120, check_state=True, delta=delta)
+
+
+@pytest.mark.parametrize("delta", [2, 3])
+def test_other_delta_functions_fp32_cylinder(delta):
+    _say("cylinder 160x80 delta=%d f32 vs oracle, 600 steps" % delta)
+    case = wl.cylinder(nx=160, ny=80, D=16.0, centre=(40.0, 40.0), U=0.05, Re=20.0)
+    o = oracle_from_case(case, delta=delta)
+    g = gpu_from_case(case, precision=lbmib.F32_SHIFTED, delta=delta)
+    o.step(600)
+    g.step(600)
+    assert velocity_rel(g.fields(), o.fields()) < 1e-5
+    Fo, Fg = o.forces(0)[0], g.forces(0)[0]
+    assert abs(Fg[0] - Fo[0]) / abs(Fo[0]) < 1e-3
+
+
+def test_unknown_delta_is_rejected():
+    with pytest.raises(lbmib.LbmError):
+        lbmib.Sim(16, 16, 0.8, delta=5)
+
+
+# ---------------------------------------------------------------- Taylor-Green box (Sec. 3.1.1)
+
+def _tgv_pair(L, precision):
+    from paper_1803_09380_amd import validate as val
+    case = wl.tgv_cylinder(L)
+    o = oracle_from_case(case)
+    g = gpu_from_case(case, precision=precision)
+    ro = val.tgv_run(o, case)
+    rg = val.tgv_run(g, case)
+    return o, g, ro, rg
+
+
+def test_tgv_cylinder_f64():
+    _say("tgv L=10 with cylinder f64, t* = 1")
+    o, g, ro, rg = _tgv_pair(10, lbmib.F64)
+    assert rel_max(g.populations(), o.populations()) < 1e-12
+    assert abs(rg["l2"] - ro["l2"]) <= 1e-9 * ro["l2"]
+
+
+def test_tgv_cylinder_fp32():
+    _say("tgv L=16 with cylinder f32, t* = 1")
+    o, g, ro, rg = _tgv_pair(16, lbmib.F32_SHIFTED)
+    assert velocity_rel(g.fields(), o.fields()) < 1e-5
+    assert abs(rg["l2"] - ro["l2"]) <= 1e-2 * ro["l2"]
+
+
+def test_dirichlet_box_needs_all_four_sides():
+    with pytest.raises(lbmib.LbmError):
+        lbmib.Sim(16, 16, 0.8, bc=(lbmib.DIRICHLET, lbmib.DIRICHLET, lbmib.WALL, lbmib.WALL))
+    s = lbmib.Sim(16, 16, 0.8, bc=(lbmib.WALL,) * 4)
+    with pytest.raises(lbmib.LbmError):
+        s.set_boundary_velocity(np.zeros((2 * 16 + 2 * 14, 2)))

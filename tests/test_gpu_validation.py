@@ -82,3 +82,13 @@ def test_single_particle_moves_to_the_centre_line():
     assert abs(out["1.03"]["final_offset_over_w"]) < 0.05
     assert out["1.03"]["max_crossing_over_w"] > 0.0  # crosses the centre line
     assert out["1.03"]["lateral_velocity_sign_changes"] >= 2
+
+
+def test_taylor_green_with_cylinder_order():
+    """Sec. 3.1.1: the L2 velocity error at t* = 1 falls at nearly third order
+    over L = 10 .. 80 (u0 = Re nu / L, so a second-order relative error gives a
+    third-order absolute one)."""
+    _say("tgv with cylinder, L = 10, 20, 40, 80, f64")
+    out = val.tgv(lbmib, [10, 20, 40, 80])
+    _say("  %s orders %s" % ({k: v["l2"] for k, v in out["results"].items()}, out["orders"]))
+    assert all(o > 2.7 for o in out["orders"]), out["orders"]

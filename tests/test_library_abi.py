@@ -42,8 +42,8 @@ def test_binding_covers_the_header():
 
 def test_binding_struct_layouts():
     # lbm_params: 2 int32, 2 double, 5 int32 (+pad), 4 double, int32 (+pad),
-    # 2 double, int32 (+pad), 9 double
-    assert ctypes.sizeof(lbmib.Params) == 184
+    # 2 double, int32 (+pad), 9 double, int32 (+pad)
+    assert ctypes.sizeof(lbmib.Params) == 192
     assert ctypes.sizeof(lbmib.Body) == 72
 
 

@@ -162,6 +162,48 @@ def test_pressure_outlet_needs_five_columns(po):
         po.Oracle(4, 6, 0.8, bc=(po.WALL, po.PRESSURE, po.WALL, po.WALL))
 
 
+def test_prescribed_velocity_box_matches_push_bruteforce(po):
+    nx, ny = 7, 6
+    f = wl.random_populations(13, nx, ny, REST, amp=0.05)
+    pts = wl.perimeter_nodes(nx, ny).astype(int)
+    rng = np.random.default_rng(5)
+    ubv = rng.normal(0, 0.03, size=(len(pts), 2))
+    o = po.Oracle(nx, ny, 0.77, bc=(po.DIRICHLET,) * 4)
+    o.set_populations(f)
+    o.set_boundary_velocity(ubv)
+    ub = {(int(x), int(y)): tuple(v) for (x, y), v in zip(pts, ubv)}
+    g = f.copy()
+    for _ in range(3):
+        o.step(1)
+        g = bf.general_step(g, 0.77, (bf.DIRICHLET,) * 4, ub=ub)
+    assert np.allclose(o.populations(), g, atol=1e-15, rtol=0)
+    # the boundary nodes carry the prescribed velocities exactly
+    _, u, v = o.fields()
+    assert np.allclose(u[pts[:, 1], pts[:, 0]], ubv[:, 0], atol=1e-15, rtol=0)
+    assert np.allclose(v[pts[:, 1], pts[:, 0]], ubv[:, 1], atol=1e-15, rtol=0)
+
+
+def _tgv_error(po, L, cylinder):
+    from paper_1803_09380_amd import validate as val
+    case = wl.tgv_cylinder(L, cylinder=cylinder)
+    o = po.Oracle(case["nx"], case["ny"], case["tau"], bc=case["bc"])
+    if cylinder:
+        b = case["bodies"][0]
+        o.set_body(0, po.FIXED, b["n"], xy=b["xy"], uv=b["uv"], ds=b["ds"])
+    return val.tgv_run(o, case)["l2"]
+
+
+@pytest.mark.parametrize("cylinder", [False, True])
+def test_taylor_green_error_falls_at_third_order(po, cylinder):
+    """Sec. 3.1.1: at fixed Re and tau, u0 = Re nu / L, so the absolute L2 error
+    of Eq. 31 is u0 times a relative error; a second-order relative error makes
+    the absolute one fall as L^-3.  Without the cylinder this checks the box
+    boundary rule; with it, the paper's observation of nearly third order."""
+    errs = [_tgv_error(po, L, cylinder=cylinder) for L in (8, 16, 32)]
+    orders = [math.log2(errs[k] / errs[k + 1]) for k in range(2)]
+    assert all(o > 2.7 for o in orders), (errs, orders)
+
+
 def test_walled_box_conserves_mass(po):
     f = wl.random_populations(8, 20, 15, REST, amp=0.05)
     o = po.Oracle(20, 15, 0.9, bc=(po.WALL,) * 4)
