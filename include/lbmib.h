@@ -198,8 +198,8 @@ size_t lbm_device_bytes(const lbm_sim* s);
 
 /* ---- batching: many simulations of one precision advanced together ----
  * A batch owns no simulation state: admitted handles keep their device memory.
- * Each step is a fixed sequence of persistent kernels over device-resident work
- * tables (cells of every admitted simulation, boundary nodes, body groups),
+ * Each step is a fixed sequence of kernels over device-resident work tables
+ * (cells of every admitted simulation, boundary nodes, body groups),
  * replayed from a HIP graph; admission and retirement rewrite the tables between
  * replays.  Results of a simulation do not depend on what else is in the batch. */
 

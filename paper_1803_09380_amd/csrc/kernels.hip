@@ -19,11 +19,12 @@
 
 namespace lbmib {
 
-// Tilings 6..11 repeat 0..5 with non-temporal loads and stores (streamed
+// Tilings 8..15 repeat 0..7 with non-temporal loads and stores (streamed
 // data is not kept in the caches).  None of them changes the arithmetic.
-const Tiling kTilings[kNumTilings] = {{64, 4, 1, 0},  {64, 4, 2, 0}, {128, 2, 2, 0}, {256, 1, 2, 0},
-                                      {256, 1, 4, 0}, {64, 4, 4, 0}, {64, 4, 1, 1},  {64, 4, 2, 1},
-                                      {128, 2, 2, 1}, {256, 1, 2, 1}, {256, 1, 4, 1}, {64, 4, 4, 1}};
+const Tiling kTilings[kNumTilings] = {
+    {64, 4, 1, 0}, {64, 4, 2, 0}, {128, 2, 2, 0}, {256, 1, 2, 0}, {256, 1, 4, 0}, {64, 4, 4, 0},
+    {256, 1, 1, 0}, {128, 2, 1, 0}, {64, 4, 1, 1}, {64, 4, 2, 1}, {128, 2, 2, 1}, {256, 1, 2, 1},
+    {256, 1, 4, 1}, {64, 4, 4, 1}, {256, 1, 1, 1}, {128, 2, 1, 1}};
 
 template <bool NTMP, typename T>
 __device__ __forceinline__ T ldg(const T* p) {
@@ -1355,12 +1356,16 @@ static hipError_t sweep_tt(int tiling, const SimDev* sims, const int4* tiles, co
         case 3: return sweep_t<T, 256, 1, 2, false>(sims, tiles, hdr, ntiles, grid, parity, st);
         case 4: return sweep_t<T, 256, 1, 4, false>(sims, tiles, hdr, ntiles, grid, parity, st);
         case 5: return sweep_t<T, 64, 4, 4, false>(sims, tiles, hdr, ntiles, grid, parity, st);
-        case 6: return sweep_t<T, 64, 4, 1, true>(sims, tiles, hdr, ntiles, grid, parity, st);
-        case 7: return sweep_t<T, 64, 4, 2, true>(sims, tiles, hdr, ntiles, grid, parity, st);
-        case 8: return sweep_t<T, 128, 2, 2, true>(sims, tiles, hdr, ntiles, grid, parity, st);
-        case 9: return sweep_t<T, 256, 1, 2, true>(sims, tiles, hdr, ntiles, grid, parity, st);
-        case 10: return sweep_t<T, 256, 1, 4, true>(sims, tiles, hdr, ntiles, grid, parity, st);
-        case 11: return sweep_t<T, 64, 4, 4, true>(sims, tiles, hdr, ntiles, grid, parity, st);
+        case 6: return sweep_t<T, 256, 1, 1, false>(sims, tiles, hdr, ntiles, grid, parity, st);
+        case 7: return sweep_t<T, 128, 2, 1, false>(sims, tiles, hdr, ntiles, grid, parity, st);
+        case 8: return sweep_t<T, 64, 4, 1, true>(sims, tiles, hdr, ntiles, grid, parity, st);
+        case 9: return sweep_t<T, 64, 4, 2, true>(sims, tiles, hdr, ntiles, grid, parity, st);
+        case 10: return sweep_t<T, 128, 2, 2, true>(sims, tiles, hdr, ntiles, grid, parity, st);
+        case 11: return sweep_t<T, 256, 1, 2, true>(sims, tiles, hdr, ntiles, grid, parity, st);
+        case 12: return sweep_t<T, 256, 1, 4, true>(sims, tiles, hdr, ntiles, grid, parity, st);
+        case 13: return sweep_t<T, 64, 4, 4, true>(sims, tiles, hdr, ntiles, grid, parity, st);
+        case 14: return sweep_t<T, 256, 1, 1, true>(sims, tiles, hdr, ntiles, grid, parity, st);
+        case 15: return sweep_t<T, 128, 2, 1, true>(sims, tiles, hdr, ntiles, grid, parity, st);
         default: return hipErrorInvalidValue;
     }
 }

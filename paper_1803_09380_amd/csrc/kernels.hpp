@@ -11,7 +11,7 @@ namespace lbmib {
 struct Tiling {
     int tx, ty, rpt, nontemporal;
 };
-constexpr int kNumTilings = 12;
+constexpr int kNumTilings = 16;
 extern const Tiling kTilings[kNumTilings];
 
 // Entries sorted in LDS when a plan is rebuilt on the device (16 per marker).

@@ -7,7 +7,9 @@
 // without free bodies are built here once, when markers are set; groups with
 // free bodies rebuild theirs on the device every step.  A batch concatenates
 // the work tables of its admitted simulations into device-resident tables and
-// replays captured HIP graphs of persistent kernels that read those tables.
+// replays captured HIP graphs of kernels that read their work counts from
+// those tables (one workgroup per sweep tile, persistent workgroups for the
+// boundary chunks and body groups).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -28,7 +30,7 @@ using namespace lbmib;
 
 namespace {
 
-constexpr int kTileDefault = 1;
+constexpr int kTileDefault = 11;  // 256 x 1 threads, 2 rows each, non-temporal
 
 template <typename... A>
 std::string fmt(const char* f, A... a) {
@@ -879,6 +881,18 @@ lbm_status upload_tables(lbm_batch* b) {
     }
     h.xcd_start[8] = (int)tiles.size();
     h.ntiles = (int)tiles.size();
+    // One workgroup per tile (workgroup b runs on XCD b mod 8 and takes that
+    // XCD's tile b / 8): with a persistent grid the tiles of late-starting
+    // workgroups made the tail of every sweep.  Extra workgroups exit at once,
+    // so the grid only grows (with headroom) and captured graphs stay valid
+    // while tiles come and go.
+    int per_xcd_max = 1;
+    for (int x = 0; x < 8; ++x) per_xcd_max = std::max(per_xcd_max, h.xcd_start[x + 1] - h.xcd_start[x]);
+    bool grid_changed = false;
+    if (8 * per_xcd_max > b->grid_sweep) {
+        b->grid_sweep = 8 * (per_xcd_max + per_xcd_max / 4);
+        grid_changed = true;
+    }
     bool grew = false;
     HIPB(b, ensure_cap<SimDev>(b->d_sims, b->cap_sims, sims.size(), grew));
     HIPB(b, ensure_cap<int4>(b->d_tiles, b->cap_tiles, tiles.size(), grew));
@@ -888,7 +902,7 @@ lbm_status upload_tables(lbm_batch* b) {
         HIPB(b, b->d_hdr.alloc(sizeof(BatchHeader)));
         grew = true;
     }
-    if (grew || variant_changed) drop_graphs(b);
+    if (grew || variant_changed || grid_changed) drop_graphs(b);
     if (!sims.empty()) HIPB(b, hipMemcpyAsync(b->d_sims.p, sims.data(), sizeof(SimDev) * sims.size(), hipMemcpyHostToDevice, b->stream));
     if (!tiles.empty()) HIPB(b, hipMemcpyAsync(b->d_tiles.p, tiles.data(), sizeof(int4) * tiles.size(), hipMemcpyHostToDevice, b->stream));
     if (!bc.empty()) HIPB(b, hipMemcpyAsync(b->d_bc.p, bc.data(), sizeof(int2) * bc.size(), hipMemcpyHostToDevice, b->stream));
@@ -951,7 +965,7 @@ lbm_status lbm_batch_create(int32_t precision, size_t budget, void* hip_stream, 
         b->own_stream = true;
     }
     const int ncu = num_cus(b->device);
-    b->grid_sweep = ncu * 8;
+    b->grid_sweep = 0;  // set from the tile count by upload_tables
     b->grid_bc = ncu * 8;
     b->grid_ib = ncu * 2;
     if (upload_tables(b) != LBM_OK) {
