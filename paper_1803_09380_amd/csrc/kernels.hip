@@ -26,19 +26,44 @@ const Tiling kTilings[kNumTilings] = {
     {256, 1, 1, 0}, {128, 2, 1, 0}, {64, 4, 1, 1}, {64, 4, 2, 1}, {128, 2, 2, 1}, {256, 1, 2, 1},
     {256, 1, 4, 1}, {64, 4, 4, 1}, {256, 1, 1, 1}, {128, 2, 1, 1}};
 
+// Typed accessors: LDS-resident arrays are read with ds_read, device memory
+// with global loads and stores (never the flat path of generic pointers, whose
+// counters also hold back LDS waits).
+#define LBM_AS3 __attribute__((address_space(3)))
+#define LBM_AS1 __attribute__((address_space(1)))
+template <bool LDS, typename T>
+__device__ __forceinline__ T ldm(const T* p) {
+    if constexpr (LDS)
+        return *(const LBM_AS3 T*)(p);
+    else
+        return *(const LBM_AS1 T*)(p);
+}
+template <bool LDS, typename T>
+__device__ __forceinline__ void stm(T* p, T v) {
+    if constexpr (LDS)
+        *(LBM_AS3 T*)(p) = v;
+    else
+        *(LBM_AS1 T*)(p) = v;
+}
+
+// device-memory accesses of the sweep, optionally non-temporal
 template <bool NTMP, typename T>
-__device__ __forceinline__ T ldg(const T* p) {
+__device__ __forceinline__ T ldg(const LBM_AS1 T* p) {
     if constexpr (NTMP)
         return __builtin_nontemporal_load(p);
     else
         return *p;
 }
 template <bool NTMP, typename T>
-__device__ __forceinline__ void stg(T* p, T v) {
+__device__ __forceinline__ void stg(LBM_AS1 T* p, T v) {
     if constexpr (NTMP)
         __builtin_nontemporal_store(v, p);
     else
         *p = v;
+}
+template <typename T>
+__device__ __forceinline__ LBM_AS1 T* gptr(T* p) {
+    return (LBM_AS1 T*)p;
 }
 
 // ---------------------------------------------------------------- collision
@@ -143,7 +168,7 @@ __global__ void __launch_bounds__(TX* TY)
         const int nx = S.nx, ny = S.ny, px = S.px, py = S.py;
         const int64_t pl = S.plane;
         const int pitch = S.pitch;
-        T* __restrict__ P = reinterpret_cast<T*>(S.pop) + S.xoff + pitch;  // (x=0, y=0)
+        LBM_AS1 T* __restrict__ P = gptr(reinterpret_cast<T*>(S.pop)) + S.xoff + pitch;  // (x=0, y=0)
         const T rho_base = T(S.rho_base), omega = T(S.omega);
         const bool use_mrt = S.collision != 0;
         T rate[9];
@@ -236,10 +261,10 @@ __device__ __forceinline__ void perim_node(const SimDev& S, int k, int& x, int& 
 template <typename T>
 __device__ __forceinline__ T post_stream(const SimDev& S, int i, int x, int y, int sw) {
     const int sx = wrap(x - ex_of(i), S.nx, S.px), sy = wrap(y - ey_of(i), S.ny, S.py);
-    if (sy >= 0 && sy < S.ny) return *pc<T>(S, i, sx, sy, sw);
+    if (sy >= 0 && sy < S.ny) return ldm<false>(pc<T>(S, i, sx, sy, sw));
     const int side = sy < 0 ? S.bc[SIDE_S] : S.bc[SIDE_N];
-    if (side == BC_WALL) return *pc<T>(S, opp_of(i), x, y, sw);
-    return *pc<T>(S, mirror_y(i), wrap(x - ex_of(i), S.nx, S.px), y, sw);
+    if (side == BC_WALL) return ldm<false>(pc<T>(S, opp_of(i), x, y, sw));
+    return ldm<false>(pc<T>(S, mirror_y(i), wrap(x - ex_of(i), S.nx, S.px), y, sw));
 }
 
 // h^eq_i for shifted sum S (= rho - rho_base), density rho and momentum j.
@@ -271,16 +296,16 @@ __global__ void __launch_bounds__(256)
             const int yn = y < 1 ? 1 : (y > ny - 2 ? ny - 2 : y);
             T fn[9];
 #pragma unroll
-            for (int i = 0; i < 9; ++i) fn[i] = *pc<T>(S, i, xn - ex_of(i), yn - ey_of(i), sw);
+            for (int i = 0; i < 9; ++i) fn[i] = ldm<false>(pc<T>(S, i, xn - ex_of(i), yn - ey_of(i), sw));
             const T Sn = ((fn[0] + fn[1]) + (fn[2] + fn[3])) + ((fn[4] + fn[5]) + (fn[6] + fn[7])) + fn[8];
             const T jxn = (fn[1] + fn[5] + fn[8]) - (fn[3] + fn[6] + fn[7]);
             const T jyn = (fn[2] + fn[5] + fn[6]) - (fn[4] + fn[7] + fn[8]);
             const T rhon = T(S.rho_base) + Sn;
-            const T jxb = rhon * T(S.ubound[2 * k]), jyb = rhon * T(S.ubound[2 * k + 1]);
+            const T jxb = rhon * T(ldm<false>(S.ubound + 2 * k)), jyb = rhon * T(ldm<false>(S.ubound + 2 * k + 1));
 #pragma unroll
             for (int i = 0; i < 9; ++i) {
                 const T v = heq_i<T>(i, Sn, rhon, jxb, jyb) + (fn[i] - heq_i<T>(i, Sn, rhon, jxn, jyn));
-                *loc<T>(S, i, x, y, sw) = v;
+                stm<false>(loc<T>(S, i, x, y, sw), v);
             }
             continue;
         }
@@ -297,7 +322,7 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
             for (int i = 0; i < 9; ++i) {
                 const T v = heq_i<T>(i, S1, rho1, jxb, jyb) + (f1[i] - heq_i<T>(i, S1, rho1, jx1, jy1));
-                *loc<T>(S, i, 0, y, sw) = v;
+                stm<false>(loc<T>(S, i, 0, y, sw), v);
             }
             continue;
         }
@@ -315,7 +340,7 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
             for (int i = 0; i < 9; ++i) {
                 const T v = heq_i<T>(i, Sb, rhob, jxb, jyb) + (f2[i] - heq_i<T>(i, S2, rho2, jx2, jy2));
-                *loc<T>(S, i, nx - 1, y, sw) = v;
+                stm<false>(loc<T>(S, i, nx - 1, y, sw), v);
             }
             continue;
         }
@@ -328,17 +353,17 @@ __global__ void __launch_bounds__(256)
             if (outx) {
                 const int side = sx < 0 ? S.bc[SIDE_W] : S.bc[SIDE_E];
                 if (side == BC_WALL)
-                    v = *pc<T>(S, opp_of(i), x, y, sw);
+                    v = ldm<false>(pc<T>(S, opp_of(i), x, y, sw));
                 else  // zero-gradient outlet (east, e_x = -1)
                     v = post_stream<T>(S, i, nx - 2, y, sw);
             } else {
                 const int side = sy < 0 ? S.bc[SIDE_S] : S.bc[SIDE_N];
                 if (side == BC_WALL)
-                    v = *pc<T>(S, opp_of(i), x, y, sw);
+                    v = ldm<false>(pc<T>(S, opp_of(i), x, y, sw));
                 else  // specular reflection
-                    v = *pc<T>(S, mirror_y(i), wrap(x - ex_of(i), nx, S.px), y, sw);
+                    v = ldm<false>(pc<T>(S, mirror_y(i), wrap(x - ex_of(i), nx, S.px), y, sw));
             }
-            *loc<T>(S, i, x, y, sw) = v;
+            stm<false>(loc<T>(S, i, x, y, sw), v);
         }
     }
 }
@@ -677,25 +702,6 @@ __device__ __forceinline__ int lookup(const GroupLookup& L, int g, int& body) {
     return L.m0[b] + g - L.gbase[b];
 }
 
-// Typed accessors: LDS-resident arrays are read with ds_read, the others with
-// global loads (never the slower flat path of generic pointers).
-#define LBM_AS3 __attribute__((address_space(3)))
-#define LBM_AS1 __attribute__((address_space(1)))
-template <bool LDS, typename T>
-__device__ __forceinline__ T ldm(const T* p) {
-    if constexpr (LDS)
-        return *(const LBM_AS3 T*)(p);
-    else
-        return *(const LBM_AS1 T*)(p);
-}
-template <bool LDS, typename T>
-__device__ __forceinline__ void stm(T* p, T v) {
-    if constexpr (LDS)
-        *(LBM_AS3 T*)(p) = v;
-    else
-        *(LBM_AS1 T*)(p) = v;
-}
-
 // native vectors for 8- and 16-byte LDS/global accesses
 template <typename T>
 using nv2 = T __attribute__((ext_vector_type(2)));
@@ -709,7 +715,6 @@ template <typename T>
 struct Band {
     T* node;                 // band records rho, 1/rho, j_x, j_y (rho is fixed during the sweeps)
     T* wt;                   // per-marker weights ds * dm of the current sweep (2 per marker)
-    T* tot;                  // per-marker totals of the sweeps for the final spread (5 per marker)
     unsigned short* run16;   // band run offsets (LDS) ...
     const int* run32;        // ... or global
     unsigned short* rows;    // per marker: first band node of each stencil row (LDS);
@@ -871,9 +876,23 @@ __device__ __forceinline__ int run_at(const Band<T>& B, int k) {
         return ldm<false>(B.run32 + k);
 }
 
-// Steps 2-6 of a group's correction (gather, N sweeps on (rho, j), final
-// spread and correction of the nine populations) for one placement of its
-// working arrays.
+// Band record of one node: rho, 1/rho, j_x, j_y of its post-stream populations.
+template <typename T>
+__device__ __forceinline__ nv4<T> band_record(const T f[9], T rho_base) {
+    const T Ssum = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
+    const T rho = rho_base + Ssum;
+    nv4<T> rec;
+    rec.x = rho;
+    rec.y = T(1) / rho;
+    rec.z = (f[1] + f[5] + f[8]) - (f[3] + f[6] + f[7]);
+    rec.w = (f[2] + f[5] + f[6]) - (f[4] + f[7] + f[8]);
+    return rec;
+}
+
+// Steps 2-5 of a group's correction (gather, N sweeps on (rho, j), per-marker
+// totals of the sweeps) for one placement of its working arrays.  Groups with
+// fixed plans have their band records gathered beforehand (k_band_gather);
+// the final spread and correction of the populations is k_band_apply.
 template <typename T, int NT, int MPT, bool CORE, bool EXTRA>
 __device__ __forceinline__ void correct_group(const SimDev& S, const GroupDev& G, const GroupLookup& L, Band<T> B,
                                               const T* phi_g, const T* entD_g, int M, int nband, int nent, int sw,
@@ -883,11 +902,11 @@ __device__ __forceinline__ void correct_group(const SimDev& S, const GroupDev& G
         // one pass issues every copy's loads together
         const int len = max(max(nband + 1, M), EXTRA ? max(8 * M, nent) : 0);
         for (int i = tid; i < len; i += NT) {
-            if (i <= nband) stm<true>(B.run16 + i, (unsigned short)G.node_run[i]);
+            if (i <= nband) stm<true>(B.run16 + i, (unsigned short)ldm<false>(G.node_run + i));
             if (i < M) {
                 int m[16];
 #pragma unroll
-                for (int q = 0; q < 16; ++q) m[q] = G.mnode[i * 16 + q];
+                for (int q = 0; q < 16; ++q) m[q] = ldm<false>(G.mnode + i * 16 + q);
                 unsigned short r[4];
 #pragma unroll
                 for (int ky = 0; ky < 4; ++ky) {
@@ -901,41 +920,34 @@ __device__ __forceinline__ void correct_group(const SimDev& S, const GroupDev& G
                 stm<true>(reinterpret_cast<nv2<unsigned>*>(B.rows + i * 4), rv);
             }
             if constexpr (EXTRA) {
-                if (i < 8 * M) stm<true>(B.phi + i, phi_g[i]);
-                if (i < nent) stm<true>(B.ent16 + i, (unsigned short)G.ent[i]);
+                if (i < 8 * M) stm<true>(B.phi + i, ldm<false>(phi_g + i));
+                if (i < nent) stm<true>(B.ent16 + i, (unsigned short)ldm<false>(G.ent + i));
             }
         }
+        if (!G.dynamic)  // band records gathered by k_band_gather
+            for (int k = tid; k < nband; k += NT)
+                stm<true>(reinterpret_cast<nv4<T>*>(B.node) + k, ldm<false>(reinterpret_cast<const nv4<T>*>(G.node4) + k));
     }
     IB_MARK(2);
-    // gather (rho, j) of the band from the post-stream populations, four nodes
-    // per thread in flight
+    // gather (rho, j) of a rebuilt band from the post-stream populations, four
+    // nodes per thread in flight
     const T rho_base = T(S.rho_base);
-    for (int k0 = tid; k0 < nband; k0 += 4 * NT) {
+    for (int k0 = tid; G.dynamic && k0 < nband; k0 += 4 * NT) {
         T h[4][9];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const int k = k0 + u * NT;
             if (k < nband) {
-                const int cell = G.node_cell[k];
+                const int cell = ldm<false>(G.node_cell + k);
                 const int x = cell % S.nx, y = cell / S.nx;
 #pragma unroll
-                for (int i = 0; i < 9; ++i) h[u][i] = *loc<T>(S, i, x, y, sw);
+                for (int i = 0; i < 9; ++i) h[u][i] = ldm<false>(loc<T>(S, i, x, y, sw));
             }
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const int k = k0 + u * NT;
-            if (k < nband) {
-                const T* f = h[u];
-                const T Ssum = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
-                const T rho = rho_base + Ssum;
-                nv4<T> rec;
-                rec.x = rho;
-                rec.y = T(1) / rho;
-                rec.z = (f[1] + f[5] + f[8]) - (f[3] + f[6] + f[7]);
-                rec.w = (f[2] + f[5] + f[6]) - (f[4] + f[7] + f[8]);
-                stm<CORE>(reinterpret_cast<nv4<T>*>(B.node) + k, rec);
-            }
+            if (k < nband) stm<CORE>(reinterpret_cast<nv4<T>*>(B.node) + k, band_record<T>(h[u], rho_base));
         }
     }
     // per-thread markers: velocities, arc lengths and running sums over the
@@ -949,9 +961,9 @@ __device__ __forceinline__ void correct_group(const SimDev& S, const GroupDev& G
         if (g < M) {
             int body;
             const int mi = lookup(L, g, body);
-            mu[q] = T(S.mU[mi]);
-            mv[q] = T(S.mV[mi]);
-            mds[q] = T(S.mds[mi]);
+            mu[q] = T(ldm<false>(S.mU + mi));
+            mv[q] = T(ldm<false>(S.mV + mi));
+            mds[q] = T(ldm<false>(S.mds + mi));
         }
 #pragma unroll
         for (int c = 0; c < 5; ++c) acc[q][c] = T(0);
@@ -1011,56 +1023,19 @@ __device__ __forceinline__ void correct_group(const SimDev& S, const GroupDev& G
             mr[4] = sqrt(r2) / (double)rs;
         }
     }
-    // totals of the sweeps for the final spread (they may reuse the band's LDS)
-    __syncthreads();
+    // totals of the sweeps for the final spread (k_band_apply), in device memory
 #pragma unroll
     for (int q = 0; q < MPT; ++q) {
         const int g = tid + q * NT;
         if (g < M) {
             int body;
-            const double ds = S.mds[lookup(L, g, body)];
+            const double ds = ldm<false>(S.mds + lookup(L, g, body));
 #pragma unroll
-            for (int c = 0; c < 5; ++c) stm<CORE>(B.tot + g * 5 + c, T(ds * (double)acc[q][c]));
+            for (int c = 0; c < 5; ++c) stm<false>(reinterpret_cast<T*>(G.m_wtot) + g * 5 + c, T(ds * (double)acc[q][c]));
         }
     }
-    __syncthreads();
+    if (tid == 0) G.flags[1] = nband;
     IB_MARK(24);
-    // final spread of sum_n delta f (Eq. 28 is linear in dm and dPi) and correction
-    // (Eq. 27), two nodes per thread in flight
-    for (int k0 = tid; k0 < nband; k0 += 2 * NT) {
-        T t5[2][5];
-        T* p[2][9];
-#pragma unroll
-        for (int u = 0; u < 2; ++u) {
-            const int k = k0 + u * NT;
-            if (k < nband) {
-                spread_node<T, CORE, EXTRA, 5>(B, B.tot, 5, run_at<T, CORE>(B, k), run_at<T, CORE>(B, k + 1), t5[u]);
-                const int cell = G.node_cell[k];
-                const int x = cell % S.nx, y = cell / S.nx;
-#pragma unroll
-                for (int i = 0; i < 9; ++i) p[u][i] = loc<T>(S, i, x, y, sw);
-            }
-        }
-        T f[2][9];
-#pragma unroll
-        for (int u = 0; u < 2; ++u)
-            if (k0 + u * NT < nband)
-#pragma unroll
-                for (int i = 0; i < 9; ++i) f[u][i] = *p[u][i];
-#pragma unroll
-        for (int u = 0; u < 2; ++u) {
-            if (k0 + u * NT >= nband) continue;
-            const T* t = t5[u];
-            const T trB = T(1.5) * (t[2] + t[4]);
-#pragma unroll
-            for (int i = 0; i < 9; ++i) {
-                const T ex = T(ex_of(i)), ey = T(ey_of(i));
-                const T d = weight_of<T>(i) *
-                            (T(3) * (ex * t[0] + ey * t[1]) + T(4.5) * (ex * ex * t[2] + T(2) * ex * ey * t[3] + ey * ey * t[4]) - trB);
-                *p[u][i] = f[u][i] + d;
-            }
-        }
-    }
 }
 
 template <typename T, int NT, int MPT>
@@ -1131,11 +1106,9 @@ __global__ void __launch_bounds__(NT)
         Band<T> B;
         T* lnode = reinterpret_cast<T*>(bump.take(4L * nband * sizeof(T)));
         T* lwt = reinterpret_cast<T*>(bump.take(2L * M * sizeof(T)));
-        // the totals of the final spread reuse the band records when they fit there
-        T* ltot = 5L * M <= 4L * nband ? lnode : reinterpret_cast<T*>(bump.take(5L * M * sizeof(T)));
         unsigned short* lrun = reinterpret_cast<unsigned short*>(bump.take(2L * (nband + 1)));
         unsigned short* lrows = reinterpret_cast<unsigned short*>(bump.take(2L * 4 * M));
-        const bool core = nband < 0xFFFF && nent < 0xFFFF && lnode && lwt && ltot && lrun && lrows;
+        const bool core = nband < 0xFFFF && nent < 0xFFFF && lnode && lwt && lrun && lrows;
         T* lphi = core ? reinterpret_cast<T*>(bump.take(8L * M * sizeof(T))) : nullptr;
         unsigned short* lent = core ? reinterpret_cast<unsigned short*>(bump.take(2L * nent)) : nullptr;
         const bool extra = core && lphi && lent && M < 4096;
@@ -1145,13 +1118,11 @@ __global__ void __launch_bounds__(NT)
         if (core) {
             B.node = lnode;
             B.wt = lwt;
-            B.tot = ltot;
             B.run16 = lrun;
             B.rows = lrows;
         } else {
             B.node = reinterpret_cast<T*>(G.node4);
             B.wt = reinterpret_cast<T*>(G.m_wtot);
-            B.tot = reinterpret_cast<T*>(G.m_wtot);
             B.run16 = nullptr;
             B.rows = nullptr;
         }
@@ -1266,6 +1237,80 @@ __global__ void __launch_bounds__(NT)
 }
 
 // ---------------------------------------------------------------- bookkeeping and I/O
+
+// Work of the band kernels: chunks of 256 band nodes, (group, first node).
+// A group with a fixed plan has nband nodes; a group whose plan is rebuilt on
+// the device has at most cap_nodes, and the count of the current step is
+// left by k_ib in flags[1].
+
+// Band records (rho, 1/rho, j) of the groups with fixed plans, from the
+// post-stream populations, before the correction sweeps.
+template <typename T>
+__global__ void __launch_bounds__(256)
+    k_band_gather(const SimDev* __restrict__ sims, const GroupDev* __restrict__ groups,
+                  const int2* __restrict__ chunks, const BatchHeader* __restrict__ hdr, int nchunks_arg, int parity) {
+    const int nchunks = hdr ? hdr->nchunks : nchunks_arg;
+    for (int c = blockIdx.x; c < nchunks; c += gridDim.x) {
+        const int2 ch = chunks[c];
+        const GroupDev& G = groups[ch.x];
+        const SimDev& S = sims[G.sim];
+        if (!S.active || G.dynamic) continue;
+        const int k = ch.y + threadIdx.x;
+        if (k >= G.nband) continue;
+        const int sw = 1 - (parity >= 0 ? parity : S.swapped);
+        const int cell = ldm<false>(G.node_cell + k);
+        const int x = cell % S.nx, y = cell / S.nx;
+        T f[9];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) f[i] = ldm<false>(loc<T>(S, i, x, y, sw));
+        stm<false>(reinterpret_cast<nv4<T>*>(G.node4) + k, band_record<T>(f, T(S.rho_base)));
+    }
+}
+
+// Final spread of the summed corrections and correction of the populations
+// (Eqs. 26-27; Eq. 28 is linear in dm and dPi, so the N sweeps' deviations
+// are spread once from their per-marker totals), one band node per thread;
+// each node sums its stencil entries in ascending marker order.
+template <typename T>
+__global__ void __launch_bounds__(256)
+    k_band_apply(const SimDev* __restrict__ sims, const GroupDev* __restrict__ groups,
+                 const int2* __restrict__ chunks, const BatchHeader* __restrict__ hdr, int nchunks_arg, int parity) {
+    const int nchunks = hdr ? hdr->nchunks : nchunks_arg;
+    for (int c = blockIdx.x; c < nchunks; c += gridDim.x) {
+        const int2 ch = chunks[c];
+        const GroupDev& G = groups[ch.x];
+        const SimDev& S = sims[G.sim];
+        if (!S.active) continue;
+        const int nband = G.dynamic ? ldm<false>(G.flags + 1) : G.nband;
+        const int k = ch.y + threadIdx.x;
+        if (k >= nband) continue;
+        const int sw = 1 - (parity >= 0 ? parity : S.swapped);
+        Band<T> B;
+        B.ent32 = G.ent;
+        B.entD = reinterpret_cast<T*>(G.ent_D);
+        B.run32 = G.node_run;
+        T t[5];
+        spread_node<T, false, false, 5>(B, reinterpret_cast<const T*>(G.m_wtot), 5, ldm<false>(G.node_run + k),
+                                        ldm<false>(G.node_run + k + 1), t);
+        const int cell = ldm<false>(G.node_cell + k);
+        const int x = cell % S.nx, y = cell / S.nx;
+        LBM_AS1 T* p[9];
+        T f[9];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            p[i] = gptr(loc<T>(S, i, x, y, sw));
+            f[i] = *p[i];
+        }
+        const T trB = T(1.5) * (t[2] + t[4]);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            const T ex = T(ex_of(i)), ey = T(ey_of(i));
+            const T d = weight_of<T>(i) *
+                        (T(3) * (ex * t[0] + ey * t[1]) + T(4.5) * (ex * ex * t[2] + T(2) * ex * ey * t[3] + ey * ey * t[4]) - trB);
+            *p[i] = f[i] + d;
+        }
+    }
+}
 
 __global__ void k_advance(SimDev* sims, const BatchHeader* hdr, int nsims_arg) {
     const int nsims = hdr ? hdr->nsims : nsims_arg;
@@ -1394,6 +1439,8 @@ static hipError_t ib_t(const SimDev* sims, GroupDev* groups, const BatchHeader* 
     return hipGetLastError();
 }
 
+int ib_variant(bool f64, int max_markers) { return f64 ? (max_markers <= 8 * 256 ? 0 : 1) : (max_markers <= 3 * 768 ? 2 : 3); }
+
 hipError_t launch_ib(bool f64, int max_markers, const SimDev* sims, GroupDev* groups, const BatchHeader* hdr,
                      int ngroups, int grid, int parity, hipStream_t stream) {
     if (grid <= 0) return hipSuccess;
@@ -1402,8 +1449,25 @@ hipError_t launch_ib(bool f64, int max_markers, const SimDev* sims, GroupDev* gr
     if (f64)
         return max_markers <= 8 * 256 ? ib_t<double, 256, 8>(sims, groups, hdr, ngroups, grid, parity, stream)
                                       : ib_t<double, 256, 16>(sims, groups, hdr, ngroups, grid, parity, stream);
-    return max_markers <= 4 * 512 ? ib_t<float, 512, 4>(sims, groups, hdr, ngroups, grid, parity, stream)
+    return max_markers <= 3 * 768 ? ib_t<float, 768, 3>(sims, groups, hdr, ngroups, grid, parity, stream)
                                   : ib_t<float, 512, 8>(sims, groups, hdr, ngroups, grid, parity, stream);
+}
+
+hipError_t launch_band(bool f64, bool apply, const SimDev* sims, const GroupDev* groups, const int2* chunks,
+                       const BatchHeader* hdr, int nchunks, int grid, int parity, hipStream_t stream) {
+    if (grid <= 0) return hipSuccess;
+    if (apply) {
+        if (f64)
+            hipLaunchKernelGGL(k_band_apply<double>, dim3(grid), dim3(256), 0, stream, sims, groups, chunks, hdr, nchunks, parity);
+        else
+            hipLaunchKernelGGL(k_band_apply<float>, dim3(grid), dim3(256), 0, stream, sims, groups, chunks, hdr, nchunks, parity);
+    } else {
+        if (f64)
+            hipLaunchKernelGGL(k_band_gather<double>, dim3(grid), dim3(256), 0, stream, sims, groups, chunks, hdr, nchunks, parity);
+        else
+            hipLaunchKernelGGL(k_band_gather<float>, dim3(grid), dim3(256), 0, stream, sims, groups, chunks, hdr, nchunks, parity);
+    }
+    return hipGetLastError();
 }
 
 hipError_t launch_advance(SimDev* sims, const BatchHeader* hdr, int nsims, hipStream_t stream) {

@@ -129,6 +129,7 @@ struct GroupDev {
 struct BatchHeader {
     int32_t nsims, ntiles, nbc, ngroups;
     int32_t xcd_start[9];
+    int32_t nchunks;  // band chunks (group, first node) of the band kernels
 };
 
 // ---------------------------------------------------------------- indexing

@@ -86,12 +86,13 @@ struct lbm_sim {
     hipStream_t stream = nullptr;
     bool own_stream = false;
     std::string err;
-    DevBuf pop, desc, status, bodies, markers, tiles, bcitems, groups, ubound;
+    DevBuf pop, desc, status, bodies, markers, tiles, bcitems, groups, ubound, chunks;
     SimDev h{};                // host mirror of the descriptor
     HostBody body[LBM_MAX_BODIES];
     std::vector<Group*> grp;
     std::vector<int4> h_tiles;
     std::vector<int2> h_bc;
+    std::vector<int2> h_chunks;  // band chunks (group, first node)
     int tiling = kTileDefault;
     int64_t steps = 0;
     int mcount = 0;
@@ -110,12 +111,12 @@ struct lbm_batch {
     bool own_stream = false;
     std::vector<lbm_sim*> sims;
     std::vector<int64_t> steps_req;
-    DevBuf d_sims, d_tiles, d_bc, d_groups, d_hdr;
-    size_t cap_sims = 0, cap_tiles = 0, cap_bc = 0, cap_groups = 0;
-    int ntiles = 0, nbc = 0, ngroups = 0;
+    DevBuf d_sims, d_tiles, d_bc, d_groups, d_hdr, d_chunks;
+    size_t cap_sims = 0, cap_tiles = 0, cap_bc = 0, cap_groups = 0, cap_chunks = 0;
+    int ntiles = 0, nbc = 0, ngroups = 0, nchunks = 0;
     int max_group = 0;
     int tiling = kTileDefault;
-    int grid_sweep = 0, grid_bc = 0, grid_ib = 0;
+    int grid_sweep = 0, grid_bc = 0, grid_ib = 0, grid_band = 0;
     hipGraphExec_t graph1 = nullptr, graphK = nullptr;
     int graphK_steps = 8;
     size_t bytes = 0;
@@ -185,6 +186,13 @@ void build_tiles(lbm_sim* s, int sim_index, int tiling, std::vector<int4>& out) 
     const int th = t.ty * t.rpt;
     for (int y0 = 0; y0 < s->p.ny; y0 += th)
         for (int x0 = 0; x0 < s->p.nx; x0 += t.tx) out.push_back(make_int4(sim_index, x0, y0, 0));
+}
+
+// Chunks of 256 band nodes of one group for the band kernels: all nodes of a
+// fixed plan, the capacity of a plan rebuilt on the device.
+void build_chunks(const GroupDev& d, int group_index, std::vector<int2>& out) {
+    const int cap = d.dynamic ? d.cap_nodes : d.nband;
+    for (int k = 0; k < cap; k += 256) out.push_back(make_int2(group_index, k));
 }
 
 void build_bc(lbm_sim* s, int sim_index, std::vector<int2>& out) {
@@ -402,6 +410,9 @@ lbm_status rebuild_ib(lbm_sim* s) {
         s->max_group = std::max(s->max_group, g->d.M);
     }
     HIPS(s, upload(s->groups, gd, st));
+    s->h_chunks.clear();
+    for (size_t gi = 0; gi < gd.size(); ++gi) build_chunks(gd[gi], (int)gi, s->h_chunks);
+    HIPS(s, upload(s->chunks, s->h_chunks, st));
     HIPS(s, hipMemcpyAsync(s->desc.p, &s->h, sizeof(SimDev), hipMemcpyHostToDevice, st));
     HIPS(s, hipStreamSynchronize(st));
     return LBM_OK;
@@ -636,11 +647,18 @@ lbm_status lbm_step(lbm_sim* s, int32_t nsteps) {
     if (s->batch) return fail(s, LBM_ERR_STATE, "simulation is stepped by its batch");
     const SimDev* d = (const SimDev*)s->desc.p;
     const int ntiles = (int)s->h_tiles.size(), nbc = (int)s->h_bc.size(), ng = (int)s->grp.size();
+    const int nch = (int)s->h_chunks.size();
+    const GroupDev* gdev = (const GroupDev*)s->groups.p;
+    const int2* ch = (const int2*)s->chunks.p;
     for (int t = 0; t < nsteps; ++t) {
         const int parity = s->h.swapped;
         HIPS(s, launch_sweep(s->f64, s->tiling, d, (const int4*)s->tiles.p, nullptr, ntiles, ntiles, parity, s->stream));
         if (nbc) HIPS(s, launch_boundary(s->f64, d, (const int2*)s->bcitems.p, nullptr, nbc, nbc, parity, s->stream));
-        if (ng) HIPS(s, launch_ib(s->f64, s->max_group, d, (GroupDev*)s->groups.p, nullptr, ng, ng, parity, s->stream));
+        if (ng) {
+            HIPS(s, launch_band(s->f64, false, d, gdev, ch, nullptr, nch, nch, parity, s->stream));
+            HIPS(s, launch_ib(s->f64, s->max_group, d, (GroupDev*)s->groups.p, nullptr, ng, ng, parity, s->stream));
+            HIPS(s, launch_band(s->f64, true, d, gdev, ch, nullptr, nch, nch, parity, s->stream));
+        }
         s->h.swapped ^= 1;
         s->h.steps_done += 1;
         ++s->steps;
@@ -769,7 +787,7 @@ lbm_status lbm_set_fields(lbm_sim* s, const double* rho, const double* ux, const
 size_t lbm_device_bytes(const lbm_sim* s) {
     if (!s) return 0;
     size_t b = s->pop.bytes + s->desc.bytes + s->status.bytes + s->bodies.bytes + s->markers.bytes + s->tiles.bytes +
-               s->bcitems.bytes + s->groups.bytes + s->ubound.bytes;
+               s->bcitems.bytes + s->groups.bytes + s->ubound.bytes + s->chunks.bytes;
     for (const Group* g : s->grp)
         b += g->node_cell.bytes + g->node_run.bytes + g->ent.bytes + g->mnode.bytes + g->flags.bytes +
              g->node4.bytes + g->ent_D.bytes + g->m_phi.bytes +
@@ -868,13 +886,16 @@ lbm_status upload_tables(lbm_batch* b) {
     }
     // largest groups first: the persistent correction kernel starts the long ones early
     std::stable_sort(groups.begin(), groups.end(), [](const GroupDev& a, const GroupDev& c) { return a.M > c.M; });
+    std::vector<int2> chunks;
+    for (size_t gi = 0; gi < groups.size(); ++gi) build_chunks(groups[gi], (int)gi, chunks);
     int max_group = groups.empty() ? 0 : groups.front().M;
-    bool variant_changed = (max_group > 2048) != (b->max_group > 2048);
+    bool variant_changed = ib_variant(b->f64, max_group) != ib_variant(b->f64, b->max_group);
     b->max_group = max_group;
     BatchHeader h{};
     h.nsims = (int)sims.size();
     h.nbc = (int)bc.size();
     h.ngroups = (int)groups.size();
+    h.nchunks = (int)chunks.size();
     for (int x = 0; x < 8; ++x) {
         h.xcd_start[x] = (int)tiles.size();
         tiles.insert(tiles.end(), per_xcd[x].begin(), per_xcd[x].end());
@@ -893,11 +914,17 @@ lbm_status upload_tables(lbm_batch* b) {
         b->grid_sweep = 8 * (per_xcd_max + per_xcd_max / 4);
         grid_changed = true;
     }
+    // band kernels: one workgroup per chunk, grown the same way
+    if (h.nchunks > b->grid_band) {
+        b->grid_band = h.nchunks + h.nchunks / 4 + 8;
+        grid_changed = true;
+    }
     bool grew = false;
     HIPB(b, ensure_cap<SimDev>(b->d_sims, b->cap_sims, sims.size(), grew));
     HIPB(b, ensure_cap<int4>(b->d_tiles, b->cap_tiles, tiles.size(), grew));
     HIPB(b, ensure_cap<int2>(b->d_bc, b->cap_bc, bc.size(), grew));
     HIPB(b, ensure_cap<GroupDev>(b->d_groups, b->cap_groups, groups.size(), grew));
+    HIPB(b, ensure_cap<int2>(b->d_chunks, b->cap_chunks, chunks.size(), grew));
     if (!b->d_hdr.p) {
         HIPB(b, b->d_hdr.alloc(sizeof(BatchHeader)));
         grew = true;
@@ -907,11 +934,13 @@ lbm_status upload_tables(lbm_batch* b) {
     if (!tiles.empty()) HIPB(b, hipMemcpyAsync(b->d_tiles.p, tiles.data(), sizeof(int4) * tiles.size(), hipMemcpyHostToDevice, b->stream));
     if (!bc.empty()) HIPB(b, hipMemcpyAsync(b->d_bc.p, bc.data(), sizeof(int2) * bc.size(), hipMemcpyHostToDevice, b->stream));
     if (!groups.empty()) HIPB(b, hipMemcpyAsync(b->d_groups.p, groups.data(), sizeof(GroupDev) * groups.size(), hipMemcpyHostToDevice, b->stream));
+    if (!chunks.empty()) HIPB(b, hipMemcpyAsync(b->d_chunks.p, chunks.data(), sizeof(int2) * chunks.size(), hipMemcpyHostToDevice, b->stream));
     HIPB(b, hipMemcpyAsync(b->d_hdr.p, &h, sizeof h, hipMemcpyHostToDevice, b->stream));
     HIPB(b, hipStreamSynchronize(b->stream));
     b->ntiles = h.ntiles;
     b->nbc = h.nbc;
     b->ngroups = h.ngroups;
+    b->nchunks = h.nchunks;
     return LBM_OK;
 }
 
@@ -921,7 +950,13 @@ hipError_t enqueue_steps(lbm_batch* b, int n) {
     for (int t = 0; t < n; ++t) {
         hipError_t e = launch_sweep(b->f64, b->tiling, sims, (const int4*)b->d_tiles.p, hdr, 0, b->grid_sweep, -1, b->stream);
         if (e == hipSuccess) e = launch_boundary(b->f64, sims, (const int2*)b->d_bc.p, hdr, 0, b->grid_bc, -1, b->stream);
+        if (e == hipSuccess)
+            e = launch_band(b->f64, false, sims, (const GroupDev*)b->d_groups.p, (const int2*)b->d_chunks.p, hdr, 0,
+                            b->grid_band, -1, b->stream);
         if (e == hipSuccess) e = launch_ib(b->f64, b->max_group, sims, (GroupDev*)b->d_groups.p, hdr, 0, b->grid_ib, -1, b->stream);
+        if (e == hipSuccess)
+            e = launch_band(b->f64, true, sims, (const GroupDev*)b->d_groups.p, (const int2*)b->d_chunks.p, hdr, 0,
+                            b->grid_band, -1, b->stream);
         if (e == hipSuccess) e = launch_advance((SimDev*)b->d_sims.p, hdr, 0, b->stream);
         if (e != hipSuccess) return e;
     }
@@ -1164,7 +1199,11 @@ lbm_status lbm_batch_profile(lbm_batch* b, int32_t nsteps, double ms[4], int64_t
         HIPB(b, hipEventRecord(ev[1], b->stream));
         HIPB(b, launch_boundary(b->f64, sims, (const int2*)b->d_bc.p, hdr, 0, b->grid_bc, -1, b->stream));
         HIPB(b, hipEventRecord(ev[2], b->stream));
+        HIPB(b, launch_band(b->f64, false, sims, (const GroupDev*)b->d_groups.p, (const int2*)b->d_chunks.p, hdr, 0,
+                            b->grid_band, -1, b->stream));
         HIPB(b, launch_ib(b->f64, b->max_group, sims, (GroupDev*)b->d_groups.p, hdr, 0, b->grid_ib, -1, b->stream));
+        HIPB(b, launch_band(b->f64, true, sims, (const GroupDev*)b->d_groups.p, (const int2*)b->d_chunks.p, hdr, 0,
+                            b->grid_band, -1, b->stream));
         HIPB(b, hipEventRecord(ev[3], b->stream));
         HIPB(b, launch_advance((SimDev*)b->d_sims.p, hdr, 0, b->stream));
         HIPB(b, hipEventRecord(ev[4], b->stream));
