@@ -722,8 +722,7 @@ struct Band {
     const int* mn32;         // per marker: band node of each of the 16 stencil slots (global)
     T* phi;
     unsigned short* ent16;   // packed entries (marker << 4 | ky << 2 | kx) in LDS; D from phi
-    const int* ent32;        // the same in global memory ...
-    T* entD;                 // ... with the weights D in global memory
+    const void* entpk;       // ... or packed (marker, D) records in device memory
 };
 
 // marker pass: interpolate (rho, j, jj/rho) at marker g from the band,
@@ -805,6 +804,42 @@ __device__ __forceinline__ void interp_marker(const Band<T> B, int g, T U, T V, 
     rs = r;
 }
 
+// Packed stencil entry in device memory: marker index g and weight D, one
+// 8-byte (FP32) or 16-byte (FP64) load per entry.
+template <typename T>
+__device__ __forceinline__ void store_entry(void* base, int e, int g, T d) {
+    if constexpr (sizeof(T) == 4) {
+        nv2<unsigned> v;
+        v.x = (unsigned)g;
+        v.y = __builtin_bit_cast(unsigned, d);
+        stm<false>(reinterpret_cast<nv2<unsigned>*>(base) + e, v);
+    } else {
+        const unsigned long long b = __builtin_bit_cast(unsigned long long, d);
+        nv4<unsigned> v;
+        v.x = (unsigned)g;
+        v.y = 0u;
+        v.z = (unsigned)(b & 0xffffffffull);
+        v.w = (unsigned)(b >> 32);
+        stm<false>(reinterpret_cast<nv4<unsigned>*>(base) + e, v);
+    }
+}
+template <typename T>
+__device__ __forceinline__ void load_entry(const void* base, int e, int& g, T& d) {
+    if constexpr (sizeof(T) == 4) {
+        const nv2<unsigned> v = ldm<false>(reinterpret_cast<const nv2<unsigned>*>(base) + e);
+        // through plain scalars: a bit cast applied to a vector element
+        // expression reinterprets the wrong element
+        const unsigned gx = v.x, dy = v.y;
+        g = (int)gx;
+        d = __builtin_bit_cast(T, dy);
+    } else {
+        const nv4<unsigned> v = ldm<false>(reinterpret_cast<const nv4<unsigned>*>(base) + e);
+        const unsigned gx = v.x, lo = v.z, hi = v.w;
+        g = (int)gx;
+        d = __builtin_bit_cast(T, ((unsigned long long)hi << 32) | lo);
+    }
+}
+
 // node pass: sum over the node's stencil entries (ascending marker) of
 // D * w[stride * g + c] for C components
 template <typename T, bool CORE, bool EXTRA, int C>
@@ -822,8 +857,7 @@ __device__ __forceinline__ void spread_node(const Band<T> B, const T* w, int str
                 g[q] = p >> 4;
                 d[q] = ldm<true>(B.phi + g[q] * 8 + (p & 3)) * ldm<true>(B.phi + g[q] * 8 + 4 + ((p >> 2) & 3));
             } else {
-                g[q] = ldm<false>(B.ent32 + e + q) >> 4;
-                d[q] = ldm<false>(B.entD + e + q);
+                load_entry<T>(B.entpk, e + q, g[q], d[q]);
             }
         }
         T wv[4][C];
@@ -844,8 +878,7 @@ __device__ __forceinline__ void spread_node(const Band<T> B, const T* w, int str
             g = p >> 4;
             d = ldm<true>(B.phi + g * 8 + (p & 3)) * ldm<true>(B.phi + g * 8 + 4 + ((p >> 2) & 3));
         } else {
-            g = ldm<false>(B.ent32 + e) >> 4;
-            d = ldm<false>(B.entD + e);
+            load_entry<T>(B.entpk, e, g, d);
         }
 #pragma unroll
         for (int c = 0; c < C; ++c) out[c] += d * ldm<CORE>(w + stride * g + c);
@@ -876,6 +909,26 @@ __device__ __forceinline__ int run_at(const Band<T>& B, int k) {
         return ldm<false>(B.run32 + k);
 }
 
+// The four stencil rows of marker i as band node indices: the first node of
+// each row, or 0xFFFF where the row's nodes are not 4 consecutive band nodes
+// (cut by a lattice edge or wrapped across a periodic one).
+__device__ __forceinline__ nv2<unsigned> stencil_rows(const GroupDev& G, int i) {
+    int m[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) m[q] = ldm<false>(G.mnode + i * 16 + q);
+    unsigned short r[4];
+#pragma unroll
+    for (int ky = 0; ky < 4; ++ky) {
+        const int a = m[ky * 4];
+        const bool reg = a >= 0 && a < 0xFFFF && m[ky * 4 + 1] == a + 1 && m[ky * 4 + 2] == a + 2 && m[ky * 4 + 3] == a + 3;
+        r[ky] = reg ? (unsigned short)a : (unsigned short)0xFFFF;
+    }
+    nv2<unsigned> rv;
+    rv.x = (unsigned)r[0] | ((unsigned)r[1] << 16);
+    rv.y = (unsigned)r[2] | ((unsigned)r[3] << 16);
+    return rv;
+}
+
 // Band record of one node: rho, 1/rho, j_x, j_y of its post-stream populations.
 template <typename T>
 __device__ __forceinline__ nv4<T> band_record(const T f[9], T rho_base) {
@@ -895,7 +948,7 @@ __device__ __forceinline__ nv4<T> band_record(const T f[9], T rho_base) {
 // the final spread and correction of the populations is k_band_apply.
 template <typename T, int NT, int MPT, bool CORE, bool EXTRA>
 __device__ __forceinline__ void correct_group(const SimDev& S, const GroupDev& G, const GroupLookup& L, Band<T> B,
-                                              const T* phi_g, const T* entD_g, int M, int nband, int nent, int sw,
+                                              const T* phi_g, int M, int nband, int nent, int sw,
                                               int gi) {
     const int tid = threadIdx.x;
     if constexpr (CORE) {
@@ -904,19 +957,8 @@ __device__ __forceinline__ void correct_group(const SimDev& S, const GroupDev& G
         for (int i = tid; i < len; i += NT) {
             if (i <= nband) stm<true>(B.run16 + i, (unsigned short)ldm<false>(G.node_run + i));
             if (i < M) {
-                int m[16];
-#pragma unroll
-                for (int q = 0; q < 16; ++q) m[q] = ldm<false>(G.mnode + i * 16 + q);
-                unsigned short r[4];
-#pragma unroll
-                for (int ky = 0; ky < 4; ++ky) {
-                    const int a = m[ky * 4];
-                    const bool reg = a >= 0 && m[ky * 4 + 1] == a + 1 && m[ky * 4 + 2] == a + 2 && m[ky * 4 + 3] == a + 3;
-                    r[ky] = reg ? (unsigned short)a : (unsigned short)0xFFFF;
-                }
-                nv2<unsigned> rv;
-                rv.x = (unsigned)r[0] | ((unsigned)r[1] << 16);
-                rv.y = (unsigned)r[2] | ((unsigned)r[3] << 16);
+                const nv2<unsigned> rv = G.dynamic ? stencil_rows(G, i)
+                                                   : ldm<false>(reinterpret_cast<const nv2<unsigned>*>(G.m_rows) + i);
                 stm<true>(reinterpret_cast<nv2<unsigned>*>(B.rows + i * 4), rv);
             }
             if constexpr (EXTRA) {
@@ -1073,7 +1115,6 @@ __global__ void __launch_bounds__(NT)
             L.gbase[G.nbody] = base;
         }
         T* phi_g = reinterpret_cast<T*>(G.m_phi);
-        T* entD_g = reinterpret_cast<T*>(G.ent_D);
         // stencil weights of Eq. 15: phi per marker, D per stencil entry (static plans: once)
         const bool fresh = G.dynamic || G.flags[0] == 0;
         __syncthreads();
@@ -1093,8 +1134,11 @@ __global__ void __launch_bounds__(NT)
             for (int e = tid; e < nent; e += NT) {
                 const int p = G.ent[e];
                 const int g = p >> 4;
-                entD_g[e] = phi_g[g * 8 + (p & 3)] * phi_g[g * 8 + 4 + ((p >> 2) & 3)];
+                store_entry<T>(G.ent_D, e, g, phi_g[g * 8 + (p & 3)] * phi_g[g * 8 + 4 + ((p >> 2) & 3)]);
             }
+            if (!G.dynamic)
+                for (int g = tid; g < M; g += NT)
+                    stm<false>(reinterpret_cast<nv2<unsigned>*>(G.m_rows) + g, stencil_rows(G, g));
             __syncthreads();
             if (tid == 0 && !G.dynamic) G.flags[0] = 1;
         }
@@ -1113,7 +1157,7 @@ __global__ void __launch_bounds__(NT)
         unsigned short* lent = core ? reinterpret_cast<unsigned short*>(bump.take(2L * nent)) : nullptr;
         const bool extra = core && lphi && lent && M < 4096;
         B.mn32 = G.mnode;
-        B.ent32 = G.ent;
+        B.entpk = G.ent_D;
         B.run32 = G.node_run;
         if (core) {
             B.node = lnode;
@@ -1129,18 +1173,16 @@ __global__ void __launch_bounds__(NT)
         if (extra) {
             B.phi = lphi;
             B.ent16 = lent;
-            B.entD = nullptr;
         } else {
             B.phi = phi_g;
             B.ent16 = nullptr;
-            B.entD = entD_g;
         }
         if (extra)
-            correct_group<T, NT, MPT, true, true>(S, G, L, B, phi_g, entD_g, M, nband, nent, sw, gi);
+            correct_group<T, NT, MPT, true, true>(S, G, L, B, phi_g, M, nband, nent, sw, gi);
         else if (core)
-            correct_group<T, NT, MPT, true, false>(S, G, L, B, phi_g, entD_g, M, nband, nent, sw, gi);
+            correct_group<T, NT, MPT, true, false>(S, G, L, B, phi_g, M, nband, nent, sw, gi);
         else
-            correct_group<T, NT, MPT, false, false>(S, G, L, B, phi_g, entD_g, M, nband, nent, sw, gi);
+            correct_group<T, NT, MPT, false, false>(S, G, L, B, phi_g, M, nband, nent, sw, gi);
         __syncthreads();
         IB_MARK(25);
         // FP64 reductions per body (order fixed by the marker index)
@@ -1286,8 +1328,7 @@ __global__ void __launch_bounds__(256)
         if (k >= nband) continue;
         const int sw = 1 - (parity >= 0 ? parity : S.swapped);
         Band<T> B;
-        B.ent32 = G.ent;
-        B.entD = reinterpret_cast<T*>(G.ent_D);
+        B.entpk = G.ent_D;
         B.run32 = G.node_run;
         T t[5];
         spread_node<T, false, false, 5>(B, reinterpret_cast<const T*>(G.m_wtot), 5, ldm<false>(G.node_run + k),

@@ -113,10 +113,12 @@ struct GroupDev {
     int32_t* flags;           // [1] device flag: stencil weights of a static plan are current
     void* node4;              // T [cap_nodes * 4]: rho, 1/rho, j_x, j_y of each band node
                               // (used when the band does not fit in LDS)
-    void* ent_D;              // T [cap_ent] delta weight D of every stencil entry
+    void* ent_D;              // [cap_ent] packed (marker, delta weight D) of every stencil entry:
+                              // {int, float} for FP32, {int, int, double} for FP64
     void* m_phi;              // T [M * 8]: phi_x[4], phi_y[4]
     void* m_wtot;             // T [M * 5]: per-sweep ds*dm (first 2M), then ds * (sum dm, sum dPi)
-    double* m_acc;            // [M * 5] running sums of dm (2) and dPi (3), FP64
+    unsigned short* m_rows;   // [M * 4] first band node of each stencil row, 0xFFFF where the
+                              // row's nodes are not 4 consecutive band nodes (fixed plans)
     double* m_red;            // [M * 5] per-marker Fx, Fy, T, |dm|^2, slip for the reductions
 };
 

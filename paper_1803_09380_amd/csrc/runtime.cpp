@@ -74,7 +74,7 @@ struct HostBody {
 // One group's plan and scratch on the device plus its host descriptor.
 struct Group {
     GroupDev d{};
-    DevBuf node_cell, node_run, ent, mnode, flags, node4, ent_D, m_phi, m_wtot, m_acc, m_red;
+    DevBuf node_cell, node_run, ent, mnode, flags, node4, ent_D, m_phi, m_wtot, m_rows, m_red;
 };
 
 }  // namespace
@@ -379,10 +379,10 @@ lbm_status rebuild_ib(lbm_sim* s) {
         HIPS(s, G->flags.alloc(sizeof(int) * 4));
         HIPS(s, hipMemsetAsync(G->flags.p, 0, sizeof(int) * 4, st));
         HIPS(s, G->node4.alloc(tsz * 4 * d.cap_nodes));
-        HIPS(s, G->ent_D.alloc(tsz * std::max(1, d.cap_ent)));
+        HIPS(s, G->ent_D.alloc(2 * tsz * std::max(1, d.cap_ent)));
         HIPS(s, G->m_phi.alloc(tsz * 8 * std::max(1, M)));
         HIPS(s, G->m_wtot.alloc(tsz * 5 * std::max(1, M)));
-        HIPS(s, G->m_acc.alloc(sizeof(double) * 5 * std::max(1, M)));
+        HIPS(s, G->m_rows.alloc(sizeof(unsigned short) * 4 * std::max(1, M)));
         HIPS(s, G->m_red.alloc(sizeof(double) * 5 * std::max(1, M)));
         d.node_cell = (int*)G->node_cell.p;
         d.node_run = (int*)G->node_run.p;
@@ -393,7 +393,7 @@ lbm_status rebuild_ib(lbm_sim* s) {
         d.ent_D = G->ent_D.p;
         d.m_phi = G->m_phi.p;
         d.m_wtot = G->m_wtot.p;
-        d.m_acc = (double*)G->m_acc.p;
+        d.m_rows = (unsigned short*)G->m_rows.p;
         d.m_red = (double*)G->m_red.p;
         if (!d.dynamic) {
             HIPS(s, hipMemcpyAsync(d.node_cell, node_cell.data(), sizeof(int) * node_cell.size(), hipMemcpyHostToDevice, st));
@@ -791,7 +791,7 @@ size_t lbm_device_bytes(const lbm_sim* s) {
     for (const Group* g : s->grp)
         b += g->node_cell.bytes + g->node_run.bytes + g->ent.bytes + g->mnode.bytes + g->flags.bytes +
              g->node4.bytes + g->ent_D.bytes + g->m_phi.bytes +
-             g->m_wtot.bytes + g->m_acc.bytes + g->m_red.bytes;
+             g->m_wtot.bytes + g->m_rows.bytes + g->m_red.bytes;
     return b;
 }
 
