@@ -153,3 +153,30 @@ def test_precision_mismatch_is_rejected():
     b = lbmib.Batch(lbmib.F32_SHIFTED)
     with pytest.raises(lbmib.LbmError):
         b.admit(s)
+
+
+def test_fp64_batch_equals_alone_and_oracle():
+    """The FP64 batch runs the same kernels as FP64 simulations alone (bitwise)
+    and stays within 1e-12 of the oracle."""
+    import pyoracle as po
+    from gpu_helpers import oracle_from_case, rel_max
+    _say("fp64 batch vs alone vs oracle, 40 steps")
+    cases = [wl.couette(40), wl.cylinder(nx=100, ny=50, D=10.0, centre=(25.0, 25.0), U=0.05, Re=20.0, precision=wl.F64),
+             wl.settling(nx=40, ny=80, D=10.0, density_ratio=1.4, two=True, lower=(20.0, 35.0), u_ref=0.05,
+                         precision=wl.F64)]
+    alone = []
+    for c in cases:
+        s = gpu_from_case(c, precision=lbmib.F64)
+        s.step(40)
+        alone.append(_state(s, len(c["bodies"])))
+    sims = [gpu_from_case(c, precision=lbmib.F64) for c in cases]
+    b = lbmib.Batch(lbmib.F64)
+    for s in sims:
+        assert b.admit(s)
+    b.step(40)
+    b.sync()
+    for s, c, ref in zip(sims, cases, alone):
+        _same(_state(s, len(c["bodies"])), ref)
+    o = oracle_from_case(cases[2])
+    o.step(40)
+    assert rel_max(sims[2].populations(), o.populations()) < 1e-12

@@ -110,14 +110,17 @@ def _compare_case(case, steps, tol_f=1e-12, tol_force=1e-12, check_state=False, 
     scale = float((np.abs(bf.E[:, 0])[:, None, None] * po_).sum(axis=0).max() / fo[0].min())
     for a, b in zip(fg[1:], fo[1:]):
         assert np.abs(a - b).max() <= tol_f * max(np.abs(b).max(), scale)
+    # a body the flow has not reached yet carries only rounding noise: its
+    # scale is floored by the largest body force scale of the case
+    scales = [np.abs(o.forces(k)[0]).max() + abs(o.forces(k)[1]) / b["radius"] for k, b in enumerate(case["bodies"])]
     for k, body in enumerate(case["bodies"]):
         Fg, Tg, dg, sg = g.forces(k)
         Fo, To, do, so = o.forces(k)
         R = body["radius"]
-        scale = np.abs(Fo).max() + abs(To) / R
+        scale = max(scales[k], max(scales))
         assert np.abs(Fg - Fo).max() <= tol_force * scale, (k, Fg, Fo, scale)
         assert abs(Tg - To) <= tol_force * scale * R, (k, Tg, To, scale)
-        assert abs(dg[0] - do[0]) <= 1e-9 * max(do[0], 1e-30) + 1e-18
+        assert abs(dg[0] - do[0]) <= 1e-9 * max(do[0], 1e-30) + 1e-15 * max(scales)
         if check_state:
             assert np.allclose(sg, so, rtol=1e-11, atol=1e-13), (k, sg, so)
     return o, g
@@ -361,3 +364,49 @@ def test_dirichlet_box_needs_all_four_sides():
     s = lbmib.Sim(16, 16, 0.8, bc=(lbmib.WALL,) * 4)
     with pytest.raises(lbmib.LbmError):
         s.set_boundary_velocity(np.zeros((2 * 16 + 2 * 14, 2)))
+
+
+# ---------------------------------------------------------------- placements and stencil edge cases
+
+def test_stencils_wrapping_a_periodic_edge_f64():
+    """A fixed circle across the x = 0 edge of a periodic box: stencil rows
+    wrap and take the irregular-row path."""
+    _say("circle across a periodic edge f64, 60 steps")
+    nx = ny = 48
+    R, n = 6.0, 38
+    xy = wl.circle_markers(2.3, 24.0, R, n) % np.array([nx, ny])
+    uv = np.stack([-0.01 * (xy[:, 1] - 24.0) / R, np.zeros(n)], axis=1)
+    g = lbmib.Sim(nx, ny, 0.8)
+    o = po.Oracle(nx, ny, 0.8)
+    for s in (g, o):
+        s.set_body(0, lbmib.FIXED, n, xy=xy, uv=uv, ds=np.full(n, 2 * math.pi * R / n))
+    g.step(60)
+    o.step(60)
+    assert rel_max(g.populations(), o.populations()) < 1e-12
+    (Fg, Tg, _, _), (Fo, To, _, _) = g.forces(0), o.forces(0)
+    scale = np.abs(Fo).max() + abs(To) / R
+    assert np.abs(Fg - Fo).max() <= 1e-12 * scale
+
+
+def test_large_group_device_memory_placement_f64():
+    """A circle of 942 markers: its FP64 plan does not fit in LDS, so the
+    sweeps read the band and the stencil entries from device memory."""
+    _say("couette 400 f64 (942-marker outer circle), 20 steps")
+    _compare_case(wl.couette(400), 20)
+
+
+def test_large_group_fp32():
+    """Couette 512 in FP32: the 1206-marker circle keeps its band in LDS and
+    reads its stencil entries from device memory."""
+    _say("couette 512 f32 vs oracle, 30 steps")
+    case = wl.couette(512)
+    o = oracle_from_case(case)
+    g = gpu_from_case(case, precision=lbmib.F32_SHIFTED)
+    o.step(30)
+    g.step(30)
+    assert rel_max(g.populations(), o.populations()) < 2e-7
+    scales = [np.abs(o.forces(k)[0]).max() + abs(o.forces(k)[1]) / b["radius"] for k, b in enumerate(case["bodies"])]
+    for k, body in enumerate(case["bodies"]):
+        (Fg, Tg, _, _), (Fo, To, _, _) = g.forces(k), o.forces(k)
+        # the outer circle has not felt the flow yet: floor by the case's force scale
+        assert np.abs(Fg - Fo).max() <= 1e-4 * max(scales), (k, Fg, Fo)
