@@ -1,6 +1,8 @@
 """Flow diagnostics of the validation cases, computed on the host from what the
 library returns (fields, body forces, body states).
 
+  * the Couette closed form of Eq. 34, its torque, and the L2 norms (relative
+    over the annulus, absolute along theta = pi/2 as in Eq. 35);
   * force coefficients C_d, C_l of Eq. 36;
   * recirculation length L_w behind a fixed cylinder: distance along the wake
     axis from the cylinder's rear point to where the streamwise velocity turns
@@ -18,6 +20,47 @@ These are post-processing of outputs; none of them is part of the time step.
 import math
 
 import numpy as np
+
+
+def couette_utheta(r, R1, R2, omega1):
+    """Eq. 34 (outer cylinder at rest): u_theta = (R1^2 - R^2 r^2) omega1 /
+    ((1 - R^2) r) with R = R1 / R2."""
+    R = R1 / R2
+    r = np.asarray(r, dtype=np.float64)
+    return (R1 * R1 - R * R * r * r) * omega1 / ((1.0 - R * R) * r)
+
+
+def couette_torque(mu, omega1, R1, R2):
+    """Torque of the fluid on the inner cylinder of the steady flow of Eq. 34,
+    T = -4 pi mu omega1 R1^2 R2^2 / (R2^2 - R1^2) per unit length."""
+    return -4.0 * math.pi * mu * omega1 * R1 * R1 * R2 * R2 / (R2 * R2 - R1 * R1)
+
+
+def couette_errors(ux, uy, centre, R1, R2, omega1):
+    """(relative L2 velocity error over the nodes of the annulus R1 < r < R2,
+    absolute L2 error of Eq. 35 on the profile theta = pi/2), against Eq. 34.
+    The profile is the node column through the centre above it, where u_theta
+    points along -x and u_r along y."""
+    ny, nx = ux.shape
+    cx, cy = centre
+    y, x = np.mgrid[0:ny, 0:nx].astype(np.float64)
+    dx, dy = x - cx, y - cy
+    rr = np.hypot(dx, dy)
+    m = (rr > R1) & (rr < R2)
+    ut = couette_utheta(rr[m], R1, R2, omega1)
+    ua, va = -ut * dy[m] / rr[m], ut * dx[m] / rr[m]
+    rel = math.sqrt(np.mean((ux[m] - ua) ** 2 + (uy[m] - va) ** 2) / np.mean(ua ** 2 + va ** 2))
+    col = int(round(cx))
+    ys = np.arange(ny, dtype=np.float64) - cy
+    p = (ys > R1) & (ys < R2)
+    utp = couette_utheta(ys[p], R1, R2, omega1)
+    e35 = math.sqrt(np.mean((ux[p, col] + utp) ** 2 + uy[p, col] ** 2))
+    return rel, e35
+
+
+def observed_order(h, err):
+    """Least-squares slope of log(err) against log(h)."""
+    return float(np.polyfit(np.log(np.asarray(h, dtype=np.float64)), np.log(np.asarray(err, dtype=np.float64)), 1)[0])
 
 
 def force_coefficients(F, U0, D, rho=1.0):

@@ -5,6 +5,7 @@ the paper prints next to its values.
   python -m paper_1803_09380_amd.validate dkt
   python -m paper_1803_09380_amd.validate single [--ratios 1.0015 1.003 1.01 1.03]
   python -m paper_1803_09380_amd.validate tgv [--sizes 10 20 40 80]
+  python -m paper_1803_09380_amd.validate couette [--grids 32 64 128 256 512]
 
 Every case runs through the library (batched FP32 shifted populations unless
 --f64); diagnostics are host-side post-processing of the returned fields,
@@ -232,9 +233,55 @@ def tgv(lbmib, sizes, f64=True, cylinder=True):
             "results": out, "orders": orders, "wall_s": time.perf_counter() - t0}
 
 
+def couette(lbmib, sides, steps_per_k2=3000):
+    """Cylindrical Couette flow (Sec. 3.1.2) on the workloads' geometry at each
+    side (k = side / 64; R1 = 12k, R2 = 24k, wall speed 0.01/k, tau = 0.8, so
+    Re is fixed), steps_per_k2 * k^2 steps, in FP64 and FP32 batches.  Reports
+    the relative annulus error, the absolute L2 norm of Eq. 35 on theta = pi/2,
+    their observed orders, the inner torque against the closed form, the mass
+    drift and the FP32-FP64 velocity difference."""
+    cases = [wl.couette(sd, precision=wl.F64) for sd in sides]
+    budgets = [int(steps_per_k2 * (sd / 64.0) ** 2) for sd in sides]
+    out = {"case": "couette", "sides": list(sides), "steps": budgets, "precisions": {}}
+    fields = {}
+    t0 = time.perf_counter()
+    for name, f64 in (("f64", True), ("f32_shifted", False)):
+        def progress(k, s, step):
+            if k == 0:
+                print("couette %s: %d steps" % (name, step), file=sys.stderr, flush=True)
+
+        sims = _run_batch(lbmib, cases, budgets, 20000, f64, progress)
+        rows = []
+        for c, s in zip(cases, sims):
+            m = c["meta"]
+            rho, ux, uy = s.fields()
+            fields[(name, c["nx"])] = (ux, uy)
+            rel, e35 = dg.couette_errors(ux, uy, m["centre"], m["R1"], m["R2"], m["omega1"])
+            T = s.forces(1)[1]
+            Ta = dg.couette_torque(m["nu"] * c["rho0"], m["omega1"], m["R1"], m["R2"])
+            rows.append({"side": c["nx"], "rel_l2": rel, "l2_eq35": e35, "torque_over_closed_form": T / Ta,
+                         "mass_drift": float(rho.sum() / (c["rho0"] * c["nx"] * c["ny"]) - 1.0)})
+            s.close()
+        out["precisions"][name] = {
+            "rows": rows,
+            "order_rel_l2": -dg.observed_order(sides, [r["rel_l2"] for r in rows]) if len(rows) > 1 else None,
+            "order_l2_eq35": -dg.observed_order(sides, [r["l2_eq35"] for r in rows]) if len(rows) > 1 else None}
+    out["fp32_vs_fp64_velocity_rel_l2"] = {}
+    for c in cases:
+        a, b = fields[("f32_shifted", c["nx"])], fields[("f64", c["nx"])]
+        num = np.sum((a[0] - b[0]) ** 2 + (a[1] - b[1]) ** 2)
+        den = np.sum(b[0] ** 2 + b[1] ** 2)
+        out["fp32_vs_fp64_velocity_rel_l2"][str(c["nx"])] = float(np.sqrt(num / den))
+    out["wall_s"] = time.perf_counter() - t0
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
-    ap.add_argument("case", choices=["table1", "dkt", "single", "tgv"])
+    ap.add_argument("case", choices=["table1", "dkt", "single", "tgv", "couette"])
+    ap.add_argument("--grids", type=int, nargs="+", default=[32, 64, 128, 256, 512],
+                    help="Couette box sides (couette)")
+    ap.add_argument("--steps-per-k2", type=int, default=3000)
     ap.add_argument("--sizes", type=int, nargs="+", default=[10, 20, 40, 80])
     ap.add_argument("--no-cylinder", action="store_true")
     ap.add_argument("--re", type=float, nargs="+", default=[20, 40, 100, 200])
@@ -261,8 +308,10 @@ def main(argv=None):
         out = dkt(lbmib, f64=args.f64, seconds=args.seconds or 4.0)
     elif args.case == "single":
         out = single(lbmib, args.ratios, f64=args.f64, seconds=args.seconds or 2.0)
-    else:
+    elif args.case == "tgv":
         out = tgv(lbmib, args.sizes, f64=True, cylinder=not args.no_cylinder)
+    else:
+        out = couette(lbmib, args.grids, steps_per_k2=args.steps_per_k2)
     print(json.dumps(out), flush=True)
     return 0
 

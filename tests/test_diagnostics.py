@@ -160,3 +160,35 @@ def test_validation_reference_values_match_the_golden_files():
         if f and not f[0].startswith("#"):
             dkt[f[0]] = float(f[1])
     assert dkt == val.DKT_PAPER
+
+
+def test_couette_closed_form_solves_the_ode_and_boundary_values():
+    """Eq. 34 satisfies Eq. 32 (finite differences) and Eq. 33."""
+    R1, R2, w = 12.0, 24.0, 0.01 / 12.0
+    assert dg.couette_utheta(R1, R1, R2, w) == pytest.approx(w * R1, rel=1e-14)
+    assert abs(dg.couette_utheta(R2, R1, R2, w)) < 1e-17
+    r = np.linspace(13.0, 23.0, 11)
+    h = 1e-3
+    u = lambda q: dg.couette_utheta(q, R1, R2, w)
+    d2 = (u(r + h) - 2 * u(r) + u(r - h)) / h ** 2
+    dq = (u(r + h) / (r + h) - u(r - h) / (r - h)) / (2 * h)
+    # the terms are about w / r ~ 1e-4; a wrong sign or power leaves residuals of that size
+    assert np.abs(d2 + dq).max() < 1e-8
+
+
+def test_couette_errors_vanish_on_the_exact_field():
+    n, c, R1, R2, w = 65, (32.0, 32.0), 12.0, 24.0, 0.001
+    y, x = np.mgrid[0:n, 0:n].astype(np.float64)
+    dx, dy = x - c[0], y - c[1]
+    r = np.maximum(np.hypot(dx, dy), 1e-9)
+    ut = dg.couette_utheta(r, R1, R2, w)
+    ux, uy = -ut * dy / r, ut * dx / r
+    rel, e35 = dg.couette_errors(ux, uy, c, R1, R2, w)
+    assert rel < 1e-14 and e35 < 1e-17
+    rel2, e352 = dg.couette_errors(1.01 * ux, 1.01 * uy, c, R1, R2, w)
+    assert rel2 == pytest.approx(0.01, rel=1e-9)
+
+
+def test_observed_order():
+    h = np.array([1.0, 0.5, 0.25])
+    assert dg.observed_order(h, 3.0 * h ** 2) == pytest.approx(2.0, abs=1e-12)

@@ -399,6 +399,8 @@ def test_free_particle_sinks_and_markers_follow(po):
 # ---------------------------------------------------------------- Couette, Eq. 34
 
 def _couette_error(po, side, steps):
+    """(relative L2 error over the annulus nodes, absolute L2 error of Eq. 35
+    on the theta = pi/2 profile, inner torque, closed-form torque)."""
     c = wl.couette(side)
     m = c["meta"]
     o = po.Oracle(c["nx"], c["ny"], c["tau"], bc=c["bc"])
@@ -414,19 +416,27 @@ def _couette_error(po, side, steps):
     ut = np.array([po.couette_utheta(q, m["R1"], m["R2"], m["omega1"]) for q in rr[mask]])
     ua, va = -ut * dy[mask] / rr[mask], ut * dx[mask] / rr[mask]
     err = math.sqrt(np.mean((u[mask] - ua) ** 2 + (v[mask] - va) ** 2) / np.mean(ua ** 2 + va ** 2))
+    # Eq. 35: the profile theta = pi/2 (x = x_c, y > y_c), where u_theta points
+    # along -x and u_r along y; absolute velocity error, no normalisation
+    col = int(round(cx))
+    ys = np.arange(side)
+    prof = (ys - cy > m["R1"]) & (ys - cy < m["R2"])
+    utp = np.array([po.couette_utheta(q, m["R1"], m["R2"], m["omega1"]) for q in (ys[prof] - cy)])
+    err35 = math.sqrt(np.mean((u[prof, col] + utp) ** 2 + v[prof, col] ** 2))
     T = o.forces(1)[1]
     Ta = po.couette_torque_inner(m["nu"], m["omega1"], m["R1"], m["R2"])
-    return err, T, Ta
+    return err, err35, T, Ta
 
 
 @pytest.mark.slow
 def test_couette_profile_torque_and_order(po):
     """Eq. 34 closed form on the Couette geometry of the workloads (R1 = 12k,
-    R2 = 24k, tau = 0.8, Re = 1.2), grids 32, 48, 64: the error falls under
-    refinement and the inner torque approaches -4 pi mu omega1 R1^2 R2^2 /
-    (R2^2 - R1^2).  The measured order of this reading is about 1 (BGK and MRT
-    alike), not the second order the paper reports for its own set-up; the
-    bound below records the measurement, it is not the paper's claim."""
+    R2 = 24k, tau = 0.8, Re fixed), grids 32, 48, 64.  Refinement keeps tau and
+    Re, so the wall speed scales as 1/k (diffusive scaling, as in Sec. 3.1.2).
+    The L2 norm of Eq. 35 is an absolute velocity error: it falls at second
+    order, the paper's observation; relative to the wall speed the error falls
+    at first order (the same numbers divided by U).  The inner torque
+    approaches -4 pi mu omega1 R1^2 R2^2 / (R2^2 - R1^2)."""
     res = {}
     for side in (32, 48, 64):
         k = side / 64.0
@@ -434,8 +444,11 @@ def test_couette_profile_torque_and_order(po):
     errs = [res[s][0] for s in (32, 48, 64)]
     assert errs[0] > errs[1] > errs[2]
     assert errs[2] < 0.1
-    order = -np.polyfit(np.log([32, 48, 64]), np.log(errs), 1)[0]
-    assert order > 0.85, order
-    ratios = [res[s][1] / res[s][2] for s in (32, 48, 64)]
+    rel_order = -np.polyfit(np.log([32, 48, 64]), np.log(errs), 1)[0]
+    assert 0.85 < rel_order < 1.3, rel_order
+    e35 = [res[s][1] for s in (32, 48, 64)]
+    order35 = -np.polyfit(np.log([32, 48, 64]), np.log(e35), 1)[0]
+    assert order35 > 1.8, (e35, order35)
+    ratios = [res[s][2] / res[s][3] for s in (32, 48, 64)]
     assert all(r > 1.0 for r in ratios) and ratios[0] > ratios[1] > ratios[2]
     assert abs(ratios[2] - 1) < 0.15
