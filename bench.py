@@ -105,22 +105,29 @@ def run_cpu_baseline(cases, seconds):
                       "FP64, IB sweeps serial, collide/stream OpenMP" % (members, steps_each, used)}
 
 
-def fp64_leg(args, cases, lbmib, wl, torch, np):
-    """Plain FP64 path on the first members (one at a time, direct launches),
-    the batched FP32 path on the same members, and the FP32-vs-FP64 velocity
-    difference on a Couette member."""
-    f64_updates, f64_time = 0, 0.0
+def plain_mlups(args, cases, lbmib, precision):
+    """The members one at a time through the plain per-simulation path
+    (direct launches, no batch, no graph)."""
+    updates, seconds = 0, 0.0
     for c in cases[:args.fp64_sample]:
-        s = lbmib.Sim.from_case(c, precision=lbmib.F64)
+        s = lbmib.Sim.from_case(c, precision=precision)
         s.step(2)
         s.sync()
         t0 = time.perf_counter()
         s.step(args.fp64_steps)
         s.sync()
-        f64_time += time.perf_counter() - t0
-        f64_updates += c["nx"] * c["ny"] * args.fp64_steps
+        seconds += time.perf_counter() - t0
+        updates += c["nx"] * c["ny"] * args.fp64_steps
         s.close()
-    f64_mlups = f64_updates / f64_time / 1e6
+    return updates / seconds / 1e6, updates
+
+
+def fp64_leg(args, cases, lbmib, wl, torch, np):
+    """Plain FP64 and plain FP32 paths on the first members (one at a time,
+    direct launches), the batched FP32 path on the same members, and the
+    FP32-vs-FP64 velocity difference on a Couette member."""
+    f64_mlups, f64_updates = plain_mlups(args, cases, lbmib, lbmib.F64)
+    f32_plain_mlups, _ = plain_mlups(args, cases, lbmib, lbmib.F32_SHIFTED)
     # batched FP32 on the same sample, for a like-for-like speedup
     sample = [lbmib.Sim.from_case(c, precision=lbmib.F32_SHIFTED) for c in cases[:args.fp64_sample]]
     b2 = lbmib.Batch(lbmib.F32_SHIFTED)
@@ -145,7 +152,7 @@ def fp64_leg(args, cases, lbmib, wl, torch, np):
     _, ub, vb = b.fields()
     err = float(np.sqrt(np.sum((ua - ub) ** 2 + (va - vb) ** 2) / np.sum(ua ** 2 + va ** 2)))
 
-    return f64_mlups, f32_sample_mlups, err
+    return f64_mlups, f32_sample_mlups, err, f32_plain_mlups
 
 
 def mrt_leg(args, cases, lbmib, wl, torch, tiling):
@@ -267,10 +274,10 @@ def main():
         mrt = mrt_leg(args, cases, lbmib, wl, torch, in_use)
 
     # ---- FP64 plain path: members of the same set one at a time, direct launches
-    f64_mlups = f32_sample_mlups = err = None
+    f64_mlups = f32_sample_mlups = err = f32_plain_mlups = None
     f64_updates, f64_time = 0, 0.0
     if args.fp64_sample > 0:
-        f64_mlups, f32_sample_mlups, err = fp64_leg(args, cases, lbmib, wl, torch, np)
+        f64_mlups, f32_sample_mlups, err, f32_plain_mlups = fp64_leg(args, cases, lbmib, wl, torch, np)
 
     # ---- served stream: Poisson arrivals of settling requests, continuous batching
     serving = None
@@ -324,7 +331,9 @@ def main():
             "value": round(f64_mlups, 1), "unit": "MLUPS",
             "sample": "first %d members, %d steps each, one at a time" % (args.fp64_sample, args.fp64_steps),
             "fp32_batched_same_sample": round(f32_sample_mlups, 1),
-            "speedup_fp32_batched": round(f32_sample_mlups / f64_mlups, 2)},
+            "speedup_fp32_batched": round(f32_sample_mlups / f64_mlups, 2),
+            "fp32_plain_same_sample": round(f32_plain_mlups, 1),
+            "speedup_of_batching_fp32": round(f32_sample_mlups / f32_plain_mlups, 2)},
         "accuracy": None if err is None else {"fp32_vs_fp64_velocity_rel_l2": err, "case": "couette64, 2000 steps"},
         "mrt": mrt,
         "unstable_members": unstable,
