@@ -6,6 +6,7 @@ the paper prints next to its values.
   python -m paper_1803_09380_amd.validate single [--ratios 1.0015 1.003 1.01 1.03]
   python -m paper_1803_09380_amd.validate tgv [--sizes 10 20 40 80]
   python -m paper_1803_09380_amd.validate couette [--grids 32 64 128 256 512]
+  python -m paper_1803_09380_amd.validate cylinder [--re 20 40 100]
 
 Every case runs through the library (batched FP32 shifted populations unless
 --f64); diagnostics are host-side post-processing of the returned fields,
@@ -276,9 +277,55 @@ def couette(lbmib, sides, steps_per_k2=3000):
     return out
 
 
+def cylinder_channel(lbmib, res, steps=None, sample=20, periods=8):
+    """Flow past a fixed cylinder in a 1600 x 800 channel (D = 40 at (400, 400),
+    126 markers, inflow U = 0.05, zero-gradient outflow, free-slip sides, BGK,
+    FP32 shifted populations), all Reynolds numbers in one batch.  Reports C_d
+    and C_l (mean and amplitude over the last shedding periods when the flow
+    sheds), the largest normal velocity at the markers from the final field
+    (non-penetration), and the batch's MLUPS."""
+    D, U = 40.0, 0.05
+    conv = D / U
+    cases = [wl.cylinder(nx=1600, ny=800, D=D, centre=(400.0, 400.0), U=U, Re=Re) for Re in res]
+    budgets = [steps or (int(100000) if Re < 49 else int(300000)) for Re in res]
+    hist = [[] for _ in res]
+
+    def record(k, s, step):
+        F = s.forces(0)[0]
+        cd, cl = dg.force_coefficients(F, U, D)
+        hist[k].append((step, cd, cl))
+        if k == 0 and step % 20000 == 0:
+            print("cylinder: %d steps" % step, file=sys.stderr, flush=True)
+
+    t0 = time.perf_counter()
+    sims = _run_batch(lbmib, cases, budgets, sample, False, record)
+    wall = time.perf_counter() - t0
+    cells = sum(c["nx"] * c["ny"] * n for c, n in zip(cases, budgets))
+    out = {}
+    for Re, s, c, h in zip(res, sims, cases, hist):
+        h = np.array(h)
+        b = c["bodies"][0]
+        _, ux, uy = s.fields()
+        xy = b["xy"]
+        nrm = (xy - np.array(b["xc"])) / b["radius"]
+        un = dg.bilinear(ux, xy[:, 0], xy[:, 1]) * nrm[:, 0] + dg.bilinear(uy, xy[:, 0], xy[:, 1]) * nrm[:, 1]
+        r = {"steps": int(h[-1, 0]), "max_normal_velocity_over_U": float(np.abs(un).max() / U),
+             "max_slip_after_sweeps_over_U": float(s.forces(0)[2][1] / U)}
+        sh = dg.shedding(h[len(h) // 2:, 0], h[len(h) // 2:, 2], h[len(h) // 2:, 1], periods=periods) if Re >= 49 else None
+        if sh is None:
+            win = h[:, 0] > h[-1, 0] - 20 * conv
+            r.update({"cd": float(h[win, 1].mean()), "cl": float(h[win, 2].mean())})
+        else:
+            r.update({"cd": sh["cd_mean"], "cl_amplitude": sh["cl_amplitude"], "st": dg.strouhal(sh["period"], D, U)})
+        out[str(Re)] = r
+        s.close()
+    return {"case": "cylinder_channel", "precision": "f32_shifted", "results": out, "wall_s": wall,
+            "mlups_including_host_sampling": cells / wall / 1e6}
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
-    ap.add_argument("case", choices=["table1", "dkt", "single", "tgv", "couette"])
+    ap.add_argument("case", choices=["table1", "dkt", "single", "tgv", "couette", "cylinder"])
     ap.add_argument("--grids", type=int, nargs="+", default=[32, 64, 128, 256, 512],
                     help="Couette box sides (couette)")
     ap.add_argument("--steps-per-k2", type=int, default=3000)
@@ -310,8 +357,11 @@ def main(argv=None):
         out = single(lbmib, args.ratios, f64=args.f64, seconds=args.seconds or 2.0)
     elif args.case == "tgv":
         out = tgv(lbmib, args.sizes, f64=True, cylinder=not args.no_cylinder)
-    else:
+    elif args.case == "couette":
         out = couette(lbmib, args.grids, steps_per_k2=args.steps_per_k2)
+    else:
+        res = [int(r) if float(r).is_integer() else r for r in (args.re if args.re != [20, 40, 100, 200] else [20, 40, 100])]
+        out = cylinder_channel(lbmib, res, steps=args.steady_steps)
     print(json.dumps(out), flush=True)
     return 0
 
