@@ -155,7 +155,7 @@ def fp64_leg(args, cases, lbmib, wl, torch, np):
     return f64_mlups, f32_sample_mlups, err, f32_plain_mlups
 
 
-def mrt_leg(args, cases, lbmib, wl, torch, tiling):
+def mrt_leg(args, cases, lbmib, wl, torch, tiling, lanes):
     """The same set with the MRT collision (rates of the validation cases) in
     every member: batched throughput and the sweep's per-launch duration."""
     sims = [lbmib.Sim.from_case(c, precision=lbmib.F32_SHIFTED, mrt_s=wl.mrt_rates(c["tau"])) for c in cases]
@@ -163,12 +163,14 @@ def mrt_leg(args, cases, lbmib, wl, torch, tiling):
     for s in sims:
         assert b.admit(s)
     b.set_tiling(tiling)
+    b.set_lanes(lanes)
     b.step(10)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     b.step(args.mrt_steps)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    b.set_lanes(1)
     ms, pcells = b.profile(10)
     b.close()
     del sims
@@ -196,6 +198,8 @@ def main():
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default sweep tiling instead of timing the candidates on the set")
     ap.add_argument("--tiling", type=int, default=-1)
+    ap.add_argument("--lanes", type=int, default=0,
+                    help="1 or 2 to force the batch's lanes (default: the library's choice, kept by the autotuner)")
     ap.add_argument("--mrt-steps", type=int, default=100,
                     help="timed steps of the same set with the MRT collision (0: skip)")
     ap.add_argument("--serve-requests", type=int, default=24)
@@ -237,9 +241,12 @@ def main():
         assert batch.admit(s)
     if args.tiling >= 0:
         batch.set_tiling(args.tiling)
+    if args.lanes:
+        batch.set_lanes(args.lanes)
     tiling = args.tiling
     if args.tiling < 0 and not args.no_autotune:
         tiling = batch.autotune(trials=3)
+    lanes = batch.lanes
     batch.step(args.warmup)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -249,7 +256,10 @@ def main():
     wall = t1 - t0
     mlups = cells * args.steps / wall / 1e6
 
-    # ---- per-kernel durations on the batch stream (HIP events), same tables and grids
+    # ---- per-kernel durations on the batch stream (HIP events), same tables and
+    # grids; in one lane, so that one sweep launch covers every node
+    if lanes != 1:
+        batch.set_lanes(1)
     ms, pcells = batch.profile(args.profile_steps)
     sweep_ms = ms[0] / args.profile_steps
     achieved = SWEEP_BYTES_F32 * pcells / (sweep_ms * 1e-3) / 1e9
@@ -271,7 +281,7 @@ def main():
     # ---- the same set with the MRT collision
     mrt = None
     if args.mrt_steps > 0:
-        mrt = mrt_leg(args, cases, lbmib, wl, torch, in_use)
+        mrt = mrt_leg(args, cases, lbmib, wl, torch, in_use, lanes)
 
     # ---- FP64 plain path: members of the same set one at a time, direct launches
     f64_mlups = f32_sample_mlups = err = f32_plain_mlups = None
@@ -313,7 +323,7 @@ def main():
                         "channel 20Dx10D with D 16..64, Re 10..100), FP32 shifted populations, "
                         "10 correction sweeps per step" % args.sims,
             "seed": args.seed, "sims": args.sims, "cells": cells, "markers": markers,
-            "tiling": in_use,
+            "tiling": in_use, "lanes": lanes,
         },
         "roofline": {
             "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -221,14 +221,28 @@ lbm_status lbm_batch_sync(lbm_batch* b);
 lbm_status lbm_batch_remaining(lbm_batch* b, lbm_sim* s, int64_t* remaining);
 size_t lbm_batch_bytes(const lbm_batch* b);
 /* Time candidate sweep tilings on the admitted set (each candidate runs `trials`
- * steps on scratch copies so state is not advanced) and keep the fastest.
- * Tilings change scheduling only, never the arithmetic.  chosen (nullable)
- * receives the index of the tiling kept. */
+ * steps, after which the state is restored, so it is not advanced) and keep the
+ * fastest; when two lanes are in use, then time one lane against two at that
+ * tiling and keep the faster (lbm_batch_set_lanes).  Tilings and lanes change
+ * scheduling only, never the arithmetic.  chosen (nullable) receives the index
+ * of the tiling kept. */
 lbm_status lbm_batch_autotune(lbm_batch* b, int32_t trials, int32_t* chosen);
 /* Force a tiling index (0 .. lbm_tiling_count()-1). */
 lbm_status lbm_batch_set_tiling(lbm_batch* b, int32_t tiling);
 /* Index of the tiling the batch launches with now. */
 int32_t lbm_batch_get_tiling(const lbm_batch* b);
+/* lanes = 2 (the default) lets the batch split its simulations into two
+ * lanes replayed on two streams: those whose largest body group has more than
+ * 400 markers, and the rest, when both are non-empty and the first holds at
+ * most half of the nodes; the long correction kernels of the first lane then
+ * overlap the sweeps of the second.  lanes = 1 keeps one lane.  The second
+ * stream is ordered after the batch stream's earlier work and the batch stream
+ * waits for it, so the batch behaves as one stream to the caller.  Results do
+ * not depend on the lanes.  lbm_batch_autotune may switch to one lane when it
+ * is faster. */
+lbm_status lbm_batch_set_lanes(lbm_batch* b, int32_t lanes);
+/* Lanes in use now (1 or 2). */
+int32_t lbm_batch_get_lanes(const lbm_batch* b);
 int32_t lbm_tiling_count(void);
 /* Describe tiling k: threads along x, rows per block, rows per thread. */
 lbm_status lbm_tiling_info(int32_t k, int32_t* tx, int32_t* ty, int32_t* rows_per_thread);

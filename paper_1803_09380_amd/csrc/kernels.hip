@@ -1,13 +1,16 @@
 // gfx950 kernels of the distribution-function-correction IB-LBM.
 //
-//   k_sweep     fused BGK collision + streaming, in place (AA pattern), SoA
-//               planes, one lattice cell per thread-row step; HBM-bound.
-//   k_boundary  rules for populations entering through non-periodic sides.
-//   k_ib        one workgroup per body group: band gather, N Jacobi sweeps of
-//               the correction of Sec. 2.3 on the band's (rho, j), one final
-//               spread of the accumulated deviation into the nine populations,
-//               FP64 force/torque reductions and the rigid-body update.
-//   k_advance   per-simulation step bookkeeping of batches.
+//   k_sweep        fused collision (BGK or MRT) + streaming, in place (AA
+//                  pattern), SoA planes, one workgroup per tile; HBM-bound.
+//   k_boundary     rules for populations entering through non-periodic sides.
+//   k_band_gather  band records (rho, 1/rho, j) of groups with fixed plans.
+//   k_ib           one workgroup per body group: plan and weights of moving
+//                  bodies, N Jacobi sweeps of the correction of Sec. 2.3 on the
+//                  band's (rho, j), per-marker totals, FP64 force/torque
+//                  reductions and the rigid-body update.
+//   k_band_apply   one final spread of the accumulated deviation into the nine
+//                  populations of every band node.
+//   k_advance      per-simulation step bookkeeping of batches.
 //
 // T = double stores f_i; T = float stores h_i = f_i - w_i rho0 (rho_base).
 // The equilibrium is written in terms of S = sum_i h_i = rho - rho_base and

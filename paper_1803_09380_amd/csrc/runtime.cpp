@@ -103,27 +103,53 @@ struct lbm_sim {
     }
 };
 
+// One lane of a batch: the work tables of a subset of its simulations
+// (contiguous in the batch's simulation table), replayed on its own stream.
+struct Lane {
+    DevBuf d_tiles, d_bc, d_groups, d_hdr, d_chunks;
+    size_t cap_tiles = 0, cap_bc = 0, cap_groups = 0, cap_chunks = 0;
+    int sim0 = 0, nsims = 0, ntiles = 0, nbc = 0, ngroups = 0, nchunks = 0;
+    int max_group = 0;
+    int grid_sweep = 0, grid_band = 0;
+    hipGraphExec_t graph1 = nullptr, graphK = nullptr;
+    void drop() {
+        if (graph1) (void)hipGraphExecDestroy(graph1);
+        if (graphK) (void)hipGraphExecDestroy(graphK);
+        graph1 = graphK = nullptr;
+    }
+};
+
+// Simulations whose largest body group has more markers than this run in the
+// first lane when the batch uses two: their long correction kernels overlap
+// the other lane's sweeps.
+constexpr int kHeavyGroupMarkers = 400;
+
 struct lbm_batch {
     bool f64 = false;
     size_t budget = 0;
     int device = 0;
-    hipStream_t stream = nullptr;
+    hipStream_t stream = nullptr;   // the caller's (or an own) stream: lane 0
     bool own_stream = false;
+    hipStream_t stream2 = nullptr;  // lane 1, owned
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     std::vector<lbm_sim*> sims;
-    std::vector<int64_t> steps_req;
-    DevBuf d_sims, d_tiles, d_bc, d_groups, d_hdr, d_chunks;
-    size_t cap_sims = 0, cap_tiles = 0, cap_bc = 0, cap_groups = 0, cap_chunks = 0;
-    int ntiles = 0, nbc = 0, ngroups = 0, nchunks = 0;
-    int max_group = 0;
+    std::vector<int> order;         // simulation table row -> index into sims
+    DevBuf d_sims;
+    size_t cap_sims = 0;
+    Lane lane[2];
+    int lanes_req = 2;              // 1 or 2 (2: split when it pays, see upload_tables)
+    int nlanes = 1;                 // lanes in use
     int tiling = kTileDefault;
-    int grid_sweep = 0, grid_bc = 0, grid_ib = 0, grid_band = 0;
-    hipGraphExec_t graph1 = nullptr, graphK = nullptr;
+    int grid_bc = 0, grid_ib = 0;
     int graphK_steps = 8;
     size_t bytes = 0;
     std::string err;
     ~lbm_batch() {
-        if (graph1) (void)hipGraphExecDestroy(graph1);
-        if (graphK) (void)hipGraphExecDestroy(graphK);
+        lane[0].drop();
+        lane[1].drop();
+        if (ev_fork) (void)hipEventDestroy(ev_fork);
+        if (ev_join) (void)hipEventDestroy(ev_join);
+        if (stream2) (void)hipStreamDestroy(stream2);
     }
 };
 
@@ -823,9 +849,8 @@ lbm_status hipfailb(lbm_batch* b, hipError_t e, const char* where) {
     } while (0)
 
 void drop_graphs(lbm_batch* b) {
-    if (b->graph1) (void)hipGraphExecDestroy(b->graph1);
-    if (b->graphK) (void)hipGraphExecDestroy(b->graphK);
-    b->graph1 = b->graphK = nullptr;
+    b->lane[0].drop();
+    b->lane[1].drop();
 }
 
 // Copy the per-simulation step state (AA state, counters) of the device table
@@ -836,7 +861,7 @@ lbm_status sync_back(lbm_batch* b) {
     std::vector<SimDev> h(b->sims.size());
     HIPB(b, hipMemcpy(h.data(), b->d_sims.p, sizeof(SimDev) * h.size(), hipMemcpyDeviceToHost));
     for (size_t k = 0; k < h.size(); ++k) {
-        lbm_sim* s = b->sims[k];
+        lbm_sim* s = b->sims[b->order[k]];
         s->h.swapped = h[k].swapped;
         s->h.steps_done = h[k].steps_done;
         s->h.steps_left = h[k].steps_left;
@@ -859,120 +884,213 @@ hipError_t ensure_cap(DevBuf& buf, size_t& cap, size_t need, bool& grew) {
 
 // Rebuild and upload the batch's work tables from the admitted simulations'
 // host descriptors (call sync_back first when simulations are in flight).
+// With two lanes requested, the simulations whose largest body group exceeds
+// kHeavyGroupMarkers form lane 0 (their long correction kernels then overlap
+// the sweeps of lane 1) when that leaves both lanes non-empty and lane 0 with
+// at most half of the nodes; otherwise one lane holds everything.
 lbm_status upload_tables(lbm_batch* b) {
+    const int n = (int)b->sims.size();
+    std::vector<int> heavy, light;
+    int64_t heavy_cells = 0, cells = 0;
+    for (int k = 0; k < n; ++k) {
+        const lbm_sim* s = b->sims[k];
+        const int64_t c = (int64_t)s->p.nx * s->p.ny;
+        cells += c;
+        if (s->max_group > kHeavyGroupMarkers) {
+            heavy.push_back(k);
+            heavy_cells += c;
+        } else {
+            light.push_back(k);
+        }
+    }
+    const bool two = b->lanes_req == 2 && !heavy.empty() && !light.empty() && 2 * heavy_cells <= cells;
+    const int nl = two ? 2 : 1;
+    if (nl != b->nlanes) drop_graphs(b);
+    b->nlanes = nl;
+    b->order.clear();
+    if (two) {
+        b->order = heavy;
+        b->order.insert(b->order.end(), light.begin(), light.end());
+    } else {
+        for (int k = 0; k < n; ++k) b->order.push_back(k);
+    }
     std::vector<SimDev> sims;
-    std::vector<int4> tiles;
-    std::vector<int2> bc;
-    std::vector<GroupDev> groups;
-    // row bands of tiles dealt round-robin to the eight XCDs
-    std::vector<int4> per_xcd[8];
-    int band = 0;
-    for (size_t k = 0; k < b->sims.size(); ++k) {
-        lbm_sim* s = b->sims[k];
-        sims.push_back(s->h);
-        std::vector<int4> mine;
-        build_tiles(s, (int)k, b->tiling, mine);
-        for (size_t i = 0; i < mine.size(); ++i) {
-            if (i > 0 && mine[i].z != mine[i - 1].z) ++band;
-            per_xcd[band & 7].push_back(mine[i]);
+    for (int r = 0; r < n; ++r) sims.push_back(b->sims[b->order[r]]->h);
+    bool grew_sims = false;
+    HIPB(b, ensure_cap<SimDev>(b->d_sims, b->cap_sims, sims.size(), grew_sims));
+    if (grew_sims) drop_graphs(b);
+    if (!sims.empty())
+        HIPB(b, hipMemcpyAsync(b->d_sims.p, sims.data(), sizeof(SimDev) * sims.size(), hipMemcpyHostToDevice, b->stream));
+    const int lane_begin[3] = {0, two ? (int)heavy.size() : n, n};
+    for (int l = 0; l < 2; ++l) {
+        Lane& L = b->lane[l];
+        const int r0 = l < nl ? lane_begin[l] : n, r1 = l < nl ? lane_begin[l + 1] : n;
+        std::vector<int4> tiles;
+        std::vector<int2> bc;
+        std::vector<GroupDev> groups;
+        // row bands of tiles dealt round-robin to the eight XCDs
+        std::vector<int4> per_xcd[8];
+        int band = 0;
+        for (int r = r0; r < r1; ++r) {
+            lbm_sim* s = b->sims[b->order[r]];
+            std::vector<int4> mine;
+            build_tiles(s, r, b->tiling, mine);
+            for (size_t i = 0; i < mine.size(); ++i) {
+                if (i > 0 && mine[i].z != mine[i - 1].z) ++band;
+                per_xcd[band & 7].push_back(mine[i]);
+            }
+            ++band;
+            build_bc(s, r, bc);
+            for (Group* g : s->grp) {
+                GroupDev d = g->d;
+                d.sim = r;
+                groups.push_back(d);
+            }
         }
-        ++band;
-        build_bc(s, (int)k, bc);
-        for (Group* g : s->grp) {
-            GroupDev d = g->d;
-            d.sim = (int)k;
-            groups.push_back(d);
+        // largest groups first: the persistent correction kernel starts the long ones early
+        std::stable_sort(groups.begin(), groups.end(), [](const GroupDev& a, const GroupDev& c) { return a.M > c.M; });
+        std::vector<int2> chunks;
+        for (size_t gi = 0; gi < groups.size(); ++gi) build_chunks(groups[gi], (int)gi, chunks);
+        const int max_group = groups.empty() ? 0 : groups.front().M;
+        bool changed = ib_variant(b->f64, max_group) != ib_variant(b->f64, L.max_group);
+        L.max_group = max_group;
+        BatchHeader h{};
+        h.nsims = r1 - r0;
+        h.nbc = (int)bc.size();
+        h.ngroups = (int)groups.size();
+        h.nchunks = (int)chunks.size();
+        std::vector<int4> tl;
+        for (int x = 0; x < 8; ++x) {
+            h.xcd_start[x] = (int)tl.size();
+            tl.insert(tl.end(), per_xcd[x].begin(), per_xcd[x].end());
         }
+        h.xcd_start[8] = (int)tl.size();
+        h.ntiles = (int)tl.size();
+        // One workgroup per tile (workgroup b runs on XCD b mod 8 and takes that
+        // XCD's tile b / 8): with a persistent grid the tiles of late-starting
+        // workgroups made the tail of every sweep.  Extra workgroups exit at once,
+        // so the grid only grows (with headroom) and captured graphs stay valid
+        // while tiles come and go.
+        int per_xcd_max = 1;
+        for (int x = 0; x < 8; ++x) per_xcd_max = std::max(per_xcd_max, h.xcd_start[x + 1] - h.xcd_start[x]);
+        if (8 * per_xcd_max > L.grid_sweep) {
+            L.grid_sweep = 8 * (per_xcd_max + per_xcd_max / 4);
+            changed = true;
+        }
+        // band kernels: one workgroup per chunk, grown the same way
+        if (h.nchunks > L.grid_band) {
+            L.grid_band = h.nchunks + h.nchunks / 4 + 8;
+            changed = true;
+        }
+        bool grew = false;
+        HIPB(b, ensure_cap<int4>(L.d_tiles, L.cap_tiles, tl.size(), grew));
+        HIPB(b, ensure_cap<int2>(L.d_bc, L.cap_bc, bc.size(), grew));
+        HIPB(b, ensure_cap<GroupDev>(L.d_groups, L.cap_groups, groups.size(), grew));
+        HIPB(b, ensure_cap<int2>(L.d_chunks, L.cap_chunks, chunks.size(), grew));
+        if (!L.d_hdr.p) {
+            HIPB(b, L.d_hdr.alloc(sizeof(BatchHeader)));
+            grew = true;
+        }
+        if (grew || changed || L.sim0 != r0) L.drop();
+        L.sim0 = r0;
+        if (!tl.empty()) HIPB(b, hipMemcpyAsync(L.d_tiles.p, tl.data(), sizeof(int4) * tl.size(), hipMemcpyHostToDevice, b->stream));
+        if (!bc.empty()) HIPB(b, hipMemcpyAsync(L.d_bc.p, bc.data(), sizeof(int2) * bc.size(), hipMemcpyHostToDevice, b->stream));
+        if (!groups.empty())
+            HIPB(b, hipMemcpyAsync(L.d_groups.p, groups.data(), sizeof(GroupDev) * groups.size(), hipMemcpyHostToDevice, b->stream));
+        if (!chunks.empty())
+            HIPB(b, hipMemcpyAsync(L.d_chunks.p, chunks.data(), sizeof(int2) * chunks.size(), hipMemcpyHostToDevice, b->stream));
+        HIPB(b, hipMemcpyAsync(L.d_hdr.p, &h, sizeof h, hipMemcpyHostToDevice, b->stream));
+        HIPB(b, hipStreamSynchronize(b->stream));
+        L.nsims = h.nsims;
+        L.ntiles = h.ntiles;
+        L.nbc = h.nbc;
+        L.ngroups = h.ngroups;
+        L.nchunks = h.nchunks;
     }
-    // largest groups first: the persistent correction kernel starts the long ones early
-    std::stable_sort(groups.begin(), groups.end(), [](const GroupDev& a, const GroupDev& c) { return a.M > c.M; });
-    std::vector<int2> chunks;
-    for (size_t gi = 0; gi < groups.size(); ++gi) build_chunks(groups[gi], (int)gi, chunks);
-    int max_group = groups.empty() ? 0 : groups.front().M;
-    bool variant_changed = ib_variant(b->f64, max_group) != ib_variant(b->f64, b->max_group);
-    b->max_group = max_group;
-    BatchHeader h{};
-    h.nsims = (int)sims.size();
-    h.nbc = (int)bc.size();
-    h.ngroups = (int)groups.size();
-    h.nchunks = (int)chunks.size();
-    for (int x = 0; x < 8; ++x) {
-        h.xcd_start[x] = (int)tiles.size();
-        tiles.insert(tiles.end(), per_xcd[x].begin(), per_xcd[x].end());
-    }
-    h.xcd_start[8] = (int)tiles.size();
-    h.ntiles = (int)tiles.size();
-    // One workgroup per tile (workgroup b runs on XCD b mod 8 and takes that
-    // XCD's tile b / 8): with a persistent grid the tiles of late-starting
-    // workgroups made the tail of every sweep.  Extra workgroups exit at once,
-    // so the grid only grows (with headroom) and captured graphs stay valid
-    // while tiles come and go.
-    int per_xcd_max = 1;
-    for (int x = 0; x < 8; ++x) per_xcd_max = std::max(per_xcd_max, h.xcd_start[x + 1] - h.xcd_start[x]);
-    bool grid_changed = false;
-    if (8 * per_xcd_max > b->grid_sweep) {
-        b->grid_sweep = 8 * (per_xcd_max + per_xcd_max / 4);
-        grid_changed = true;
-    }
-    // band kernels: one workgroup per chunk, grown the same way
-    if (h.nchunks > b->grid_band) {
-        b->grid_band = h.nchunks + h.nchunks / 4 + 8;
-        grid_changed = true;
-    }
-    bool grew = false;
-    HIPB(b, ensure_cap<SimDev>(b->d_sims, b->cap_sims, sims.size(), grew));
-    HIPB(b, ensure_cap<int4>(b->d_tiles, b->cap_tiles, tiles.size(), grew));
-    HIPB(b, ensure_cap<int2>(b->d_bc, b->cap_bc, bc.size(), grew));
-    HIPB(b, ensure_cap<GroupDev>(b->d_groups, b->cap_groups, groups.size(), grew));
-    HIPB(b, ensure_cap<int2>(b->d_chunks, b->cap_chunks, chunks.size(), grew));
-    if (!b->d_hdr.p) {
-        HIPB(b, b->d_hdr.alloc(sizeof(BatchHeader)));
-        grew = true;
-    }
-    if (grew || variant_changed || grid_changed) drop_graphs(b);
-    if (!sims.empty()) HIPB(b, hipMemcpyAsync(b->d_sims.p, sims.data(), sizeof(SimDev) * sims.size(), hipMemcpyHostToDevice, b->stream));
-    if (!tiles.empty()) HIPB(b, hipMemcpyAsync(b->d_tiles.p, tiles.data(), sizeof(int4) * tiles.size(), hipMemcpyHostToDevice, b->stream));
-    if (!bc.empty()) HIPB(b, hipMemcpyAsync(b->d_bc.p, bc.data(), sizeof(int2) * bc.size(), hipMemcpyHostToDevice, b->stream));
-    if (!groups.empty()) HIPB(b, hipMemcpyAsync(b->d_groups.p, groups.data(), sizeof(GroupDev) * groups.size(), hipMemcpyHostToDevice, b->stream));
-    if (!chunks.empty()) HIPB(b, hipMemcpyAsync(b->d_chunks.p, chunks.data(), sizeof(int2) * chunks.size(), hipMemcpyHostToDevice, b->stream));
-    HIPB(b, hipMemcpyAsync(b->d_hdr.p, &h, sizeof h, hipMemcpyHostToDevice, b->stream));
-    HIPB(b, hipStreamSynchronize(b->stream));
-    b->ntiles = h.ntiles;
-    b->nbc = h.nbc;
-    b->ngroups = h.ngroups;
-    b->nchunks = h.nchunks;
     return LBM_OK;
 }
 
-hipError_t enqueue_steps(lbm_batch* b, int n) {
-    const SimDev* sims = (const SimDev*)b->d_sims.p;
-    const BatchHeader* hdr = (const BatchHeader*)b->d_hdr.p;
-    for (int t = 0; t < n; ++t) {
-        hipError_t e = launch_sweep(b->f64, b->tiling, sims, (const int4*)b->d_tiles.p, hdr, 0, b->grid_sweep, -1, b->stream);
-        if (e == hipSuccess) e = launch_boundary(b->f64, sims, (const int2*)b->d_bc.p, hdr, 0, b->grid_bc, -1, b->stream);
-        if (e == hipSuccess)
-            e = launch_band(b->f64, false, sims, (const GroupDev*)b->d_groups.p, (const int2*)b->d_chunks.p, hdr, 0,
-                            b->grid_band, -1, b->stream);
-        if (e == hipSuccess) e = launch_ib(b->f64, b->max_group, sims, (GroupDev*)b->d_groups.p, hdr, 0, b->grid_ib, -1, b->stream);
-        if (e == hipSuccess)
-            e = launch_band(b->f64, true, sims, (const GroupDev*)b->d_groups.p, (const int2*)b->d_chunks.p, hdr, 0,
-                            b->grid_band, -1, b->stream);
-        if (e == hipSuccess) e = launch_advance((SimDev*)b->d_sims.p, hdr, 0, b->stream);
-        if (e != hipSuccess) return e;
+// The kernels of one step of lane l, one kernel kind k (0 sweep, 1 boundary,
+// 2 band gather, 3 correction sweeps, 4 band apply, 5 bookkeeping) on `st`.
+hipError_t launch_kind(lbm_batch* b, int l, int k, hipStream_t st) {
+    const Lane& L = b->lane[l];
+    SimDev* sims = (SimDev*)b->d_sims.p;
+    const BatchHeader* hdr = (const BatchHeader*)L.d_hdr.p;
+    switch (k) {
+        case 0: return launch_sweep(b->f64, b->tiling, sims, (const int4*)L.d_tiles.p, hdr, 0, L.grid_sweep, -1, st);
+        case 1: return launch_boundary(b->f64, sims, (const int2*)L.d_bc.p, hdr, 0, b->grid_bc, -1, st);
+        case 2:
+            return launch_band(b->f64, false, sims, (const GroupDev*)L.d_groups.p, (const int2*)L.d_chunks.p, hdr, 0,
+                               L.grid_band, -1, st);
+        case 3: return launch_ib(b->f64, L.max_group, sims, (GroupDev*)L.d_groups.p, hdr, 0, b->grid_ib, -1, st);
+        case 4:
+            return launch_band(b->f64, true, sims, (const GroupDev*)L.d_groups.p, (const int2*)L.d_chunks.p, hdr, 0,
+                               L.grid_band, -1, st);
+        default: return launch_advance(sims + L.sim0, hdr, 0, st);
     }
+}
+
+hipError_t enqueue_steps(lbm_batch* b, int l, int n, hipStream_t st) {
+    for (int t = 0; t < n; ++t)
+        for (int k = 0; k < 6; ++k) {
+            hipError_t e = launch_kind(b, l, k, st);
+            if (e != hipSuccess) return e;
+        }
     return hipSuccess;
 }
 
-hipError_t capture(lbm_batch* b, int n, hipGraphExec_t* out) {
+hipError_t capture(lbm_batch* b, int l, int n, hipStream_t st, hipGraphExec_t* out) {
     hipGraph_t g = nullptr;
-    hipError_t e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
+    hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return e;
-    hipError_t e2 = enqueue_steps(b, n);
-    e = hipStreamEndCapture(b->stream, &g);
+    hipError_t e2 = enqueue_steps(b, l, n, st);
+    e = hipStreamEndCapture(st, &g);
     if (e2 != hipSuccess) e = e2;
     if (e == hipSuccess) e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
     if (g) (void)hipGraphDestroy(g);
     return e;
+}
+
+// Lane 1 runs on the batch's second stream, ordered after everything already
+// enqueued on the batch stream; the batch stream waits for it at the end.
+lbm_status ensure_lane_stream(lbm_batch* b) {
+    if (b->stream2) return LBM_OK;
+    HIPB(b, hipStreamCreateWithFlags(&b->stream2, hipStreamNonBlocking));
+    HIPB(b, hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming));
+    HIPB(b, hipEventCreateWithFlags(&b->ev_join, hipEventDisableTiming));
+    return LBM_OK;
+}
+
+// n steps of every lane: replayed graphs of 8 and 1 steps per lane.
+lbm_status run_steps(lbm_batch* b, int n) {
+    hipStream_t st[2] = {b->stream, b->stream2};
+    if (b->nlanes == 2) {
+        lbm_status rc = ensure_lane_stream(b);
+        if (rc != LBM_OK) return rc;
+        st[1] = b->stream2;
+    }
+    for (int l = 0; l < b->nlanes; ++l) {
+        Lane& L = b->lane[l];
+        if (!L.graph1) HIPB(b, capture(b, l, 1, st[l], &L.graph1));
+        if (!L.graphK) HIPB(b, capture(b, l, b->graphK_steps, st[l], &L.graphK));
+    }
+    if (b->nlanes == 2) {
+        HIPB(b, hipEventRecord(b->ev_fork, b->stream));
+        HIPB(b, hipStreamWaitEvent(b->stream2, b->ev_fork, 0));
+    }
+    for (int l = 0; l < b->nlanes; ++l) {
+        int left = n;
+        while (left >= b->graphK_steps) {
+            HIPB(b, hipGraphLaunch(b->lane[l].graphK, st[l]));
+            left -= b->graphK_steps;
+        }
+        while (left-- > 0) HIPB(b, hipGraphLaunch(b->lane[l].graph1, st[l]));
+    }
+    if (b->nlanes == 2) {
+        HIPB(b, hipEventRecord(b->ev_join, b->stream2));
+        HIPB(b, hipStreamWaitEvent(b->stream, b->ev_join, 0));
+    }
+    return LBM_OK;
 }
 
 }  // namespace
@@ -1000,7 +1118,6 @@ lbm_status lbm_batch_create(int32_t precision, size_t budget, void* hip_stream, 
         b->own_stream = true;
     }
     const int ncu = num_cus(b->device);
-    b->grid_sweep = 0;  // set from the tile count by upload_tables
     b->grid_bc = ncu * 8;
     b->grid_ib = ncu * 2;
     if (upload_tables(b) != LBM_OK) {
@@ -1069,15 +1186,7 @@ lbm_status lbm_batch_retire(lbm_batch* b, lbm_sim* s) {
 
 lbm_status lbm_batch_step(lbm_batch* b, int32_t nsteps) {
     if (!b || nsteps < 0) return LBM_ERR_INVALID;
-    if (!b->graph1) HIPB(b, capture(b, 1, &b->graph1));
-    if (!b->graphK) HIPB(b, capture(b, b->graphK_steps, &b->graphK));
-    int left = nsteps;
-    while (left >= b->graphK_steps) {
-        HIPB(b, hipGraphLaunch(b->graphK, b->stream));
-        left -= b->graphK_steps;
-    }
-    while (left-- > 0) HIPB(b, hipGraphLaunch(b->graph1, b->stream));
-    return LBM_OK;
+    return run_steps(b, nsteps);
 }
 
 lbm_status lbm_batch_sync(lbm_batch* b) {
@@ -1138,28 +1247,23 @@ lbm_status lbm_batch_autotune(lbm_batch* b, int32_t trials, int32_t* chosen) {
         HIPB(b, hipMemcpyAsync(saved[k].markers.p, s->markers.p, s->markers.bytes, hipMemcpyDeviceToDevice, b->stream));
     }
     HIPB(b, hipStreamSynchronize(b->stream));
-    const int old = b->tiling;
-    int best = old;
-    float best_ms = 1e30f;
     hipEvent_t e0, e1;
     HIPB(b, hipEventCreate(&e0));
     HIPB(b, hipEventCreate(&e1));
-    for (int k = 0; k < kNumTilings; ++k) {
-        b->tiling = k;
-        rc = upload_tables(b);
-        if (rc != LBM_OK) break;
-        HIPB(b, enqueue_steps(b, 1));  // warm-up
+    // one candidate: tables, a warm-up step, then `trials` timed steps replayed
+    // from freshly captured graphs; the state is restored afterwards
+    auto trial = [&](float& ms) -> lbm_status {
+        drop_graphs(b);
+        lbm_status r = upload_tables(b);
+        if (r != LBM_OK) return r;
+        r = run_steps(b, 1);
+        if (r != LBM_OK) return r;
         HIPB(b, hipEventRecord(e0, b->stream));
-        HIPB(b, enqueue_steps(b, trials));
+        r = run_steps(b, trials);
+        if (r != LBM_OK) return r;
         HIPB(b, hipEventRecord(e1, b->stream));
         HIPB(b, hipEventSynchronize(e1));
-        float ms = 0;
         HIPB(b, hipEventElapsedTime(&ms, e0, e1));
-        if (ms < best_ms) {
-            best_ms = ms;
-            best = k;
-        }
-        // restore
         for (size_t q = 0; q < b->sims.size(); ++q) {
             lbm_sim* s = b->sims[q];
             s->h = saved[q].h;
@@ -1169,16 +1273,49 @@ lbm_status lbm_batch_autotune(lbm_batch* b, int32_t trials, int32_t* chosen) {
             HIPB(b, hipMemsetAsync(s->status.p, 0, sizeof(uint32_t), b->stream));
         }
         HIPB(b, hipStreamSynchronize(b->stream));
+        return LBM_OK;
+    };
+    int best = b->tiling;
+    float best_ms = 1e30f;
+    for (int k = 0; k < kNumTilings && rc == LBM_OK; ++k) {
+        b->tiling = k;
+        float ms = 0.f;
+        rc = trial(ms);
+        if (rc == LBM_OK && ms < best_ms) {
+            best_ms = ms;
+            best = k;
+        }
+    }
+    b->tiling = best;
+    // then one lane against two at the chosen tiling (when two are possible)
+    if (rc == LBM_OK && b->lanes_req == 2 && b->nlanes == 2) {
+        float ms2 = 0.f, ms1 = 0.f;
+        rc = trial(ms2);
+        if (rc == LBM_OK) {
+            b->lanes_req = 1;
+            rc = trial(ms1);
+            if (rc == LBM_OK && ms2 <= ms1) b->lanes_req = 2;
+        }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    b->tiling = best;
     drop_graphs(b);
     lbm_status rc2 = upload_tables(b);
     if (rc == LBM_OK) rc = rc2;
     if (chosen) *chosen = best;
     return rc;
 }
+
+lbm_status lbm_batch_set_lanes(lbm_batch* b, int32_t lanes) {
+    if (!b || lanes < 1 || lanes > 2) return LBM_ERR_INVALID;
+    lbm_status rc = sync_back(b);
+    if (rc != LBM_OK) return rc;
+    b->lanes_req = lanes;
+    drop_graphs(b);
+    return upload_tables(b);
+}
+
+int32_t lbm_batch_get_lanes(const lbm_batch* b) { return b ? b->nlanes : -1; }
 
 lbm_status lbm_batch_profile(lbm_batch* b, int32_t nsteps, double ms[4], int64_t* cells) {
     if (!b || nsteps < 0 || !ms) return LBM_ERR_INVALID;
@@ -1189,32 +1326,26 @@ lbm_status lbm_batch_profile(lbm_batch* b, int32_t nsteps, double ms[4], int64_t
         if (s->h.active) c += (int64_t)s->p.nx * s->p.ny;
     if (cells) *cells = c;
     for (int k = 0; k < 4; ++k) ms[k] = 0.0;
-    hipEvent_t ev[5];
-    for (int k = 0; k < 5; ++k) HIPB(b, hipEventCreate(&ev[k]));
-    const SimDev* sims = (const SimDev*)b->d_sims.p;
-    const BatchHeader* hdr = (const BatchHeader*)b->d_hdr.p;
+    // every kernel kind of every lane in turn on the batch stream, events
+    // around each kind: sweep, boundary, correction (band gather, sweeps,
+    // band apply), bookkeeping
+    static const int cat_of[6] = {0, 1, 2, 2, 2, 3};
+    hipEvent_t ev[7];
+    for (int k = 0; k < 7; ++k) HIPB(b, hipEventCreate(&ev[k]));
     for (int t = 0; t < nsteps; ++t) {
         HIPB(b, hipEventRecord(ev[0], b->stream));
-        HIPB(b, launch_sweep(b->f64, b->tiling, sims, (const int4*)b->d_tiles.p, hdr, 0, b->grid_sweep, -1, b->stream));
-        HIPB(b, hipEventRecord(ev[1], b->stream));
-        HIPB(b, launch_boundary(b->f64, sims, (const int2*)b->d_bc.p, hdr, 0, b->grid_bc, -1, b->stream));
-        HIPB(b, hipEventRecord(ev[2], b->stream));
-        HIPB(b, launch_band(b->f64, false, sims, (const GroupDev*)b->d_groups.p, (const int2*)b->d_chunks.p, hdr, 0,
-                            b->grid_band, -1, b->stream));
-        HIPB(b, launch_ib(b->f64, b->max_group, sims, (GroupDev*)b->d_groups.p, hdr, 0, b->grid_ib, -1, b->stream));
-        HIPB(b, launch_band(b->f64, true, sims, (const GroupDev*)b->d_groups.p, (const int2*)b->d_chunks.p, hdr, 0,
-                            b->grid_band, -1, b->stream));
-        HIPB(b, hipEventRecord(ev[3], b->stream));
-        HIPB(b, launch_advance((SimDev*)b->d_sims.p, hdr, 0, b->stream));
-        HIPB(b, hipEventRecord(ev[4], b->stream));
-        HIPB(b, hipEventSynchronize(ev[4]));
-        for (int k = 0; k < 4; ++k) {
+        for (int k = 0; k < 6; ++k) {
+            for (int l = 0; l < b->nlanes; ++l) HIPB(b, launch_kind(b, l, k, b->stream));
+            HIPB(b, hipEventRecord(ev[k + 1], b->stream));
+        }
+        HIPB(b, hipEventSynchronize(ev[6]));
+        for (int k = 0; k < 6; ++k) {
             float m = 0.f;
             HIPB(b, hipEventElapsedTime(&m, ev[k], ev[k + 1]));
-            ms[k] += m;
+            ms[cat_of[k]] += m;
         }
     }
-    for (int k = 0; k < 5; ++k) (void)hipEventDestroy(ev[k]);
+    for (int k = 0; k < 7; ++k) (void)hipEventDestroy(ev[k]);
     return LBM_OK;
 }
 

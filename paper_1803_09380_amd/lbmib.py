@@ -77,6 +77,8 @@ SIGNATURES = [
     ("lbm_batch_autotune", _ST, [_P, _I32, ctypes.POINTER(_I32)]),
     ("lbm_batch_set_tiling", _ST, [_P, _I32]),
     ("lbm_batch_get_tiling", _I32, [_P]),
+    ("lbm_batch_set_lanes", _ST, [_P, _I32]),
+    ("lbm_batch_get_lanes", _I32, [_P]),
     ("lbm_tiling_count", _I32, []),
     ("lbm_tiling_info", _ST, [_I32, ctypes.POINTER(_I32), ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
     ("lbm_batch_profile", _ST, [_P, _I32, _DP, ctypes.POINTER(_I64)]),
@@ -350,6 +352,16 @@ class Batch:
     def tiling(self):
         """Index of the sweep tiling in use."""
         return load().lbm_batch_get_tiling(self._h)
+
+    def set_lanes(self, n):
+        rc = load().lbm_batch_set_lanes(self._h, n)
+        if rc != OK:
+            raise LbmError(rc, "lbm_batch_set_lanes")
+
+    @property
+    def lanes(self):
+        """Lanes (streams) the batch replays its steps on."""
+        return load().lbm_batch_get_lanes(self._h)
 
 
 def tilings():

@@ -180,3 +180,56 @@ def test_fp64_batch_equals_alone_and_oracle():
     o = oracle_from_case(cases[2])
     o.step(40)
     assert rel_max(sims[2].populations(), o.populations()) < 1e-12
+
+
+def _lane_cases():
+    """A member with a large body group (Couette 176: 415-marker outer circle)
+    and members with small ones holding more nodes, so the batch splits."""
+    return [wl.couette(176, precision=wl.F32)] + _cases() + [
+        wl.cylinder(nx=200, ny=100, D=12.0, centre=(50.0, 50.0), U=0.05, Re=40.0)]
+
+
+def test_two_lanes_give_the_same_bits():
+    """The member with a large body group goes to its own lane on a second
+    stream; every member's result is the same with one lane, with two lanes,
+    and alone."""
+    _say("lanes: one vs two vs alone, 17 steps")
+    cases = _lane_cases()
+    res = {}
+    for lanes in (1, 2):
+        sims = [gpu_from_case(c, precision=lbmib.F32_SHIFTED) for c in cases]
+        b = lbmib.Batch(lbmib.F32_SHIFTED)
+        for s in sims:
+            assert b.admit(s)
+        b.set_lanes(lanes)
+        assert b.lanes == lanes
+        b.step(17)
+        b.sync()
+        res[lanes] = [_state(s, len(c["bodies"])) for s, c in zip(sims, cases)]
+        b.close()
+    alone = gpu_from_case(cases[0], precision=lbmib.F32_SHIFTED)
+    alone.step(17)
+    for x, y in zip(res[1], res[2]):
+        _same(x, y)
+    _same(res[2][0], _state(alone, 2))
+
+
+def test_lanes_survive_admission_and_retirement():
+    _say("lanes with admission and retirement")
+    lc = _lane_cases()
+    big = gpu_from_case(lc[0], precision=lbmib.F32_SHIFTED)
+    small = [gpu_from_case(c, precision=lbmib.F32_SHIFTED) for c in lc[1:]]
+    b = lbmib.Batch(lbmib.F32_SHIFTED)
+    for s in small:
+        assert b.admit(s)
+    b.step(5)
+    assert b.admit(big, steps=7)
+    assert b.lanes == 2
+    b.step(9)
+    b.sync()
+    assert big.step_count == 7 and all(s.step_count == 14 for s in small)
+    b.retire(big)
+    assert b.lanes == 1
+    b.step(3)
+    b.sync()
+    assert all(s.step_count == 17 for s in small)
