@@ -945,6 +945,29 @@ __device__ __forceinline__ nv4<T> band_record(const T f[9], T rho_base) {
     return rec;
 }
 
+// Outputs of marker g after the sweeps: force and torque of its accumulated
+// deviation, the mismatch left (dmx, dmy) and the slip relative to the
+// interpolated density rs, for the FP64 reductions; and the totals of the
+// sweeps (ds times the sums of dm and dPi) for the final spread (k_band_apply).
+template <typename T>
+__device__ __forceinline__ void marker_outputs(const SimDev& S, const GroupDev& G, const GroupLookup& L, int g,
+                                               const T acc[5], T dmx, T dmy, T rs) {
+    int body;
+    const int mi = lookup(L, g, body);
+    const double ds = ldm<false>(S.mds + mi);
+    const BodyDev& Bd = S.bodies[body];
+    const double Fx = -ds * (double)acc[0], Fy = -ds * (double)acc[1];
+    const double r2 = (double)dmx * (double)dmx + (double)dmy * (double)dmy;
+    double* mr = G.m_red + g * 5;
+    mr[0] = Fx;
+    mr[1] = Fy;
+    mr[2] = (S.mX[mi] - Bd.xc[0]) * Fy - (S.mY[mi] - Bd.xc[1]) * Fx;
+    mr[3] = r2;
+    mr[4] = sqrt(r2) / (double)rs;
+#pragma unroll
+    for (int c = 0; c < 5; ++c) stm<false>(reinterpret_cast<T*>(G.m_wtot) + g * 5 + c, T(ds * (double)acc[c]));
+}
+
 // Steps 2-5 of a group's correction (gather, N sweeps on (rho, j), per-marker
 // totals of the sweeps) for one placement of its working arrays.  Groups with
 // fixed plans have their band records gathered beforehand (k_band_gather);
@@ -1047,36 +1070,274 @@ __device__ __forceinline__ void correct_group(const SimDev& S, const GroupDev& G
         __syncthreads();
         IB_MARK(4 + (n < 20 ? n : 19));
     }
-    // mismatch left after the sweeps, per-marker force and torque
+    // mismatch left after the sweeps, per-marker force and torque, totals
 #pragma unroll
     for (int q = 0; q < MPT; ++q) {
         const int g = tid + q * NT;
+        if (g < M) {
+            T dmx, dmy, dpxx, dpxy, dpyy, rs;
+            interp_marker<T, CORE, EXTRA>(B, g, mu[q], mv[q], dmx, dmy, dpxx, dpxy, dpyy, rs);
+            marker_outputs<T>(S, G, L, g, acc[q], dmx, dmy, rs);
+        }
+    }
+    if (tid == 0) G.flags[1] = nband;
+    IB_MARK(24);
+}
+
+// Colour-class form of a fixed band whose stencil rows are all four consecutive
+// band nodes.  Markers are coloured so that no two of a class share a band
+// node; the node pass then walks the classes in order, one thread per stencil
+// row (marker, ky) adding D * (ds dm) into its four nodes, with no conflicts
+// inside a class and a fixed order of the classes at every node.  rho enters
+// the sweeps only through each marker's interpolated density, which does not
+// change during them and stays in a register; the band keeps 1/rho and j.
+// Per-marker arrays are stored by position (class, then marker).  Everything
+// the sweeps read is in LDS.
+template <typename T>
+struct ColBand {
+    T* inv;                 // 1/rho per band node
+    nv2<T>* j;              // j per band node
+    T* wt;                  // per-position weights ds * dm of the current sweep
+    T* phi;                 // [8 M] phi_x[4], phi_y[4] per position
+    unsigned short* rows;   // [4 M] first band node of each stencil row per position
+};
+
+__device__ __forceinline__ void row_starts(nv2<unsigned> rv, int rs[4]) {
+    rs[0] = (int)(rv.x & 0xffffu);
+    rs[1] = (int)(rv.x >> 16);
+    rs[2] = (int)(rv.y & 0xffffu);
+    rs[3] = (int)(rv.y >> 16);
+}
+
+// density interpolated at marker g from the band records in device memory
+// (the same weights and order as the sweeps' interpolation)
+template <typename T>
+__device__ __forceinline__ T interp_rho(const nv4<T>* node4, nv2<unsigned> rv, const T* phi_g, int g) {
+    int rs[4];
+    row_starts(rv, rs);
+    const nv4<T> a = ldm<false>(reinterpret_cast<const nv4<T>*>(phi_g + g * 8));
+    const nv4<T> c = ldm<false>(reinterpret_cast<const nv4<T>*>(phi_g + g * 8) + 1);
+    const T px[4] = {a.x, a.y, a.z, a.w}, py[4] = {c.x, c.y, c.z, c.w};
+    T rho[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) rho[q] = ldm<false>(reinterpret_cast<const T*>(node4 + rs[q >> 2] + (q & 3)));
+    T r = 0;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) r += (px[q & 3] * py[q >> 2]) * rho[q];
+    return r;
+}
+
+// marker pass on the class band for the marker at position p with row starts
+// rv: deviation dm = r U - j*, dPi = r U U - Pi*
+template <typename T>
+__device__ __forceinline__ void interp_marker_col(const ColBand<T>& B, nv2<unsigned> rv, int p, T r, T U, T V, T& dmx,
+                                                  T& dmy, T& dpxx, T& dpxy, T& dpyy) {
+    int rs[4];
+    row_starts(rv, rs);
+    const nv4<T> a = ldm<true>(reinterpret_cast<const nv4<T>*>(B.phi + p * 8));
+    const nv4<T> c = ldm<true>(reinterpret_cast<const nv4<T>*>(B.phi + p * 8) + 1);
+    const T px[4] = {a.x, a.y, a.z, a.w}, py[4] = {c.x, c.y, c.z, c.w};
+    T jx = 0, jy = 0, pxx = 0, pxy = 0, pyy = 0;
+#pragma unroll
+    for (int half = 0; half < 2; ++half) {
+        nv2<T> jv[8];
+        T iv[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int kk = rs[half * 2 + (q >> 2)] + (q & 3);
+            jv[q] = ldm<true>(B.j + kk);
+            iv[q] = ldm<true>(B.inv + kk);
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const T D = px[q & 3] * py[half * 2 + (q >> 2)];
+            const T nx = jv[q].x, ny = jv[q].y, inv = iv[q];
+            jx += D * nx;
+            jy += D * ny;
+            pxx += D * nx * nx * inv;
+            pxy += D * nx * ny * inv;
+            pyy += D * ny * ny * inv;
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    dmx = r * U - jx;
+    dmy = r * V - jy;
+    dpxx = r * U * U - pxx;
+    dpxy = r * U * V - pxy;
+    dpyy = r * V * V - pyy;
+}
+
+// One stencil row of the class spread: D * (ds dm) of the marker at position p
+// added to the four band nodes from k0.  With two rows they are requested together.
+template <typename T, int R>
+__device__ __forceinline__ void class_rows(const ColBand<T>& B, const int p[R], const int ky[R], const int k0[R],
+                                           const bool on[R]) {
+    nv4<T> px[R];
+    T py[R];
+    nv2<T> w[R], jv[R][4];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        if (!on[r]) continue;
+        px[r] = ldm<true>(reinterpret_cast<const nv4<T>*>(B.phi + p[r] * 8));
+        py[r] = ldm<true>(B.phi + p[r] * 8 + 4 + ky[r]);
+        w[r] = ldm<true>(reinterpret_cast<const nv2<T>*>(B.wt) + p[r]);
+#pragma unroll
+        for (int kx = 0; kx < 4; ++kx) jv[r][kx] = ldm<true>(B.j + k0[r] + kx);
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        if (!on[r]) continue;
+        const T pxa[4] = {px[r].x, px[r].y, px[r].z, px[r].w};
+#pragma unroll
+        for (int kx = 0; kx < 4; ++kx) {
+            const T D = pxa[kx] * py[r];
+            jv[r][kx].x += D * w[r].x;
+            jv[r][kx].y += D * w[r].y;
+            stm<true>(B.j + k0[r] + kx, jv[r][kx]);
+        }
+    }
+}
+
+// Steps 3-5 of the correction on a class band whose records were gathered by
+// k_band_gather, for groups of at most MPT NT markers.  The marker pass takes
+// the markers in their own order (their stencils overlap from lane to lane);
+// the node pass walks the classes, with the first nodes of the thread's rows
+// held in registers when there are at most kRegClasses classes of at most two
+// rows per thread.
+constexpr int kRegClasses = 8;
+
+template <typename T, int NT, int MPT>
+__device__ __forceinline__ void correct_group_col(const SimDev& S, const GroupDev& G, const GroupLookup& L,
+                                                  ColBand<T> B, const int* coff, const T* phi_g, int M, int nband,
+                                                  int gi) {
+    const int tid = threadIdx.x;
+    const nv4<T>* node4 = reinterpret_cast<const nv4<T>*>(G.node4);
+    const int len = max(nband, M);
+    for (int i = tid; i < len; i += NT) {
+        if (i < nband) {
+            const nv4<T> rec = ldm<false>(node4 + i);
+            nv2<T> jj;
+            jj.x = rec.z;
+            jj.y = rec.w;
+            stm<true>(B.inv + i, rec.y);
+            stm<true>(B.j + i, jj);
+        }
+        if (i < M) {
+            const int g = ldm<false>(G.cord + i);
+            const nv4<T>* src = reinterpret_cast<const nv4<T>*>(phi_g + g * 8);
+            nv4<T>* dst = reinterpret_cast<nv4<T>*>(B.phi + i * 8);
+            stm<true>(dst, ldm<false>(src));
+            stm<true>(dst + 1, ldm<false>(src + 1));
+            stm<true>(reinterpret_cast<nv2<unsigned>*>(B.rows + i * 4),
+                      ldm<false>(reinterpret_cast<const nv2<unsigned>*>(G.m_rows) + g));
+        }
+    }
+    IB_MARK(2);
+    // the thread's markers g = tid + q NT and their positions
+    int pm[MPT];
+    T mu[MPT], mv[MPT], mds[MPT], rr[MPT];
+    nv2<unsigned> rw[MPT];
+    T acc[MPT][5];
+#pragma unroll
+    for (int q = 0; q < MPT; ++q) {
+        const int g = tid + q * NT;
+        pm[q] = 0;
+        mu[q] = mv[q] = mds[q] = rr[q] = T(0);
+        rw[q].x = rw[q].y = 0u;
         if (g < M) {
             int body;
             const int mi = lookup(L, g, body);
-            T dmx, dmy, dpxx, dpxy, dpyy, rs;
-            interp_marker<T, CORE, EXTRA>(B, g, mu[q], mv[q], dmx, dmy, dpxx, dpxy, dpyy, rs);
-            const double ds = S.mds[mi];
-            const BodyDev& Bd = S.bodies[body];
-            const double Fx = -ds * (double)acc[q][0], Fy = -ds * (double)acc[q][1];
-            const double r2 = (double)dmx * (double)dmx + (double)dmy * (double)dmy;
-            double* mr = G.m_red + g * 5;
-            mr[0] = Fx;
-            mr[1] = Fy;
-            mr[2] = (S.mX[mi] - Bd.xc[0]) * Fy - (S.mY[mi] - Bd.xc[1]) * Fx;
-            mr[3] = r2;
-            mr[4] = sqrt(r2) / (double)rs;
+            pm[q] = ldm<false>(G.cord + M + g);
+            mu[q] = T(ldm<false>(S.mU + mi));
+            mv[q] = T(ldm<false>(S.mV + mi));
+            mds[q] = T(ldm<false>(S.mds + mi));
+            rw[q] = ldm<false>(reinterpret_cast<const nv2<unsigned>*>(G.m_rows) + g);
+            rr[q] = interp_rho<T>(node4, rw[q], phi_g, g);
+        }
+#pragma unroll
+        for (int c = 0; c < 5; ++c) acc[q][c] = T(0);
+    }
+    __syncthreads();
+    // the class offsets one per lane, and the first nodes of the thread's rows
+    // (4 p + ky = 4 coff[c] + tid + h NT) of every class, two 16-bit halves
+    const int ncolor = G.ncolor;
+    const int coffv = (tid & 63) <= ncolor ? coff[tid & 63] : 0;
+    bool reg = ncolor <= kRegClasses;
+    for (int c = 0; c < ncolor; ++c) reg = reg && 4 * (coff[c + 1] - coff[c]) <= 2 * NT;
+    unsigned k0h[kRegClasses];
+#pragma unroll
+    for (int c = 0; c < kRegClasses; ++c) {
+        k0h[c] = 0u;
+        if (reg && c < ncolor) {
+            const int base = 4 * coff[c], nrow = 4 * (coff[c + 1] - coff[c]);
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+                if (tid + h * NT < nrow) k0h[c] |= (unsigned)ldm<true>(B.rows + base + tid + h * NT) << (16 * h);
         }
     }
-    // totals of the sweeps for the final spread (k_band_apply), in device memory
+    IB_MARK(3);
+    const int iters = S.ib_iters;
+    for (int n = 0; n < iters; ++n) {
+#pragma unroll
+        for (int q = 0; q < MPT; ++q) {
+            const int g = tid + q * NT;
+            if (g < M) {
+                T dmx, dmy, dpxx, dpxy, dpyy;
+                interp_marker_col<T>(B, rw[q], pm[q], rr[q], mu[q], mv[q], dmx, dmy, dpxx, dpxy, dpyy);
+                acc[q][0] += dmx;
+                acc[q][1] += dmy;
+                acc[q][2] += dpxx;
+                acc[q][3] += dpxy;
+                acc[q][4] += dpyy;
+                nv2<T> w;
+                w.x = mds[q] * dmx;
+                w.y = mds[q] * dmy;
+                stm<true>(reinterpret_cast<nv2<T>*>(B.wt) + pm[q], w);
+            }
+        }
+        __syncthreads();
+        if (n < 2) IB_MARK(28 + n);
+        // Eqs. 26-27 on the momentum, class by class
+        if (reg) {
+#pragma unroll
+            for (int c = 0; c < kRegClasses; ++c) {
+                if (c < ncolor) {
+                    const int c0 = __builtin_amdgcn_readlane(coffv, c), c1 = __builtin_amdgcn_readlane(coffv, c + 1);
+                    int p[2], ky[2], k0[2];
+                    bool on[2];
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        const int t = tid + h * NT, pk = 4 * c0 + t;
+                        on[h] = t < 4 * (c1 - c0);
+                        p[h] = pk >> 2;
+                        ky[h] = pk & 3;
+                        k0[h] = (int)((k0h[c] >> (16 * h)) & 0xFFFFu);
+                    }
+                    class_rows<T, 2>(B, p, ky, k0, on);
+                    __syncthreads();
+                }
+            }
+        } else {
+            for (int c = 0; c < ncolor; ++c) {
+                const int p0 = coff[c], rows_c = 4 * (coff[c + 1] - p0);
+                for (int t = tid; t < rows_c; t += NT) {
+                    const int pk = 4 * p0 + t;
+                    const int p[1] = {pk >> 2}, ky[1] = {pk & 3}, k0[1] = {(int)ldm<true>(B.rows + pk)};
+                    const bool on[1] = {true};
+                    class_rows<T, 1>(B, p, ky, k0, on);
+                }
+                __syncthreads();
+            }
+        }
+        IB_MARK(4 + (n < 20 ? n : 19));
+    }
 #pragma unroll
     for (int q = 0; q < MPT; ++q) {
         const int g = tid + q * NT;
         if (g < M) {
-            int body;
-            const double ds = ldm<false>(S.mds + lookup(L, g, body));
-#pragma unroll
-            for (int c = 0; c < 5; ++c) stm<false>(reinterpret_cast<T*>(G.m_wtot) + g * 5 + c, T(ds * (double)acc[q][c]));
+            T dmx, dmy, dpxx, dpxy, dpyy;
+            interp_marker_col<T>(B, rw[q], pm[q], rr[q], mu[q], mv[q], dmx, dmy, dpxx, dpxy, dpyy);
+            marker_outputs<T>(S, G, L, g, acc[q], dmx, dmy, rr[q]);
         }
     }
     if (tid == 0) G.flags[1] = nband;
@@ -1093,6 +1354,7 @@ __global__ void __launch_bounds__(NT)
     __shared__ double body_out[8][5];
     __shared__ GroupLookup L;
     __shared__ int bbox[4];
+    __shared__ int coff_s[kMaxColors + 1];
     const int ngroups = hdr ? hdr->ngroups : ngroups_arg;
     const int tid = threadIdx.x;
     for (int gi = blockIdx.x; gi < ngroups; gi += gridDim.x) {
@@ -1146,7 +1408,28 @@ __global__ void __launch_bounds__(NT)
             if (tid == 0 && !G.dynamic) G.flags[0] = 1;
         }
         IB_MARK(1);
-        // placement of the working arrays (the same decision on every thread)
+        // placement of the working arrays (the same decision on every thread):
+        // the segment band when the plan has one and it fits, else the entry band
+        bool done = false;
+        // (two markers per thread at most: larger groups never fit the class band)
+        constexpr int MPTC = MPT < 2 ? MPT : 2;
+        if (G.ncolor > 0 && M <= MPTC * NT) {
+            Bump cb;
+            cb.base = arena;
+            cb.off = 0;
+            ColBand<T> CB;
+            CB.inv = reinterpret_cast<T*>(cb.take((long)nband * sizeof(T)));
+            CB.j = reinterpret_cast<nv2<T>*>(cb.take(2L * nband * sizeof(T)));
+            CB.wt = reinterpret_cast<T*>(cb.take(2L * M * sizeof(T)));
+            CB.phi = reinterpret_cast<T*>(cb.take(8L * M * sizeof(T)));
+            CB.rows = reinterpret_cast<unsigned short*>(cb.take(2L * 4 * M));
+            if (CB.inv && CB.j && CB.wt && CB.phi && CB.rows) {
+                if (tid <= G.ncolor) coff_s[tid] = G.coff[tid];
+                __syncthreads();
+                correct_group_col<T, NT, MPTC>(S, G, L, CB, coff_s, phi_g, M, nband, gi);
+                done = true;
+            }
+        }
         Bump bump;
         bump.base = arena;
         bump.off = 0;
@@ -1180,12 +1463,15 @@ __global__ void __launch_bounds__(NT)
             B.phi = phi_g;
             B.ent16 = nullptr;
         }
-        if (extra)
+        if (done) {
+            // corrected on the class band
+        } else if (extra) {
             correct_group<T, NT, MPT, true, true>(S, G, L, B, phi_g, M, nband, nent, sw, gi);
-        else if (core)
+        } else if (core) {
             correct_group<T, NT, MPT, true, false>(S, G, L, B, phi_g, M, nband, nent, sw, gi);
-        else
+        } else {
             correct_group<T, NT, MPT, false, false>(S, G, L, B, phi_g, M, nband, nent, sw, gi);
+        }
         __syncthreads();
         IB_MARK(25);
         // FP64 reductions per body (order fixed by the marker index)

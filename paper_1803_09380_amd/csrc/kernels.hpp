@@ -17,6 +17,7 @@ extern const Tiling kTilings[kNumTilings];
 // Entries sorted in LDS when a plan is rebuilt on the device (16 per marker).
 constexpr int kMaxDynEntries = 8192;
 constexpr int kMaxGroupMarkers = 4096;
+constexpr int kMaxColors = 32;  // colour classes of a band spread without conflicts
 
 // All launchers enqueue on `stream`.  `parity` >= 0 forces the AA state the
 // step starts from; -1 reads it from each simulation's descriptor (batches).

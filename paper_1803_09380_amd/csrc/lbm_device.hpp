@@ -120,6 +120,13 @@ struct GroupDev {
     unsigned short* m_rows;   // [M * 4] first band node of each stencil row, 0xFFFF where the
                               // row's nodes are not 4 consecutive band nodes (fixed plans)
     double* m_red;            // [M * 5] per-marker Fx, Fy, T, |dm|^2, slip for the reductions
+    // Colour classes of a fixed plan whose stencil rows are all four consecutive
+    // band nodes: no two markers of a class share a band node, so a class
+    // spreads into the band without conflicts (ncolor = 0: no such plan).
+    int32_t ncolor;
+    unsigned short* cord;     // [2 M] group marker at each position (by class, then marker),
+                              // then the position of each group marker
+    int32_t* coff;            // [ncolor + 1] first position of each class
 };
 
 // Work counts of a batch, read by persistent kernels so that a captured graph

@@ -20,6 +20,7 @@
 #include <cstring>
 #include <new>
 #include <numeric>
+#include <utility>
 #include <string>
 #include <vector>
 
@@ -74,7 +75,7 @@ struct HostBody {
 // One group's plan and scratch on the device plus its host descriptor.
 struct Group {
     GroupDev d{};
-    DevBuf node_cell, node_run, ent, mnode, flags, node4, ent_D, m_phi, m_wtot, m_rows, m_red;
+    DevBuf node_cell, node_run, ent, mnode, flags, node4, ent_D, m_phi, m_wtot, m_rows, m_red, cord, coff;
 };
 
 }  // namespace
@@ -397,6 +398,53 @@ lbm_status rebuild_ib(lbm_sim* s) {
             d.nband = nband;
             d.nent = (int)ent.size();
         }
+        // colour classes: every stencil row four consecutive band nodes; two
+        // markers conflict when their stencils share a band node; greedy
+        // colouring in marker order
+        std::vector<unsigned short> cord;
+        std::vector<int> coff;
+        if (!d.dynamic && M > 0 && M <= 0xFFFF && nband < 0xFFFF) {
+            bool regular = true;
+            for (int g = 0; g < M && regular; ++g)
+                for (int ky = 0; ky < 4; ++ky) {
+                    const int* m = &mnode[16 * (size_t)g + 4 * ky];
+                    if (m[0] < 0 || m[1] != m[0] + 1 || m[2] != m[0] + 2 || m[3] != m[0] + 3) {
+                        regular = false;
+                        break;
+                    }
+                }
+            if (regular) {
+                std::vector<int> color(M, -1);
+                int ncolor = 0;
+                for (int g = 0; g < M && ncolor <= kMaxColors; ++g) {
+                    unsigned long long used = 0;
+                    for (int k = 0; k < 16; ++k) {
+                        const int nd = mnode[16 * (size_t)g + k];
+                        for (int e = node_run[nd]; e < node_run[nd + 1]; ++e) {
+                            const int o = ent[e] >> 4;
+                            if (o != g && color[o] >= 0) used |= 1ull << color[o];
+                        }
+                    }
+                    int c = 0;
+                    while (c < 64 && (used >> c & 1ull)) ++c;
+                    color[g] = c;
+                    ncolor = std::max(ncolor, c + 1);
+                }
+                if (ncolor <= kMaxColors) {
+                    coff.assign(ncolor + 1, 0);
+                    for (int g = 0; g < M; ++g) ++coff[color[g] + 1];
+                    for (int c = 0; c < ncolor; ++c) coff[c + 1] += coff[c];
+                    cord.assign(2 * (size_t)M, 0);  // marker at each position, then position of each marker
+                    std::vector<int> fill(coff.begin(), coff.end() - 1);
+                    for (int g = 0; g < M; ++g) {
+                        const int pos = fill[color[g]]++;
+                        cord[pos] = (unsigned short)g;
+                        cord[M + g] = (unsigned short)pos;
+                    }
+                }
+            }
+        }
+        d.ncolor = cord.empty() ? 0 : (int)coff.size() - 1;
         d.cap_nodes = std::max(1, nband);
         HIPS(s, G->node_cell.alloc(sizeof(int) * d.cap_nodes));
         HIPS(s, G->node_run.alloc(sizeof(int) * (d.cap_nodes + 1)));
@@ -410,6 +458,10 @@ lbm_status rebuild_ib(lbm_sim* s) {
         HIPS(s, G->m_wtot.alloc(tsz * 5 * std::max(1, M)));
         HIPS(s, G->m_rows.alloc(sizeof(unsigned short) * 4 * std::max(1, M)));
         HIPS(s, G->m_red.alloc(sizeof(double) * 5 * std::max(1, M)));
+        if (d.ncolor) {
+            HIPS(s, G->cord.alloc(sizeof(unsigned short) * cord.size()));
+            HIPS(s, G->coff.alloc(sizeof(int) * coff.size()));
+        }
         d.node_cell = (int*)G->node_cell.p;
         d.node_run = (int*)G->node_run.p;
         d.ent = (int*)G->ent.p;
@@ -421,12 +473,18 @@ lbm_status rebuild_ib(lbm_sim* s) {
         d.m_wtot = G->m_wtot.p;
         d.m_rows = (unsigned short*)G->m_rows.p;
         d.m_red = (double*)G->m_red.p;
+        d.cord = (unsigned short*)G->cord.p;
+        d.coff = (int*)G->coff.p;
         if (!d.dynamic) {
             HIPS(s, hipMemcpyAsync(d.node_cell, node_cell.data(), sizeof(int) * node_cell.size(), hipMemcpyHostToDevice, st));
             HIPS(s, hipMemcpyAsync(d.node_run, node_run.data(), sizeof(int) * node_run.size(), hipMemcpyHostToDevice, st));
             if (!ent.empty())
                 HIPS(s, hipMemcpyAsync(d.ent, ent.data(), sizeof(int) * ent.size(), hipMemcpyHostToDevice, st));
             if (M) HIPS(s, hipMemcpyAsync(d.mnode, mnode.data(), sizeof(int) * mnode.size(), hipMemcpyHostToDevice, st));
+            if (d.ncolor) {
+                HIPS(s, hipMemcpyAsync(d.cord, cord.data(), sizeof(unsigned short) * cord.size(), hipMemcpyHostToDevice, st));
+                HIPS(s, hipMemcpyAsync(d.coff, coff.data(), sizeof(int) * coff.size(), hipMemcpyHostToDevice, st));
+            }
         }
     }
     std::vector<GroupDev> gd;
@@ -817,7 +875,7 @@ size_t lbm_device_bytes(const lbm_sim* s) {
     for (const Group* g : s->grp)
         b += g->node_cell.bytes + g->node_run.bytes + g->ent.bytes + g->mnode.bytes + g->flags.bytes +
              g->node4.bytes + g->ent_D.bytes + g->m_phi.bytes +
-             g->m_wtot.bytes + g->m_rows.bytes + g->m_red.bytes;
+             g->m_wtot.bytes + g->m_rows.bytes + g->m_red.bytes + g->cord.bytes + g->coff.bytes;
     return b;
 }
 

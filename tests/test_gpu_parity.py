@@ -395,11 +395,15 @@ def test_large_group_device_memory_placement_f64():
     _compare_case(wl.couette(400), 20)
 
 
-def test_large_group_fp32():
-    """Couette 512 in FP32: the 1206-marker circle keeps its band in LDS and
-    reads its stencil entries from device memory."""
-    _say("couette 512 f32 vs oracle, 30 steps")
-    case = wl.couette(512)
+@pytest.mark.parametrize("side", [512, 620, 700])
+def test_large_group_fp32(side):
+    """Couette in FP32 with a large outer circle: at side 512 (1206 markers)
+    the whole correction runs on the colour-class band in LDS; at side 620
+    (1461 markers) the band and weights stay in LDS and the stencil entries
+    are read from device memory; at side 700 (1649 markers) everything is
+    read from device memory."""
+    _say("couette %d f32 vs oracle, 30 steps" % side)
+    case = wl.couette(side)
     o = oracle_from_case(case)
     g = gpu_from_case(case, precision=lbmib.F32_SHIFTED)
     o.step(30)
@@ -410,3 +414,44 @@ def test_large_group_fp32():
         (Fg, Tg, _, _), (Fo, To, _, _) = g.forces(k), o.forces(k)
         # the outer circle has not felt the flow yet: floor by the case's force scale
         assert np.abs(Fg - Fo).max() <= 1e-4 * max(scales), (k, Fg, Fo)
+
+
+def _two_close_cylinders(precision):
+    """Two fixed circles of diameter 20 whose surfaces are 2.7 spacings apart:
+    their stencils share band nodes, so they form one group whose colour
+    classes span both bodies (nine classes)."""
+    case = wl.cylinder(nx=160, ny=100, D=20.0, centre=(40.2, 50.3), Re=20.0, precision=precision)
+    b0 = case["bodies"][0]
+    b1 = dict(b0, xy=wl.circle_markers(62.9, 50.3, 10.0, b0["n"]), uv=np.zeros((b0["n"], 2)), xc=(62.9, 50.3))
+    case["bodies"] = [b0, b1]
+    return case
+
+
+def test_touching_cylinders_one_group_f64():
+    _say("two touching cylinders f64, 40 steps")
+    _compare_case(_two_close_cylinders(wl.F64), 40)
+
+
+def test_touching_cylinders_one_group_fp32():
+    _say("two touching cylinders f32, 40 steps")
+    case = _two_close_cylinders(wl.F32)
+    o, g = oracle_from_case(case), gpu_from_case(case, precision=lbmib.F32_SHIFTED)
+    o.step(40)
+    g.step(40)
+    assert velocity_rel(g.fields(), o.fields()) < 1e-5
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_densely_marked_cylinder(precision):
+    """151 markers on a circle of radius 12 (half a spacing apart): eleven
+    colour classes, more than the spread keeps in registers."""
+    _say("densely marked cylinder %s, 40 steps" % precision)
+    if precision == "f64":
+        case = wl.cylinder(nx=160, ny=100, D=24.0, centre=(50.3, 50.7), Re=20.0, n_markers=151, precision=wl.F64)
+        _compare_case(case, 40)
+    else:
+        case = wl.cylinder(nx=160, ny=100, D=24.0, centre=(50.3, 50.7), Re=20.0, n_markers=151, precision=wl.F32)
+        o, g = oracle_from_case(case), gpu_from_case(case, precision=lbmib.F32_SHIFTED)
+        o.step(40)
+        g.step(40)
+        assert velocity_rel(g.fields(), o.fields()) < 1e-5
