@@ -133,7 +133,7 @@ def fp64_leg(args, cases, lbmib, wl, torch, np):
     b2 = lbmib.Batch(lbmib.F32_SHIFTED)
     for s in sample:
         b2.admit(s)
-    b2.step(4)
+    b2.step(10)  # captures the replayed graphs (1 and 8 steps) before the timed steps
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     b2.step(args.fp64_steps)

@@ -7,7 +7,9 @@
 //   k_ib           one workgroup per body group: plan and weights of moving
 //                  bodies, N Jacobi sweeps of the correction of Sec. 2.3 on the
 //                  band's (rho, j), per-marker totals, FP64 force/torque
-//                  reductions and the rigid-body update.
+//                  reductions and the rigid-body update.  Fixed bands are
+//                  spread by colour classes of markers that share no band
+//                  node; other bands through per-node entry lists.
 //   k_band_apply   one final spread of the accumulated deviation into the nine
 //                  populations of every band node.
 //   k_advance      per-simulation step bookkeeping of batches.
@@ -152,15 +154,30 @@ __device__ __forceinline__ void mrt(T h[9], T rho_base, const T rate[9], uint32_
 
 // ---------------------------------------------------------------- sweep
 
+// Kernels on a lane's critical path (boundary rules, band gather and apply,
+// correction) raise their waves' issue priority above the sweep's: when two
+// lanes overlap, their waves share SIMDs with streaming sweep waves that mostly
+// wait on memory, and the latency-bound kernels would otherwise queue behind them.
+__device__ __forceinline__ void raise_wave_priority() { __builtin_amdgcn_s_setprio(2); }
+
 template <typename T, int TX, int TY, int RPT, bool NTMP>
 __global__ void __launch_bounds__(TX* TY)
     k_sweep(const SimDev* __restrict__ sims, const int4* __restrict__ tiles,
-            const BatchHeader* __restrict__ hdr, int ntiles_arg, int parity) {
+            const BatchHeader* __restrict__ hdr, int ntiles_arg, int parity, int part) {
     int t0 = blockIdx.x, t1 = hdr ? hdr->ntiles : ntiles_arg, dt = gridDim.x;
     if (hdr && (gridDim.x & 7) == 0) {
+        // part 0 or 1: the first or second half of every XCD's tiles
         const int xcd = blockIdx.x & 7;
-        t0 = hdr->xcd_start[xcd] + (blockIdx.x >> 3);
-        t1 = hdr->xcd_start[xcd + 1];
+        int s = hdr->xcd_start[xcd], e = hdr->xcd_start[xcd + 1];
+        if (part >= 0) {
+            const int mid = s + (e - s) / 2;
+            if (part == 0)
+                e = mid;
+            else
+                s = mid;
+        }
+        t0 = s + (blockIdx.x >> 3);
+        t1 = e;
         dt = gridDim.x >> 3;
     }
     for (int t = t0; t < t1; t += dt) {
@@ -281,6 +298,7 @@ template <typename T>
 __global__ void __launch_bounds__(256)
     k_boundary(const SimDev* __restrict__ sims, const int2* __restrict__ items,
                const BatchHeader* __restrict__ hdr, int nitems_arg, int parity) {
+    raise_wave_priority();
     const int nitems = hdr ? hdr->nbc : nitems_arg;
     for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
         const int2 item = items[it];
@@ -1355,6 +1373,7 @@ __global__ void __launch_bounds__(NT)
     __shared__ GroupLookup L;
     __shared__ int bbox[4];
     __shared__ int coff_s[kMaxColors + 1];
+    raise_wave_priority();
     const int ngroups = hdr ? hdr->ngroups : ngroups_arg;
     const int tid = threadIdx.x;
     for (int gi = blockIdx.x; gi < ngroups; gi += gridDim.x) {
@@ -1580,6 +1599,7 @@ template <typename T>
 __global__ void __launch_bounds__(256)
     k_band_gather(const SimDev* __restrict__ sims, const GroupDev* __restrict__ groups,
                   const int2* __restrict__ chunks, const BatchHeader* __restrict__ hdr, int nchunks_arg, int parity) {
+    raise_wave_priority();
     const int nchunks = hdr ? hdr->nchunks : nchunks_arg;
     for (int c = blockIdx.x; c < nchunks; c += gridDim.x) {
         const int2 ch = chunks[c];
@@ -1606,6 +1626,7 @@ template <typename T>
 __global__ void __launch_bounds__(256)
     k_band_apply(const SimDev* __restrict__ sims, const GroupDev* __restrict__ groups,
                  const int2* __restrict__ chunks, const BatchHeader* __restrict__ hdr, int nchunks_arg, int parity) {
+    raise_wave_priority();
     const int nchunks = hdr ? hdr->nchunks : nchunks_arg;
     for (int c = blockIdx.x; c < nchunks; c += gridDim.x) {
         const int2 ch = chunks[c];
@@ -1715,41 +1736,41 @@ __global__ void k_set_eq(const SimDev* sim, int sw, const double* rho, const dou
 
 template <typename T, int TX, int TY, int RPT, bool NTMP>
 static hipError_t sweep_t(const SimDev* sims, const int4* tiles, const BatchHeader* hdr, int ntiles, int grid,
-                          int parity, hipStream_t st) {
+                          int parity, int part, hipStream_t st) {
     hipLaunchKernelGGL((k_sweep<T, TX, TY, RPT, NTMP>), dim3(grid), dim3(TX, TY), 0, st, sims, tiles, hdr, ntiles,
-                       parity);
+                       parity, part);
     return hipGetLastError();
 }
 
 template <typename T>
 static hipError_t sweep_tt(int tiling, const SimDev* sims, const int4* tiles, const BatchHeader* hdr, int ntiles,
-                           int grid, int parity, hipStream_t st) {
+                           int grid, int parity, int part, hipStream_t st) {
     switch (tiling) {
-        case 0: return sweep_t<T, 64, 4, 1, false>(sims, tiles, hdr, ntiles, grid, parity, st);
-        case 1: return sweep_t<T, 64, 4, 2, false>(sims, tiles, hdr, ntiles, grid, parity, st);
-        case 2: return sweep_t<T, 128, 2, 2, false>(sims, tiles, hdr, ntiles, grid, parity, st);
-        case 3: return sweep_t<T, 256, 1, 2, false>(sims, tiles, hdr, ntiles, grid, parity, st);
-        case 4: return sweep_t<T, 256, 1, 4, false>(sims, tiles, hdr, ntiles, grid, parity, st);
-        case 5: return sweep_t<T, 64, 4, 4, false>(sims, tiles, hdr, ntiles, grid, parity, st);
-        case 6: return sweep_t<T, 256, 1, 1, false>(sims, tiles, hdr, ntiles, grid, parity, st);
-        case 7: return sweep_t<T, 128, 2, 1, false>(sims, tiles, hdr, ntiles, grid, parity, st);
-        case 8: return sweep_t<T, 64, 4, 1, true>(sims, tiles, hdr, ntiles, grid, parity, st);
-        case 9: return sweep_t<T, 64, 4, 2, true>(sims, tiles, hdr, ntiles, grid, parity, st);
-        case 10: return sweep_t<T, 128, 2, 2, true>(sims, tiles, hdr, ntiles, grid, parity, st);
-        case 11: return sweep_t<T, 256, 1, 2, true>(sims, tiles, hdr, ntiles, grid, parity, st);
-        case 12: return sweep_t<T, 256, 1, 4, true>(sims, tiles, hdr, ntiles, grid, parity, st);
-        case 13: return sweep_t<T, 64, 4, 4, true>(sims, tiles, hdr, ntiles, grid, parity, st);
-        case 14: return sweep_t<T, 256, 1, 1, true>(sims, tiles, hdr, ntiles, grid, parity, st);
-        case 15: return sweep_t<T, 128, 2, 1, true>(sims, tiles, hdr, ntiles, grid, parity, st);
+        case 0: return sweep_t<T, 64, 4, 1, false>(sims, tiles, hdr, ntiles, grid, parity, part, st);
+        case 1: return sweep_t<T, 64, 4, 2, false>(sims, tiles, hdr, ntiles, grid, parity, part, st);
+        case 2: return sweep_t<T, 128, 2, 2, false>(sims, tiles, hdr, ntiles, grid, parity, part, st);
+        case 3: return sweep_t<T, 256, 1, 2, false>(sims, tiles, hdr, ntiles, grid, parity, part, st);
+        case 4: return sweep_t<T, 256, 1, 4, false>(sims, tiles, hdr, ntiles, grid, parity, part, st);
+        case 5: return sweep_t<T, 64, 4, 4, false>(sims, tiles, hdr, ntiles, grid, parity, part, st);
+        case 6: return sweep_t<T, 256, 1, 1, false>(sims, tiles, hdr, ntiles, grid, parity, part, st);
+        case 7: return sweep_t<T, 128, 2, 1, false>(sims, tiles, hdr, ntiles, grid, parity, part, st);
+        case 8: return sweep_t<T, 64, 4, 1, true>(sims, tiles, hdr, ntiles, grid, parity, part, st);
+        case 9: return sweep_t<T, 64, 4, 2, true>(sims, tiles, hdr, ntiles, grid, parity, part, st);
+        case 10: return sweep_t<T, 128, 2, 2, true>(sims, tiles, hdr, ntiles, grid, parity, part, st);
+        case 11: return sweep_t<T, 256, 1, 2, true>(sims, tiles, hdr, ntiles, grid, parity, part, st);
+        case 12: return sweep_t<T, 256, 1, 4, true>(sims, tiles, hdr, ntiles, grid, parity, part, st);
+        case 13: return sweep_t<T, 64, 4, 4, true>(sims, tiles, hdr, ntiles, grid, parity, part, st);
+        case 14: return sweep_t<T, 256, 1, 1, true>(sims, tiles, hdr, ntiles, grid, parity, part, st);
+        case 15: return sweep_t<T, 128, 2, 1, true>(sims, tiles, hdr, ntiles, grid, parity, part, st);
         default: return hipErrorInvalidValue;
     }
 }
 
 hipError_t launch_sweep(bool f64, int tiling, const SimDev* sims, const int4* tiles, const BatchHeader* hdr,
-                        int ntiles, int grid, int parity, hipStream_t stream) {
+                        int ntiles, int grid, int parity, hipStream_t stream, int part) {
     if (grid <= 0) return hipSuccess;
-    return f64 ? sweep_tt<double>(tiling, sims, tiles, hdr, ntiles, grid, parity, stream)
-               : sweep_tt<float>(tiling, sims, tiles, hdr, ntiles, grid, parity, stream);
+    return f64 ? sweep_tt<double>(tiling, sims, tiles, hdr, ntiles, grid, parity, part, stream)
+               : sweep_tt<float>(tiling, sims, tiles, hdr, ntiles, grid, parity, part, stream);
 }
 
 hipError_t launch_boundary(bool f64, const SimDev* sims, const int2* items, const BatchHeader* hdr, int nitems,

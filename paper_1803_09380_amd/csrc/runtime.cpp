@@ -113,10 +113,12 @@ struct Lane {
     int max_group = 0;
     int grid_sweep = 0, grid_band = 0;
     hipGraphExec_t graph1 = nullptr, graphK = nullptr;
+    hipGraphExec_t graphA = nullptr, graphB = nullptr;  // one step split: sweep (two launches), the rest
     void drop() {
-        if (graph1) (void)hipGraphExecDestroy(graph1);
-        if (graphK) (void)hipGraphExecDestroy(graphK);
-        graph1 = graphK = nullptr;
+        for (hipGraphExec_t* g : {&graph1, &graphK, &graphA, &graphB}) {
+            if (*g) (void)hipGraphExecDestroy(*g);
+            *g = nullptr;
+        }
     }
 };
 
@@ -124,6 +126,9 @@ struct Lane {
 // first lane when the batch uses two: their long correction kernels overlap
 // the other lane's sweeps.
 constexpr int kHeavyGroupMarkers = 400;
+// Two lanes are launched step by step from the host; below this many nodes a
+// step is too short for that, and one lane replays graphs of several steps.
+constexpr int64_t kTwoLaneMinCells = 16 << 20;
 
 struct lbm_batch {
     bool f64 = false;
@@ -133,12 +138,13 @@ struct lbm_batch {
     bool own_stream = false;
     hipStream_t stream2 = nullptr;  // lane 1, owned
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    hipEvent_t ev_sweep = nullptr;  // lane 1's sweep of the current step is done
     std::vector<lbm_sim*> sims;
     std::vector<int> order;         // simulation table row -> index into sims
     DevBuf d_sims;
     size_t cap_sims = 0;
     Lane lane[2];
-    int lanes_req = 2;              // 1 or 2 (2: split when it pays, see upload_tables)
+    int lanes_req = 0;              // 0 automatic, 1 one lane, 2 two whenever the split exists (upload_tables)
     int nlanes = 1;                 // lanes in use
     int tiling = kTileDefault;
     int grid_bc = 0, grid_ib = 0;
@@ -150,6 +156,7 @@ struct lbm_batch {
         lane[1].drop();
         if (ev_fork) (void)hipEventDestroy(ev_fork);
         if (ev_join) (void)hipEventDestroy(ev_join);
+        if (ev_sweep) (void)hipEventDestroy(ev_sweep);
         if (stream2) (void)hipStreamDestroy(stream2);
     }
 };
@@ -961,7 +968,8 @@ lbm_status upload_tables(lbm_batch* b) {
             light.push_back(k);
         }
     }
-    const bool two = b->lanes_req == 2 && !heavy.empty() && !light.empty() && 2 * heavy_cells <= cells;
+    const bool two = b->lanes_req != 1 && !heavy.empty() && !light.empty() && 2 * heavy_cells <= cells &&
+                     (b->lanes_req == 2 || cells >= kTwoLaneMinCells);
     const int nl = two ? 2 : 1;
     if (nl != b->nlanes) drop_graphs(b);
     b->nlanes = nl;
@@ -1097,6 +1105,19 @@ hipError_t enqueue_steps(lbm_batch* b, int l, int n, hipStream_t st) {
     return hipSuccess;
 }
 
+template <typename F>
+hipError_t capture_fn(hipStream_t st, F&& enqueue, hipGraphExec_t* out) {
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return e;
+    hipError_t e2 = enqueue();
+    e = hipStreamEndCapture(st, &g);
+    if (e2 != hipSuccess) e = e2;
+    if (e == hipSuccess) e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+    if (g) (void)hipGraphDestroy(g);
+    return e;
+}
+
 hipError_t capture(lbm_batch* b, int l, int n, hipStream_t st, hipGraphExec_t* out) {
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
@@ -1116,38 +1137,67 @@ lbm_status ensure_lane_stream(lbm_batch* b) {
     HIPB(b, hipStreamCreateWithFlags(&b->stream2, hipStreamNonBlocking));
     HIPB(b, hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming));
     HIPB(b, hipEventCreateWithFlags(&b->ev_join, hipEventDisableTiming));
+    HIPB(b, hipEventCreateWithFlags(&b->ev_sweep, hipEventDisableTiming));
     return LBM_OK;
 }
 
-// n steps of every lane: replayed graphs of 8 and 1 steps per lane.
+// Two lanes, interleaved step by step.  Lane 1's sweep is split into two
+// launches (halves of every XCD's tiles) and lane 0's step t waits for lane 1's
+// sweep of step t - 1, so lane 0's sweep runs during lane 1's boundary and
+// correction kernels.  A correction workgroup needs a whole CU (its register
+// file and most of its LDS), which a running sweep never leaves free; lane 0's
+// correction finds free CUs where lane 1's first sweep launch drains.
+lbm_status run_interleaved(lbm_batch* b, int n) {
+    hipStream_t st0 = b->stream, st1 = b->stream2;
+    Lane& H = b->lane[0];
+    Lane& Lt = b->lane[1];
+    if (!H.graph1) HIPB(b, capture(b, 0, 1, st0, &H.graph1));
+    if (!Lt.graphA) {
+        const int half = 8 * ((Lt.grid_sweep / 8 + 1) / 2);
+        SimDev* sims = (SimDev*)b->d_sims.p;
+        const BatchHeader* hdr = (const BatchHeader*)Lt.d_hdr.p;
+        const int4* tiles = (const int4*)Lt.d_tiles.p;
+        HIPB(b, capture_fn(st1, [&]() {
+            hipError_t e = launch_sweep(b->f64, b->tiling, sims, tiles, hdr, 0, half, -1, st1, 0);
+            return e != hipSuccess ? e : launch_sweep(b->f64, b->tiling, sims, tiles, hdr, 0, half, -1, st1, 1);
+        }, &Lt.graphA));
+    }
+    if (!Lt.graphB)
+        HIPB(b, capture_fn(st1, [&]() {
+            for (int k = 1; k < 6; ++k) {
+                hipError_t e = launch_kind(b, 1, k, st1);
+                if (e != hipSuccess) return e;
+            }
+            return hipSuccess;
+        }, &Lt.graphB));
+    HIPB(b, hipEventRecord(b->ev_fork, st0));
+    HIPB(b, hipStreamWaitEvent(st1, b->ev_fork, 0));
+    for (int t = 0; t < n; ++t) {
+        if (t > 0) HIPB(b, hipStreamWaitEvent(st0, b->ev_sweep, 0));
+        HIPB(b, hipGraphLaunch(H.graph1, st0));
+        HIPB(b, hipGraphLaunch(Lt.graphA, st1));
+        HIPB(b, hipEventRecord(b->ev_sweep, st1));
+        HIPB(b, hipGraphLaunch(Lt.graphB, st1));
+    }
+    HIPB(b, hipEventRecord(b->ev_join, st1));
+    HIPB(b, hipStreamWaitEvent(st0, b->ev_join, 0));
+    return LBM_OK;
+}
+
+// n steps of every lane: one lane replays graphs of 8 and 1 steps; two lanes
+// are interleaved step by step (run_interleaved).
 lbm_status run_steps(lbm_batch* b, int n) {
-    hipStream_t st[2] = {b->stream, b->stream2};
     if (b->nlanes == 2) {
         lbm_status rc = ensure_lane_stream(b);
         if (rc != LBM_OK) return rc;
-        st[1] = b->stream2;
+        return run_interleaved(b, n);
     }
-    for (int l = 0; l < b->nlanes; ++l) {
-        Lane& L = b->lane[l];
-        if (!L.graph1) HIPB(b, capture(b, l, 1, st[l], &L.graph1));
-        if (!L.graphK) HIPB(b, capture(b, l, b->graphK_steps, st[l], &L.graphK));
-    }
-    if (b->nlanes == 2) {
-        HIPB(b, hipEventRecord(b->ev_fork, b->stream));
-        HIPB(b, hipStreamWaitEvent(b->stream2, b->ev_fork, 0));
-    }
-    for (int l = 0; l < b->nlanes; ++l) {
-        int left = n;
-        while (left >= b->graphK_steps) {
-            HIPB(b, hipGraphLaunch(b->lane[l].graphK, st[l]));
-            left -= b->graphK_steps;
-        }
-        while (left-- > 0) HIPB(b, hipGraphLaunch(b->lane[l].graph1, st[l]));
-    }
-    if (b->nlanes == 2) {
-        HIPB(b, hipEventRecord(b->ev_join, b->stream2));
-        HIPB(b, hipStreamWaitEvent(b->stream, b->ev_join, 0));
-    }
+    Lane& L = b->lane[0];
+    if (!L.graph1) HIPB(b, capture(b, 0, 1, b->stream, &L.graph1));
+    if (!L.graphK) HIPB(b, capture(b, 0, b->graphK_steps, b->stream, &L.graphK));
+    int left = n;
+    for (; left >= b->graphK_steps; left -= b->graphK_steps) HIPB(b, hipGraphLaunch(L.graphK, b->stream));
+    for (; left > 0; --left) HIPB(b, hipGraphLaunch(L.graph1, b->stream));
     return LBM_OK;
 }
 
@@ -1346,13 +1396,14 @@ lbm_status lbm_batch_autotune(lbm_batch* b, int32_t trials, int32_t* chosen) {
     }
     b->tiling = best;
     // then one lane against two at the chosen tiling (when two are possible)
-    if (rc == LBM_OK && b->lanes_req == 2 && b->nlanes == 2) {
+    if (rc == LBM_OK && b->lanes_req != 1 && b->nlanes == 2) {
+        const int req = b->lanes_req;
         float ms2 = 0.f, ms1 = 0.f;
         rc = trial(ms2);
         if (rc == LBM_OK) {
             b->lanes_req = 1;
             rc = trial(ms1);
-            if (rc == LBM_OK && ms2 <= ms1) b->lanes_req = 2;
+            if (rc == LBM_OK && ms2 <= ms1) b->lanes_req = req;
         }
     }
     (void)hipEventDestroy(e0);
@@ -1365,7 +1416,7 @@ lbm_status lbm_batch_autotune(lbm_batch* b, int32_t trials, int32_t* chosen) {
 }
 
 lbm_status lbm_batch_set_lanes(lbm_batch* b, int32_t lanes) {
-    if (!b || lanes < 1 || lanes > 2) return LBM_ERR_INVALID;
+    if (!b || lanes < 0 || lanes > 2) return LBM_ERR_INVALID;
     lbm_status rc = sync_back(b);
     if (rc != LBM_OK) return rc;
     b->lanes_req = lanes;

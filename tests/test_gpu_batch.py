@@ -214,12 +214,31 @@ def test_two_lanes_give_the_same_bits():
     _same(res[2][0], _state(alone, 2))
 
 
+def test_automatic_lanes_keep_small_batches_in_one_lane():
+    """By default a batch splits only when it is large enough for steps
+    launched one by one; an explicit request splits whenever it can."""
+    _say("automatic lanes on a small batch")
+    sims = [gpu_from_case(c, precision=lbmib.F32_SHIFTED) for c in _lane_cases()]
+    b = lbmib.Batch(lbmib.F32_SHIFTED)
+    for s in sims:
+        assert b.admit(s)
+    assert b.lanes == 1
+    b.set_lanes(2)
+    assert b.lanes == 2
+    b.set_lanes(0)
+    assert b.lanes == 1
+    with pytest.raises(lbmib.LbmError):
+        b.set_lanes(3)
+    b.close()
+
+
 def test_lanes_survive_admission_and_retirement():
     _say("lanes with admission and retirement")
     lc = _lane_cases()
     big = gpu_from_case(lc[0], precision=lbmib.F32_SHIFTED)
     small = [gpu_from_case(c, precision=lbmib.F32_SHIFTED) for c in lc[1:]]
     b = lbmib.Batch(lbmib.F32_SHIFTED)
+    b.set_lanes(2)
     for s in small:
         assert b.admit(s)
     b.step(5)
