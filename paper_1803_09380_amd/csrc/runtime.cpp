@@ -98,6 +98,10 @@ struct lbm_sim {
     int64_t steps = 0;
     int mcount = 0;
     int max_group = 0;  // markers of the largest body group
+    // some band node lies within three nodes of a non-periodic side (or a band
+    // is rebuilt on the device): the boundary rules and the correction may
+    // touch the same populations, so they run in order
+    bool band_near_edge = false;
     lbm_batch* batch = nullptr;
     ~lbm_sim() {
         for (Group* g : grp) delete g;
@@ -114,6 +118,7 @@ struct Lane {
     int grid_sweep = 0, grid_band = 0;
     hipGraphExec_t graph1 = nullptr, graphK = nullptr;
     hipGraphExec_t graphA = nullptr, graphB = nullptr;  // one step split: sweep (two launches), the rest
+    bool bnd_apart = false;  // graphB leaves out the boundary rules and the bookkeeping (run_interleaved)
     void drop() {
         for (hipGraphExec_t* g : {&graph1, &graphK, &graphA, &graphB}) {
             if (*g) (void)hipGraphExecDestroy(*g);
@@ -137,8 +142,10 @@ struct lbm_batch {
     hipStream_t stream = nullptr;   // the caller's (or an own) stream: lane 0
     bool own_stream = false;
     hipStream_t stream2 = nullptr;  // lane 1, owned
+    hipStream_t stream3 = nullptr;  // lane 1's boundary rules beside its correction, owned
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     hipEvent_t ev_sweep = nullptr;  // lane 1's sweep of the current step is done
+    hipEvent_t ev_bnd = nullptr;    // lane 1's boundary rules of the current step are done
     std::vector<lbm_sim*> sims;
     std::vector<int> order;         // simulation table row -> index into sims
     DevBuf d_sims;
@@ -157,6 +164,8 @@ struct lbm_batch {
         if (ev_fork) (void)hipEventDestroy(ev_fork);
         if (ev_join) (void)hipEventDestroy(ev_join);
         if (ev_sweep) (void)hipEventDestroy(ev_sweep);
+        if (ev_bnd) (void)hipEventDestroy(ev_bnd);
+        if (stream3) (void)hipStreamDestroy(stream3);
         if (stream2) (void)hipStreamDestroy(stream2);
     }
 };
@@ -357,6 +366,7 @@ lbm_status rebuild_ib(lbm_sim* s) {
     for (Group* g : s->grp) delete g;
     s->grp.clear();
     const size_t tsz = s->f64 ? sizeof(double) : sizeof(float);
+    s->band_near_edge = false;
     for (auto& members : groups) {
         Group* G = new (std::nothrow) Group();
         if (!G) return fail(s, LBM_ERR_NOMEM, "host allocation");
@@ -404,6 +414,13 @@ lbm_status rebuild_ib(lbm_sim* s) {
             nband = (int)node_cell.size();
             d.nband = nband;
             d.nent = (int)ent.size();
+            const int nx = s->h.nx, ny = s->h.ny;
+            for (int c : node_cell) {
+                const int x = c % nx, y = c / nx;
+                if ((!s->h.px && (x < 3 || x > nx - 4)) || (!s->h.py && (y < 3 || y > ny - 4))) s->band_near_edge = true;
+            }
+        } else {
+            s->band_near_edge = true;
         }
         // colour classes: every stencil row four consecutive band nodes; two
         // markers conflict when their stencils share a band node; greedy
@@ -1119,15 +1136,7 @@ hipError_t capture_fn(hipStream_t st, F&& enqueue, hipGraphExec_t* out) {
 }
 
 hipError_t capture(lbm_batch* b, int l, int n, hipStream_t st, hipGraphExec_t* out) {
-    hipGraph_t g = nullptr;
-    hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
-    if (e != hipSuccess) return e;
-    hipError_t e2 = enqueue_steps(b, l, n, st);
-    e = hipStreamEndCapture(st, &g);
-    if (e2 != hipSuccess) e = e2;
-    if (e == hipSuccess) e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
-    if (g) (void)hipGraphDestroy(g);
-    return e;
+    return capture_fn(st, [&]() { return enqueue_steps(b, l, n, st); }, out);
 }
 
 // Lane 1 runs on the batch's second stream, ordered after everything already
@@ -1138,6 +1147,8 @@ lbm_status ensure_lane_stream(lbm_batch* b) {
     HIPB(b, hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming));
     HIPB(b, hipEventCreateWithFlags(&b->ev_join, hipEventDisableTiming));
     HIPB(b, hipEventCreateWithFlags(&b->ev_sweep, hipEventDisableTiming));
+    HIPB(b, hipStreamCreateWithFlags(&b->stream3, hipStreamNonBlocking));
+    HIPB(b, hipEventCreateWithFlags(&b->ev_bnd, hipEventDisableTiming));
     return LBM_OK;
 }
 
@@ -1162,14 +1173,21 @@ lbm_status run_interleaved(lbm_batch* b, int n) {
             return e != hipSuccess ? e : launch_sweep(b->f64, b->tiling, sims, tiles, hdr, 0, half, -1, st1, 1);
         }, &Lt.graphA));
     }
-    if (!Lt.graphB)
+    if (!Lt.graphB) {
+        // lane 1's boundary rules run beside its correction when no band of
+        // its simulations comes near a non-periodic side
+        Lt.bnd_apart = true;
+        for (int r = Lt.sim0; r < Lt.sim0 + Lt.nsims; ++r)
+            Lt.bnd_apart = Lt.bnd_apart && !b->sims[b->order[r]]->band_near_edge;
+        const int k0 = Lt.bnd_apart ? 2 : 1, k1 = Lt.bnd_apart ? 5 : 6;
         HIPB(b, capture_fn(st1, [&]() {
-            for (int k = 1; k < 6; ++k) {
+            for (int k = k0; k < k1; ++k) {
                 hipError_t e = launch_kind(b, 1, k, st1);
                 if (e != hipSuccess) return e;
             }
             return hipSuccess;
         }, &Lt.graphB));
+    }
     HIPB(b, hipEventRecord(b->ev_fork, st0));
     HIPB(b, hipStreamWaitEvent(st1, b->ev_fork, 0));
     for (int t = 0; t < n; ++t) {
@@ -1177,7 +1195,16 @@ lbm_status run_interleaved(lbm_batch* b, int n) {
         HIPB(b, hipGraphLaunch(H.graph1, st0));
         HIPB(b, hipGraphLaunch(Lt.graphA, st1));
         HIPB(b, hipEventRecord(b->ev_sweep, st1));
+        if (Lt.bnd_apart) {
+            HIPB(b, hipStreamWaitEvent(b->stream3, b->ev_sweep, 0));
+            HIPB(b, launch_kind(b, 1, 1, b->stream3));
+            HIPB(b, hipEventRecord(b->ev_bnd, b->stream3));
+        }
         HIPB(b, hipGraphLaunch(Lt.graphB, st1));
+        if (Lt.bnd_apart) {
+            HIPB(b, hipStreamWaitEvent(st1, b->ev_bnd, 0));
+            HIPB(b, launch_kind(b, 1, 5, st1));
+        }
     }
     HIPB(b, hipEventRecord(b->ev_join, st1));
     HIPB(b, hipStreamWaitEvent(st0, b->ev_join, 0));

@@ -214,6 +214,31 @@ def test_two_lanes_give_the_same_bits():
     _same(res[2][0], _state(alone, 2))
 
 
+def test_two_lanes_with_boundary_beside_correction_give_the_same_bits():
+    """The light lane holds channel cylinders far from the sides and periodic
+    Couette cells only, so its boundary rules run on their own stream beside
+    its correction; every member's result is the same as with one lane."""
+    _say("lanes: boundary rules beside the correction, 17 steps")
+    cases = [wl.couette(176, precision=wl.F32),
+             wl.cylinder(nx=200, ny=100, D=12.0, centre=(50.0, 50.0), U=0.05, Re=40.0),
+             wl.cylinder(nx=160, ny=80, D=10.0, centre=(40.0, 40.0), U=0.04, Re=20.0),
+             wl.couette(64, precision=wl.F32), wl.couette(96, precision=wl.F32)]
+    res = {}
+    for lanes in (1, 2):
+        sims = [gpu_from_case(c, precision=lbmib.F32_SHIFTED) for c in cases]
+        b = lbmib.Batch(lbmib.F32_SHIFTED)
+        for s in sims:
+            assert b.admit(s)
+        b.set_lanes(lanes)
+        assert b.lanes == lanes
+        b.step(17)
+        b.sync()
+        res[lanes] = [_state(s, len(c["bodies"])) for s, c in zip(sims, cases)]
+        b.close()
+    for a, c in zip(res[1], res[2]):
+        _same(a, c)
+
+
 def test_automatic_lanes_keep_small_batches_in_one_lane():
     """By default a batch splits only when it is large enough for steps
     launched one by one; an explicit request splits whenever it can."""
