@@ -163,7 +163,8 @@ def mrt_leg(args, cases, lbmib, wl, torch, tiling, lanes):
     for s in sims:
         assert b.admit(s)
     b.set_tiling(tiling)
-    b.set_lanes(lanes)
+    if lanes:
+        b.set_lanes(lanes)
     b.step(10)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -199,7 +200,8 @@ def main():
                     help="keep the default sweep tiling instead of timing the candidates on the set")
     ap.add_argument("--tiling", type=int, default=-1)
     ap.add_argument("--lanes", type=int, default=0,
-                    help="1 or 2 to force the batch's lanes (default: the library's choice, kept by the autotuner)")
+                    help="1, 2 (free-running) or 3 (interleaved) to force the batch's lanes "
+                         "(default: the library's choice, kept by the autotuner)")
     ap.add_argument("--mrt-steps", type=int, default=100,
                     help="timed steps of the same set with the MRT collision (0: skip)")
     ap.add_argument("--serve-requests", type=int, default=24)
@@ -281,7 +283,7 @@ def main():
     # ---- the same set with the MRT collision
     mrt = None
     if args.mrt_steps > 0:
-        mrt = mrt_leg(args, cases, lbmib, wl, torch, in_use, lanes)
+        mrt = mrt_leg(args, cases, lbmib, wl, torch, in_use, args.lanes)
 
     # ---- FP64 plain path: members of the same set one at a time, direct launches
     f64_mlups = f32_sample_mlups = err = f32_plain_mlups = None

@@ -234,16 +234,17 @@ int32_t lbm_batch_get_tiling(const lbm_batch* b);
 /* The batch may split its simulations into two lanes replayed on two
  * streams: those whose largest body group has more than 400 markers, and the
  * rest, when both are non-empty and the first holds at most half of the nodes.
- * The lanes are interleaved step by step: the second lane's sweep runs as two
- * launches, the first lane's step waits for the second lane's previous sweep,
- * so each lane's sweep overlaps the other's boundary and correction kernels.
- * lanes = 0 (the default) splits when the batch also has at least 16 Mi nodes
- * (shorter steps are replayed as graphs of several steps in one lane);
- * lanes = 2 splits whenever the split exists; lanes = 1 keeps one lane.  The
- * second stream is ordered after the batch stream's earlier work and the batch
- * stream waits for it, so the batch behaves as one stream to the caller.
- * Results do not depend on the lanes.  lbm_batch_autotune may switch to one
- * lane when it is faster.  LBM_ERR_INVALID for other values. */
+ * lanes = 2 replays each lane's captured graphs of several steps on its own
+ * stream, independently; lanes = 3 interleaves the lanes step by step (the
+ * second lane's sweep runs as two launches and the first lane's step waits for
+ * the second lane's previous sweep, so each lane's sweep overlaps the other's
+ * boundary and correction kernels; steps are launched one by one from the
+ * host).  lanes = 0 (the default) takes 3 for batches of at least 16 Mi nodes
+ * and 2 below; lanes = 1 keeps one lane.  The second stream is ordered after
+ * the batch stream's earlier work and the batch stream waits for it, so the
+ * batch behaves as one stream to the caller.  Results do not depend on the
+ * lanes.  lbm_batch_autotune may switch to one lane when it is faster.
+ * LBM_ERR_INVALID for other values. */
 lbm_status lbm_batch_set_lanes(lbm_batch* b, int32_t lanes);
 /* Lanes in use now (1 or 2). */
 int32_t lbm_batch_get_lanes(const lbm_batch* b);

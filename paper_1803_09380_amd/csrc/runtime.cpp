@@ -131,9 +131,10 @@ struct Lane {
 // first lane when the batch uses two: their long correction kernels overlap
 // the other lane's sweeps.
 constexpr int kHeavyGroupMarkers = 400;
-// Two lanes are launched step by step from the host; below this many nodes a
-// step is too short for that, and one lane replays graphs of several steps.
-constexpr int64_t kTwoLaneMinCells = 16 << 20;
+// Two interleaved lanes are launched step by step from the host; below this
+// many nodes the automatic choice replays each lane's graphs of several steps
+// independently instead.
+constexpr int64_t kInterleaveMinCells = 16 << 20;
 
 struct lbm_batch {
     bool f64 = false;
@@ -151,7 +152,8 @@ struct lbm_batch {
     DevBuf d_sims;
     size_t cap_sims = 0;
     Lane lane[2];
-    int lanes_req = 0;              // 0 automatic, 1 one lane, 2 two whenever the split exists (upload_tables)
+    int lanes_req = 0;              // 0 automatic, 1 one lane, 2 two free-running, 3 two interleaved (upload_tables)
+    bool interleave = false;        // two lanes in use are interleaved step by step
     int nlanes = 1;                 // lanes in use
     int tiling = kTileDefault;
     int grid_bc = 0, grid_ib = 0;
@@ -985,11 +987,12 @@ lbm_status upload_tables(lbm_batch* b) {
             light.push_back(k);
         }
     }
-    const bool two = b->lanes_req != 1 && !heavy.empty() && !light.empty() && 2 * heavy_cells <= cells &&
-                     (b->lanes_req == 2 || cells >= kTwoLaneMinCells);
+    const bool two = b->lanes_req != 1 && !heavy.empty() && !light.empty() && 2 * heavy_cells <= cells;
     const int nl = two ? 2 : 1;
-    if (nl != b->nlanes) drop_graphs(b);
+    const bool il = two && (b->lanes_req == 3 || (b->lanes_req == 0 && cells >= kInterleaveMinCells));
+    if (nl != b->nlanes || il != b->interleave) drop_graphs(b);
     b->nlanes = nl;
+    b->interleave = il;
     b->order.clear();
     if (two) {
         b->order = heavy;
@@ -1211,20 +1214,30 @@ lbm_status run_interleaved(lbm_batch* b, int n) {
     return LBM_OK;
 }
 
-// n steps of every lane: one lane replays graphs of 8 and 1 steps; two lanes
-// are interleaved step by step (run_interleaved).
+// n steps of every lane: each lane replays its graphs of 8 and 1 steps on its
+// own stream, or two lanes are interleaved step by step (run_interleaved).
 lbm_status run_steps(lbm_batch* b, int n) {
+    hipStream_t st[2] = {b->stream, nullptr};
     if (b->nlanes == 2) {
         lbm_status rc = ensure_lane_stream(b);
         if (rc != LBM_OK) return rc;
-        return run_interleaved(b, n);
+        if (b->interleave) return run_interleaved(b, n);
+        st[1] = b->stream2;
+        HIPB(b, hipEventRecord(b->ev_fork, st[0]));
+        HIPB(b, hipStreamWaitEvent(st[1], b->ev_fork, 0));
     }
-    Lane& L = b->lane[0];
-    if (!L.graph1) HIPB(b, capture(b, 0, 1, b->stream, &L.graph1));
-    if (!L.graphK) HIPB(b, capture(b, 0, b->graphK_steps, b->stream, &L.graphK));
-    int left = n;
-    for (; left >= b->graphK_steps; left -= b->graphK_steps) HIPB(b, hipGraphLaunch(L.graphK, b->stream));
-    for (; left > 0; --left) HIPB(b, hipGraphLaunch(L.graph1, b->stream));
+    for (int l = 0; l < b->nlanes; ++l) {
+        Lane& L = b->lane[l];
+        if (!L.graph1) HIPB(b, capture(b, l, 1, st[l], &L.graph1));
+        if (!L.graphK) HIPB(b, capture(b, l, b->graphK_steps, st[l], &L.graphK));
+        int left = n;
+        for (; left >= b->graphK_steps; left -= b->graphK_steps) HIPB(b, hipGraphLaunch(L.graphK, st[l]));
+        for (; left > 0; --left) HIPB(b, hipGraphLaunch(L.graph1, st[l]));
+    }
+    if (b->nlanes == 2) {
+        HIPB(b, hipEventRecord(b->ev_join, st[1]));
+        HIPB(b, hipStreamWaitEvent(st[0], b->ev_join, 0));
+    }
     return LBM_OK;
 }
 
@@ -1443,7 +1456,7 @@ lbm_status lbm_batch_autotune(lbm_batch* b, int32_t trials, int32_t* chosen) {
 }
 
 lbm_status lbm_batch_set_lanes(lbm_batch* b, int32_t lanes) {
-    if (!b || lanes < 0 || lanes > 2) return LBM_ERR_INVALID;
+    if (!b || lanes < 0 || lanes > 3) return LBM_ERR_INVALID;
     lbm_status rc = sync_back(b);
     if (rc != LBM_OK) return rc;
     b->lanes_req = lanes;

@@ -354,8 +354,9 @@ class Batch:
         return load().lbm_batch_get_tiling(self._h)
 
     def set_lanes(self, n):
-        """0: automatic (two lanes on large batches with a heavy/light split),
-        1: one lane, 2: two lanes whenever the split exists."""
+        """0: automatic, 1: one lane, 2: two lanes replayed independently,
+        3: two lanes interleaved step by step (two lanes need a heavy/light
+        split of the members)."""
         rc = load().lbm_batch_set_lanes(self._h, n)
         if rc != OK:
             raise LbmError(rc, "lbm_batch_set_lanes")

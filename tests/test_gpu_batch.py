@@ -193,25 +193,26 @@ def test_two_lanes_give_the_same_bits():
     """The member with a large body group goes to its own lane on a second
     stream; every member's result is the same with one lane, with two lanes,
     and alone."""
-    _say("lanes: one vs two vs alone, 17 steps")
+    _say("lanes: one vs two (free-running, interleaved) vs alone, 17 steps")
     cases = _lane_cases()
     res = {}
-    for lanes in (1, 2):
+    for lanes in (1, 2, 3):
         sims = [gpu_from_case(c, precision=lbmib.F32_SHIFTED) for c in cases]
         b = lbmib.Batch(lbmib.F32_SHIFTED)
         for s in sims:
             assert b.admit(s)
         b.set_lanes(lanes)
-        assert b.lanes == lanes
+        assert b.lanes == min(lanes, 2)
         b.step(17)
         b.sync()
         res[lanes] = [_state(s, len(c["bodies"])) for s, c in zip(sims, cases)]
         b.close()
     alone = gpu_from_case(cases[0], precision=lbmib.F32_SHIFTED)
     alone.step(17)
-    for x, y in zip(res[1], res[2]):
-        _same(x, y)
-    _same(res[2][0], _state(alone, 2))
+    for lanes in (2, 3):
+        for x, y in zip(res[1], res[lanes]):
+            _same(x, y)
+        _same(res[lanes][0], _state(alone, 2))
 
 
 def test_two_lanes_with_boundary_beside_correction_give_the_same_bits():
@@ -224,46 +225,54 @@ def test_two_lanes_with_boundary_beside_correction_give_the_same_bits():
              wl.cylinder(nx=160, ny=80, D=10.0, centre=(40.0, 40.0), U=0.04, Re=20.0),
              wl.couette(64, precision=wl.F32), wl.couette(96, precision=wl.F32)]
     res = {}
-    for lanes in (1, 2):
+    for lanes in (1, 3):
         sims = [gpu_from_case(c, precision=lbmib.F32_SHIFTED) for c in cases]
         b = lbmib.Batch(lbmib.F32_SHIFTED)
         for s in sims:
             assert b.admit(s)
         b.set_lanes(lanes)
-        assert b.lanes == lanes
+        assert b.lanes == min(lanes, 2)
         b.step(17)
         b.sync()
         res[lanes] = [_state(s, len(c["bodies"])) for s, c in zip(sims, cases)]
         b.close()
-    for a, c in zip(res[1], res[2]):
+    for a, c in zip(res[1], res[3]):
         _same(a, c)
 
 
-def test_automatic_lanes_keep_small_batches_in_one_lane():
-    """By default a batch splits only when it is large enough for steps
-    launched one by one; an explicit request splits whenever it can."""
-    _say("automatic lanes on a small batch")
+def test_lane_requests():
+    """The default splits a batch with a heavy/light split; one lane on
+    request; a batch without large body groups keeps one lane."""
+    _say("lane requests")
     sims = [gpu_from_case(c, precision=lbmib.F32_SHIFTED) for c in _lane_cases()]
     b = lbmib.Batch(lbmib.F32_SHIFTED)
     for s in sims:
         assert b.admit(s)
-    assert b.lanes == 1
-    b.set_lanes(2)
     assert b.lanes == 2
-    b.set_lanes(0)
+    b.set_lanes(1)
     assert b.lanes == 1
+    b.set_lanes(3)
+    assert b.lanes == 2
     with pytest.raises(lbmib.LbmError):
-        b.set_lanes(3)
+        b.set_lanes(4)
+    b.close()
+    small = [gpu_from_case(c, precision=lbmib.F32_SHIFTED) for c in _cases()]
+    b = lbmib.Batch(lbmib.F32_SHIFTED)
+    for s in small:
+        assert b.admit(s)
+    b.set_lanes(3)
+    assert b.lanes == 1
     b.close()
 
 
-def test_lanes_survive_admission_and_retirement():
-    _say("lanes with admission and retirement")
+@pytest.mark.parametrize("lanes", [2, 3])
+def test_lanes_survive_admission_and_retirement(lanes):
+    _say("lanes %d with admission and retirement" % lanes)
     lc = _lane_cases()
     big = gpu_from_case(lc[0], precision=lbmib.F32_SHIFTED)
     small = [gpu_from_case(c, precision=lbmib.F32_SHIFTED) for c in lc[1:]]
     b = lbmib.Batch(lbmib.F32_SHIFTED)
-    b.set_lanes(2)
+    b.set_lanes(lanes)
     for s in small:
         assert b.admit(s)
     b.step(5)
