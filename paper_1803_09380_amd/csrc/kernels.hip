@@ -431,20 +431,31 @@ __device__ __forceinline__ bool stencil_cell(const SimDev& S, double X, double Y
 }
 
 // Block-wide exclusive scan of one int per thread (NT threads); returns the
-// prefix and the total in *total.
+// prefix and the total in *total.  A shuffle scan inside each wave, then the
+// wave totals in order; tmp holds NT / 64 + 1 ints.
 template <int NT>
 __device__ __forceinline__ int block_scan(int v, int* tmp, int* total) {
-    const int tid = threadIdx.x;
-    tmp[tid] = v;
-    __syncthreads();
-    for (int off = 1; off < NT; off <<= 1) {
-        int add = tid >= off ? tmp[tid - off] : 0;
-        __syncthreads();
-        tmp[tid] += add;
-        __syncthreads();
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    int x = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int y = __shfl_up(x, off, 64);
+        if (lane >= off) x += y;
     }
-    const int incl = tmp[tid];
-    *total = tmp[NT - 1];
+    if (lane == 63) tmp[w] = x;
+    __syncthreads();
+    if (tid == 0) {
+        int run = 0;
+        for (int k = 0; k < NT / 64; ++k) {
+            const int t = tmp[k];
+            tmp[k] = run;
+            run += t;
+        }
+        tmp[NT / 64] = run;
+    }
+    __syncthreads();
+    const int incl = x + tmp[w];
+    *total = tmp[NT / 64];
     __syncthreads();
     return incl - v;
 }
@@ -526,15 +537,20 @@ __device__ void build_plan(const SimDev& S, const GroupDev& G, unsigned long lon
 // case for moving particles): count stencil entries per box cell in LDS, scan
 // the counts into band-node indices and entry offsets, drop each entry into
 // its cell's run, and order every run by marker (insertion sort of a handful of
-// entries) so the plan is the same whatever order the atomics came in.
-// Returns false, without touching the plan, when the box is too large.
+// entries) so the plan is the same whatever order the atomics came in.  The
+// markers' stencil corners, the counts and the entries stay in LDS; the plan is
+// written to device memory once.  Returns false, without touching the plan,
+// when the box or its LDS arrays are too large.
 constexpr int kBinCells = 16384;
+// LDS arena of the correction kernel (plan build, then the band's working arrays)
+constexpr int kIbArenaBytes = 148 * 1024;
 
 template <int NT>
 __device__ bool build_plan_binned(const SimDev& S, const GroupDev& G, int* lds, int* scan_tmp, int* bbox,
                                   int& nband_out, int& nent_out) {
     const int tid = threadIdx.x;
     const int M = G.M, NE = 16 * M;
+    if (M == 0 || 2L * M * (int)sizeof(int) > kIbArenaBytes) return false;
     if (tid == 0) {
         bbox[0] = 0x7fffffff;
         bbox[1] = 0x7fffffff;
@@ -542,11 +558,16 @@ __device__ bool build_plan_binned(const SimDev& S, const GroupDev& G, int* lds, 
         bbox[3] = -0x7fffffff;
     }
     __syncthreads();
+    // lower-left stencil corner of every marker, kept for the passes below
+    int* mfx = lds;
+    int* mfy = lds + M;
     int lx = 0x7fffffff, ly = 0x7fffffff, hx = -0x7fffffff, hy = -0x7fffffff;
     for (int g = tid; g < M; g += NT) {
         int body;
         const int mi = marker_index(S, G, g, body);
         const int fx = (int)floor(S.mX[mi]) - 1, fy = (int)floor(S.mY[mi]) - 1;
+        mfx[g] = fx;
+        mfy[g] = fy;
         lx = min(lx, fx);
         ly = min(ly, fy);
         hx = max(hx, fx + 3);
@@ -561,18 +582,19 @@ __device__ bool build_plan_binned(const SimDev& S, const GroupDev& G, int* lds, 
     __syncthreads();
     const int x0 = bbox[0], y0 = bbox[1];
     const long W = (long)bbox[2] - x0 + 1, H = (long)bbox[3] - y0 + 1;
-    if (M == 0 || W * H > kBinCells || (S.px && W >= S.nx) || (S.py && H >= S.ny)) return false;
+    const long words = 2L * M + 2 * W * H + NE;
+    if (W * H > kBinCells || words * (long)sizeof(int) > kIbArenaBytes || (S.px && W >= S.nx) || (S.py && H >= S.ny))
+        return false;
     const int ncell = (int)(W * H);
-    int* count = lds;              // per box cell: entries, then band-node index
-    int* start = lds + kBinCells;  // per box cell: first entry, then fill position
+    int* count = lds + 2 * M;  // per box cell: entries, then band-node index
+    int* start = count + ncell;  // per box cell: first entry, then fill position
+    int* ents = start + ncell;   // entries by run
     for (int c = tid; c < ncell; c += NT) count[c] = 0;
     for (int e = tid; e < NE; e += NT) G.mnode[e] = -1;
     __syncthreads();
     for (int e = tid; e < NE; e += NT) {
         const int g = e >> 4, sl = e & 15;
-        int body;
-        const int mi = marker_index(S, G, g, body);
-        const int ux = (int)floor(S.mX[mi]) - 1 + (sl & 3), uy = (int)floor(S.mY[mi]) - 1 + (sl >> 2);
+        const int ux = mfx[g] + (sl & 3), uy = mfy[g] + (sl >> 2);
         const int x = wrap(ux, S.nx, S.px), y = wrap(uy, S.ny, S.py);
         if (x < 0 || x >= S.nx || y < 0 || y >= S.ny) continue;
         atomicAdd(&count[(uy - y0) * (int)W + (ux - x0)], 1);
@@ -606,27 +628,33 @@ __device__ bool build_plan_binned(const SimDev& S, const GroupDev& G, int* lds, 
     __syncthreads();
     for (int e = tid; e < NE; e += NT) {
         const int g = e >> 4, sl = e & 15;
-        int body;
-        const int mi = marker_index(S, G, g, body);
-        const int ux = (int)floor(S.mX[mi]) - 1 + (sl & 3), uy = (int)floor(S.mY[mi]) - 1 + (sl >> 2);
+        const int ux = mfx[g] + (sl & 3), uy = mfy[g] + (sl >> 2);
         const int x = wrap(ux, S.nx, S.px), y = wrap(uy, S.ny, S.py);
         if (x < 0 || x >= S.nx || y < 0 || y >= S.ny) continue;
         const int slot = atomicAdd(&start[(uy - y0) * (int)W + (ux - x0)], 1);
-        G.ent[slot] = e;  // e = 16 * marker + (ky << 2 | kx)
+        ents[slot] = e;  // e = 16 * marker + (ky << 2 | kx)
     }
     __syncthreads();
-    for (int k = tid; k < ntotal; k += NT) {
-        const int e0 = G.node_run[k], e1 = G.node_run[k + 1];
+    // each non-empty cell's run ends at its fill position and holds count
+    // entries no more; order it by marker and write the plan
+    for (int c = tid; c < ncell; c += NT) {
+        const int e1 = start[c];
+        const int e0 = c == 0 ? 0 : start[c - 1];
+        if (e1 == e0) continue;
+        const int k = count[c];
         for (int a = e0 + 1; a < e1; ++a) {
-            const int v = G.ent[a];
+            const int v = ents[a];
             int b = a - 1;
-            while (b >= e0 && G.ent[b] > v) {
-                G.ent[b + 1] = G.ent[b];
+            while (b >= e0 && ents[b] > v) {
+                ents[b + 1] = ents[b];
                 --b;
             }
-            G.ent[b + 1] = v;
+            ents[b + 1] = v;
         }
-        for (int e = e0; e < e1; ++e) G.mnode[G.ent[e]] = k;
+        for (int e = e0; e < e1; ++e) {
+            G.ent[e] = ents[e];
+            G.mnode[ents[e]] = k;
+        }
     }
     nband_out = ntotal;
     nent_out = etotal;
@@ -689,8 +717,7 @@ __device__ void collision_force(double xi0, double xi1, double xj0, double xj1, 
 // indices (16-bit), the per-marker phi values and the stencil entries are
 // placed here while they fit; the rest stay in the group's global scratch
 // (generic pointers serve both).  A plan rebuilt on the device first uses the
-// arena for its sort keys.
-constexpr int kIbArenaBytes = 148 * 1024;
+// arena (kIbArenaBytes) for its sort keys or bins.
 
 struct Bump {
     char* base;
