@@ -149,6 +149,30 @@ def test_free_particles_f64():
     _compare_case(case, 200, check_state=True)
 
 
+def _far_apart_particles(precision):
+    """Two free particles 1200 spacings apart: the group's bounding box (about
+    15 x 1215 cells) exceeds the bins of the binned rebuild, so the plan is
+    rebuilt by the sort-based path every step."""
+    case = wl.settling(nx=40, ny=1400, D=10.0, density_ratio=1.3, two=True, precision=precision,
+                       lower=(20.0, 100.0), u_ref=0.05)
+    case["bodies"][1] = dict(case["bodies"][1], xc=(20.1, 1300.0))
+    return case
+
+
+def test_far_apart_particles_sort_based_plan_f64():
+    _say("two far-apart particles 40x1400 f64, 30 steps")
+    _compare_case(_far_apart_particles(wl.F64), 30, check_state=True)
+
+
+def test_far_apart_particles_sort_based_plan_fp32():
+    _say("two far-apart particles 40x1400 f32, 30 steps")
+    case = _far_apart_particles(wl.F32)
+    o, g = oracle_from_case(case), gpu_from_case(case, precision=lbmib.F32_SHIFTED)
+    o.step(30)
+    g.step(30)
+    assert velocity_rel(g.fields(), o.fields()) < 1e-5
+
+
 def test_particle_near_wall_collision_f64():
     """A particle close to a wall: stencils cut by the wall and the mirror
     collision force of Eq. 39 act."""
