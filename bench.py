@@ -206,6 +206,8 @@ def main():
                     help="timed steps of the same set with the MRT collision (0: skip)")
     ap.add_argument("--serve-requests", type=int, default=24)
     ap.add_argument("--serve-steps", type=int, default=2000)
+    ap.add_argument("--serve-overload", type=int, default=16,
+                    help="requests of the overload leg (10x the steps, HBM budget of 8 requests; 0 skips it)")
     ap.add_argument("--only-batch", action="store_true",
                     help="time the batched set only (for profiler runs): no CPU baseline, FP64 sample, "
                          "accuracy or serving legs")
@@ -223,6 +225,7 @@ def main():
         args.no_cpu = True
         args.fp64_sample = 0
         args.serve_requests = 0
+        args.serve_overload = 0
         args.mrt_steps = 0
     cpu = None
     if not args.no_cpu:
@@ -307,6 +310,25 @@ def main():
                         "steps_per_request": args.serve_steps, "hbm_budget_bytes": budget,
                         "particles": "1 or 2 free circles, D 16..40, density ratio 1.01..1.5"})
 
+    # ---- overload: ten times the steps per request and an HBM budget of eight
+    # requests, so that arrivals queue for admission
+    overload = None
+    if args.serve_overload > 0:
+        from paper_1803_09380_amd.serve import GpuExecutor, Request, Server
+        arr = wl.arrivals(seed=args.seed + 1, rate=20.0, count=args.serve_overload, steps=10 * args.serve_steps)
+        reqs = [Request(rid=r["id"], t_arrive=r["t_arrive"], case=r["case"], steps=r["steps"]) for r in arr]
+        probe = lbmib.Sim.from_case(arr[0]["case"], precision=lbmib.F32_SHIFTED)
+        budget = 8 * probe.device_bytes + probe.device_bytes // 2
+        probe.close()
+        ex = GpuExecutor(lbmib.F32_SHIFTED, hbm_budget=budget)
+        srv = Server(ex, hbm_budget=budget, chunk=100)
+        srv.run(reqs)
+        ex.close()
+        overload = srv.stats.summary()
+        overload.update({"arrivals": "Poisson, mean 20/s, seed %d" % (args.seed + 1),
+                         "lattice": "400x4000 closed box", "steps_per_request": 10 * args.serve_steps,
+                         "hbm_budget_bytes": budget, "budget_requests": 8})
+
     out = {
         "metric": METRIC,
         "value": round(mlups, 1),
@@ -350,6 +372,7 @@ def main():
         "mrt": mrt,
         "unstable_members": unstable,
         "serving": serving,
+        "serving_overload": overload,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
