@@ -81,13 +81,18 @@ class Stats:
     wall: float = 0.0
     max_live: int = 0
     queue_peak: int = 0
+    timeline: list = field(default_factory=list)  # (time, requests on the device, requests queued) per chunk
 
-    def summary(self):
+    def summary(self, points=32):
         lat = np.array(self.latencies) if self.latencies else np.zeros(1)
+        tl = self.timeline
+        if len(tl) > points:
+            tl = [tl[int(round(k * (len(tl) - 1) / (points - 1)))] for k in range(points)]
         return {"requests": len(self.latencies), "p50_s": float(np.percentile(lat, 50)),
                 "p99_s": float(np.percentile(lat, 99)), "mean_s": float(lat.mean()),
                 "aggregate_mlups": self.updates / self.wall / 1e6 if self.wall > 0 else 0.0,
-                "max_concurrent": self.max_live, "queue_peak": self.queue_peak, "wall_s": self.wall}
+                "max_concurrent": self.max_live, "queue_peak": self.queue_peak, "wall_s": self.wall,
+                "timeline_s_live_queued": [[round(t, 3), a, q] for t, a, q in tl]}
 
 
 class Server:
@@ -142,6 +147,7 @@ class Server:
                     self.sleep(max(0.0, pending[0].t_arrive - self.clock()))
                 continue
             # advance the batch by one chunk (members stop on their own budgets)
+            self.stats.timeline.append((now - start, len(self.live), len(waiting)))
             n = min(self.chunk, max(r[0].steps - r[3] for r in self.live))
             self.ex.step(n)
             self.ex.sync()

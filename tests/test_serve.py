@@ -93,6 +93,12 @@ def test_budget_limits_concurrency_and_keeps_arrival_order():
     admits = [rid for kind, rid, _ in ex.trace if kind == "admit"]
     assert admits == sorted(admits)
     assert srv.stats.queue_peak >= 5
+    # the timeline of requests on the device and queued: never more than the
+    # budget allows, queued requests drain, times increase
+    tl = srv.stats.summary(points=8)["timeline_s_live_queued"]
+    assert 2 <= len(tl) <= 8
+    assert all(0 < a <= 3 for _, a, _ in tl) and max(q for _, _, q in tl) >= 5 and tl[-1][2] == 0
+    assert all(t1 >= t0 for (t0, _, _), (t1, _, _) in zip(tl, tl[1:]))
 
 
 def test_requests_arriving_while_others_run_are_admitted_between_chunks():
