@@ -240,6 +240,30 @@ def test_two_lanes_with_boundary_beside_correction_give_the_same_bits():
         _same(a, c)
 
 
+def test_fp64_lanes_give_the_same_bits():
+    """FP64 batches split and interleave their lanes like FP32 ones: both
+    schedules give the same bits as one lane."""
+    _say("fp64 lanes: one vs free-running vs interleaved, 11 steps")
+    cases = [wl.couette(176), wl.couette(64),
+             wl.cylinder(nx=200, ny=100, D=12.0, centre=(50.0, 50.0), U=0.05, Re=40.0, precision=wl.F64),
+             wl.cylinder(nx=160, ny=80, D=10.0, centre=(40.0, 40.0), U=0.04, Re=20.0, precision=wl.F64)]
+    res = {}
+    for lanes in (1, 2, 3):
+        sims = [gpu_from_case(c, precision=lbmib.F64) for c in cases]
+        b = lbmib.Batch(lbmib.F64)
+        for s in sims:
+            assert b.admit(s)
+        b.set_lanes(lanes)
+        assert b.lanes == min(lanes, 2)
+        b.step(11)
+        b.sync()
+        res[lanes] = [_state(s, len(c["bodies"])) for s, c in zip(sims, cases)]
+        b.close()
+    for lanes in (2, 3):
+        for x, y in zip(res[1], res[lanes]):
+            _same(x, y)
+
+
 def test_lane_requests():
     """The default splits a batch with a heavy/light split; one lane on
     request; a batch without large body groups keeps one lane."""
