@@ -160,8 +160,10 @@ __device__ __forceinline__ void mrt(T h[9], T rho_base, const T rate[9], uint32_
 // wait on memory, and the latency-bound kernels would otherwise queue behind them.
 __device__ __forceinline__ void raise_wave_priority() { __builtin_amdgcn_s_setprio(2); }
 
+// At most seven waves per SIMD: the sweep streams at a higher rate than with
+// eight (measured), and each SIMD keeps a wave slot for the other kernels.
 template <typename T, int TX, int TY, int RPT, bool NTMP>
-__global__ void __launch_bounds__(TX* TY)
+__global__ void __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(1, 7)))
     k_sweep(const SimDev* __restrict__ sims, const int4* __restrict__ tiles,
             const BatchHeader* __restrict__ hdr, int ntiles_arg, int parity, int part) {
     int t0 = blockIdx.x, t1 = hdr ? hdr->ntiles : ntiles_arg, dt = gridDim.x;
