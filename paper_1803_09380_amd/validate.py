@@ -89,6 +89,8 @@ def table1(lbmib, res, f64=False, D=40.0, steady_steps=None, unsteady_steps=None
         F = s.forces(0)[0]
         cd, cl = dg.force_coefficients(F, U0, D)
         hist[k].append((step, cd, cl))
+        if k == 0 and step % 20000 == 0:
+            print("table1: %d steps" % step, file=sys.stderr, flush=True)
         if res[k] < 49 and step > budgets[k] - window and step % field_every == 0:
             _, ux, uy = s.fields()
             acc[k][0] += 1
