@@ -128,8 +128,9 @@ struct Lane {
 };
 
 // Simulations whose largest body group has more markers than this run in the
-// first lane when the batch uses two: their long correction kernels overlap
-// the other lane's sweeps.
+// first lane when the batch uses two: their long correction kernels run while
+// the other lane's lighter work does (between its two sweep launches when the
+// lanes are interleaved).
 constexpr int kHeavyGroupMarkers = 400;
 // Two interleaved lanes are launched step by step from the host; below this
 // many nodes the automatic choice replays each lane's graphs of several steps
@@ -968,10 +969,10 @@ hipError_t ensure_cap(DevBuf& buf, size_t& cap, size_t need, bool& grew) {
 
 // Rebuild and upload the batch's work tables from the admitted simulations'
 // host descriptors (call sync_back first when simulations are in flight).
-// With two lanes requested, the simulations whose largest body group exceeds
-// kHeavyGroupMarkers form lane 0 (their long correction kernels then overlap
-// the sweeps of lane 1) when that leaves both lanes non-empty and lane 0 with
-// at most half of the nodes; otherwise one lane holds everything.
+// Unless one lane is requested, the simulations whose largest body group
+// exceeds kHeavyGroupMarkers form lane 0 when that leaves both lanes non-empty
+// and lane 0 with at most half of the nodes; otherwise one lane holds
+// everything.
 lbm_status upload_tables(lbm_batch* b) {
     const int n = (int)b->sims.size();
     std::vector<int> heavy, light;
