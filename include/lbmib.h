@@ -236,10 +236,11 @@ int32_t lbm_batch_get_tiling(const lbm_batch* b);
  * rest, when both are non-empty and the first holds at most half of the nodes.
  * lanes = 2 replays each lane's captured graphs of several steps on its own
  * stream, independently; lanes = 3 interleaves the lanes step by step (the
- * second lane's sweep runs as two launches and the first lane's step waits for
- * the second lane's previous sweep, so each lane's sweep overlaps the other's
- * boundary and correction kernels; steps are launched one by one from the
- * host).  lanes = 0 (the default) takes 3 for batches of at least 16 Mi nodes
+ * second lane's sweep runs as two launches, the first lane's step waits for
+ * the second lane's previous sweep, and when no band of the second lane comes
+ * within three nodes of a non-periodic side its boundary rules run on a third
+ * stream beside its correction; steps are launched one by one from the host).
+ * lanes = 0 (the default) takes 3 for batches of at least 16 Mi nodes
  * and 2 below; lanes = 1 keeps one lane.  The second stream is ordered after
  * the batch stream's earlier work and the batch stream waits for it, so the
  * batch behaves as one stream to the caller.  Results do not depend on the
