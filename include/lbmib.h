@@ -124,12 +124,16 @@ typedef struct lbm_batch lbm_batch;
 #define LBM_MAX_GROUP_MARKERS 4096 /* markers in one group of interacting bodies     */
 #define LBM_MAX_FREE_MARKERS 512   /* markers in a simulation that has free bodies  */
 
-/* Create a simulation on the current HIP device with all populations at
- * f^eq(rho0, u_init).  hip_stream is a hipStream_t (NULL: a stream the handle
- * creates and owns).  Errors: LBM_ERR_INVALID (sizes, tau, boundary pairing:
- * periodic sides come in pairs, FREESLIP only south/north, VELOCITY only west,
- * OUTFLOW/PRESSURE only east, PRESSURE with nx < 5, DIRICHLET not on all four
- * sides), LBM_ERR_NOMEM. */
+/* Create a simulation on the current HIP device: the lattice of Sec. 2.1
+ * (D2Q9, Eq. 4), the relaxation of Eq. 2 (BGK with S = I/tau, or the MRT
+ * rates of Eq. 6; viscosity from tau by Eq. 8), the boundary rules named
+ * above (Fig. 2, Secs. 3.1.1 and 3.2), and every population at the
+ * equilibrium of Eq. 3 for (rho0, u_init).  *p is copied; the handle owns its
+ * device memory until lbm_destroy.  hip_stream is a hipStream_t (NULL: a
+ * stream the handle creates and owns).  Errors: LBM_ERR_INVALID (sizes,
+ * tau <= 1/2, boundary pairing: periodic sides come in pairs, FREESLIP only
+ * south/north, VELOCITY only west, OUTFLOW/PRESSURE only east, PRESSURE with
+ * nx < 5, DIRICHLET not on all four sides), LBM_ERR_NOMEM, LBM_ERR_DEVICE. */
 lbm_status lbm_create(const lbm_params* p, void* hip_stream, lbm_sim** out);
 void lbm_destroy(lbm_sim* s);
 const char* lbm_last_error(const lbm_sim* s);
@@ -145,9 +149,14 @@ const char* lbm_last_error(const lbm_sim* s);
  *     with ds = 2 pi R / n.
  * Bodies whose delta stencils (4 x 4 nodes each) share a node are corrected
  * together; a simulation with a free body corrects all its bodies together.
- * Errors: LBM_ERR_INVALID (marker counts above LBM_MAX_GROUP_MARKERS or
- * LBM_MAX_FREE_MARKERS, a body wider than a periodic period, bad radius or
- * density), LBM_ERR_NOMEM. */
+ * Markers must lie in the lattice: on a non-periodic axis within half a
+ * spacing of the first and last nodes (-1/2 <= X <= n - 1/2, where half-way
+ * bounce-back puts the wall), for a free circle the whole circle; on a
+ * periodic axis within one period (0 <= X < n).
+ * Errors: LBM_ERR_INVALID (a marker outside the lattice, marker counts above
+ * LBM_MAX_GROUP_MARKERS or LBM_MAX_FREE_MARKERS, a body wider than a periodic
+ * period, bad radius or density; the previous bodies stay), LBM_ERR_NOMEM,
+ * LBM_ERR_STATE (the simulation is in a batch). */
 lbm_status ib_set_markers(lbm_sim* s, int32_t body_id, int32_t n, const double* xy,
                           const double* uv, const double* ds, const ib_body* body);
 
@@ -167,7 +176,13 @@ lbm_status lbm_set_boundary_velocity(lbm_sim* s, const double* ub);
  * batch), LBM_ERR_DEVICE. */
 lbm_status ib_set_marker_velocities(lbm_sim* s, int32_t id, const double* uv);
 
-/* Enqueue nsteps time steps on the handle's stream (no host synchronisation). */
+/* Enqueue nsteps time steps on the handle's stream (no host synchronisation).
+ * One step: collision and streaming (Eqs. 1-3, 7), the boundary rules, N
+ * correction sweeps of Sec. 2.3 (interpolation Eq. 22, deviation Eqs. 23-25
+ * in the form of Eq. 28, spreading and correction Eqs. 26-27), force and
+ * torque (Eqs. 29, 38) and the rigid-body update of free circles (Eqs. 37,
+ * 39-42).  Errors: LBM_ERR_INVALID (nsteps < 0), LBM_ERR_STATE (in a batch),
+ * LBM_ERR_DEVICE (a launch failed). */
 lbm_status lbm_step(lbm_sim* s, int32_t nsteps);
 /* Wait for the handle's stream; reports LBM_ERR_UNSTABLE once a density went bad. */
 lbm_status lbm_sync(lbm_sim* s);
@@ -182,8 +197,11 @@ int64_t lbm_step_count(lbm_sim* s);
 lbm_status ib_forces(lbm_sim* s, int32_t body_id, double F[2], double* T, double diag[2],
                      ib_body* state_out);
 
-/* Density and velocity of the (corrected) populations after the last step,
- * host arrays [ny][nx]; NULL skips an output.  Synchronises. */
+/* Density and velocity (Eq. 7: rho = sum_i f_i, rho u = sum_i e_i f_i) of
+ * the corrected populations after the last step, written to caller-owned host
+ * arrays of nx * ny doubles, [ny][nx] with x fastest; NULL skips an output.
+ * Synchronises.  Errors: LBM_ERR_NOMEM, LBM_ERR_DEVICE, LBM_ERR_UNSTABLE
+ * (the fields are still written). */
 lbm_status lbm_fields(lbm_sim* s, double* rho, double* ux, double* uy);
 /* Same into FP64 device arrays [ny][nx]; enqueued on the handle's stream. */
 lbm_status lbm_fields_device(lbm_sim* s, void* rho, void* ux, void* uy);

@@ -254,6 +254,25 @@ bool stencil_cell_host(const SimDev& S, double X, double Y, int kx, int ky, int&
     return true;
 }
 
+// The domain a marker may occupy: on a non-periodic axis the lattice is
+// closed half a spacing outside its first and last nodes (where half-way
+// bounce-back places the wall, Fig. 2), so -1/2 <= X <= n - 1/2; on a
+// periodic axis, one period, 0 <= X < n.  A free circle must fit whole
+// (centre +- radius) on non-periodic axes, since its markers move on it.
+bool markers_inside(const SimDev& h, const HostBody& B) {
+    auto axis_ok = [](double v, double lo_pad, int n, bool periodic) {
+        if (periodic) return v >= 0.0 && v < (double)n;
+        return v - lo_pad >= -0.5 && v + lo_pad <= (double)n - 0.5;
+    };
+    if (B.kind == IB_FREE) {
+        const double R = B.b.radius;
+        return axis_ok(B.b.xc[0], h.px ? 0.0 : R, h.nx, h.px) && axis_ok(B.b.xc[1], h.py ? 0.0 : R, h.ny, h.py);
+    }
+    for (int l = 0; l < B.n; ++l)
+        if (!axis_ok(B.X[l], 0.0, h.nx, h.px) || !axis_ok(B.Y[l], 0.0, h.ny, h.py)) return false;
+    return true;
+}
+
 std::vector<int> body_cells(const lbm_sim* s, int b) {
     std::vector<int> c;
     const HostBody& B = s->body[b];
@@ -714,6 +733,9 @@ lbm_status ib_set_markers(lbm_sim* s, int32_t id, int32_t n, const double* xy, c
         } else {
             return fail(s, LBM_ERR_INVALID, "unknown body kind");
         }
+        if (!markers_inside(s->h, nb))
+            return fail(s, LBM_ERR_INVALID, "a marker lies outside the lattice (beyond a non-periodic side, "
+                                            "or outside one period of a periodic axis)");
         B = nb;
     }
     lbm_status rc = rebuild_ib(s);

@@ -62,6 +62,41 @@ def couette(side=64, tau=0.8, u_inner=None, precision=F64, ib_iters=10):
                 meta=dict(R1=R1, R2=R2, omega1=U1 / R1, centre=(c, c), nu=(tau - 0.5) / 3.0))
 
 
+def couette_paper(N, radius_ratio, tau, Re=10.0, margin=4, precision=F64, ib_iters=10):
+    """Cylindrical Couette flow as set up in Sec. 3.1.2: outer radius R2 = 1
+    resolved by N lattice spacings (dx = 1/N), inner radius R1 = R R2 with the
+    radius ratio R = 0.5 or 0.8, Re = U1 (R2 - R1) / nu = 10 with U1 = omega1 R1,
+    tau_s = 0.65 or 0.85 and the MRT rates of Sec. 4.1.  Refinement keeps tau_s
+    and Re, so the lattice wall speed U1 = Re nu / (R2 - R1) falls as 1/N.
+
+    The box is periodic with `margin` nodes between the outer circle and its
+    periodic image's stencil.  meta["steps"] is the run length: 1.5 diffusion
+    times of the gap and one of the inner disc (R1^2 / nu), after which the
+    slowest transients (decay rates about pi^2 nu / (R2 - R1)^2 and
+    14.7 nu / R1^2) are below 1e-6 of their start."""
+    R2 = float(N)
+    R1 = radius_ratio * R2
+    side = int(2 * (N + margin))
+    c = side / 2.0
+    nu = (tau - 0.5) / 3.0
+    U1 = Re * nu / (R2 - R1)
+    n1, n2 = int(round(2 * math.pi * R1)), int(round(2 * math.pi * R2))
+    bodies = [
+        dict(kind=FIXED, n=n2, xy=circle_markers(c, c, R2, n2), uv=None,
+             ds=np.full(n2, 2 * math.pi * R2 / n2), xc=(c, c), U=(0.0, 0.0), omega=0.0,
+             theta=0.0, radius=R2, rho_s=0.0),
+        dict(kind=FIXED, n=n1, xy=circle_markers(c, c, R1, n1), uv=None,
+             ds=np.full(n1, 2 * math.pi * R1 / n1), xc=(c, c), U=(0.0, 0.0), omega=U1 / R1,
+             theta=0.0, radius=R1, rho_s=0.0),
+    ]
+    steps = int(math.ceil(max(1.5 * (R2 - R1) ** 2, R1 * R1) / nu))
+    return dict(name="couette_paper_N%d_R%g_tau%g" % (N, radius_ratio, tau), nx=side, ny=side, tau=tau,
+                rho0=1.0, bc=(PERIODIC,) * 4, u_in=(0.0, 0.0), u_init=(0.0, 0.0), ib_iters=ib_iters,
+                precision=precision, gravity=(0.0, 0.0), bodies=bodies, mrt_s=mrt_rates(tau),
+                meta=dict(R1=R1, R2=R2, omega1=U1 / R1, U1=U1, centre=(c, c), nu=nu, N=N,
+                          radius_ratio=radius_ratio, steps=steps))
+
+
 def cylinder(nx=1600, ny=800, D=40.0, centre=None, U=0.05, Re=20.0, precision=F32, ib_iters=10,
              n_markers=None):
     """Flow past a fixed circular cylinder in a channel."""

@@ -479,3 +479,28 @@ def test_densely_marked_cylinder(precision):
         o.step(40)
         g.step(40)
         assert velocity_rel(g.fields(), o.fields()) < 1e-5
+
+
+# ---------------------------------------------------------------- boundary validation
+
+def test_markers_outside_the_lattice_are_rejected():
+    """Markers beyond a non-periodic side (more than half a spacing outside the
+    first or last node, where the half-way wall sits) or outside one period of
+    a periodic axis give LBM_ERR_INVALID and leave the bodies as they were."""
+    _say("marker domain validation")
+    g = lbmib.Sim(32, 24, 0.8, bc=(lbmib.WALL, lbmib.WALL, lbmib.PERIODIC, lbmib.PERIODIC))
+    ok = np.array([[-0.5, 3.0], [31.5, 5.0], [10.0, 0.0], [12.0, 23.99]])
+    g.set_body(0, lbmib.FIXED, len(ok), xy=ok, ds=np.ones(len(ok)))
+    for bad in ([-0.51, 3.0], [31.51, 5.0], [10.0, -0.01], [12.0, 24.0]):
+        xy = np.array([[5.0, 5.0], bad, [6.0, 6.0]])
+        with pytest.raises(lbmib.LbmError) as e:
+            g.set_body(1, lbmib.FIXED, 3, xy=xy, ds=np.ones(3))
+        assert e.value.code == lbmib.ERR_INVALID
+    # a free circle must fit whole between the walls
+    with pytest.raises(lbmib.LbmError) as e:
+        g.set_body(1, lbmib.FREE, 20, xc=(4.0, 12.0), radius=4.6, rho_s=1.2)
+    assert e.value.code == lbmib.ERR_INVALID
+    g.set_body(1, lbmib.FREE, 20, xc=(4.0, 12.0), radius=4.5, rho_s=1.2)
+    g.step(2)
+    g.sync()
+    assert g.forces(0)[3] is not None

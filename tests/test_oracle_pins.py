@@ -100,6 +100,55 @@ def test_mrt_matrix_inverse_and_bgk_limit(po):
         assert np.allclose(bf.E.T @ c, bf.E.T @ f, atol=1e-15, rtol=0)
 
 
+def _equilibrium_moments(rho, ux, uy):
+    """Moments of Eq. 3 in the basis of Eq. 5, worked out by hand from the
+    lattice sums sum w = 1, sum w e_a e_b = delta_ab / 3 and
+    sum w e_a e_b e_c e_d = (delta_ab delta_cd + delta_ac delta_bd + delta_ad delta_bc) / 9:
+    (rho, e, epsilon, j_x, q_x, j_y, q_y, p_xx, p_xy) =
+    (rho, -2 rho + 3 rho |u|^2, rho - 3 rho |u|^2, rho u_x, -rho u_x, rho u_y,
+    -rho u_y, rho (u_x^2 - u_y^2), rho u_x u_y)."""
+    uu = ux * ux + uy * uy
+    return np.array([rho, -2 * rho + 3 * rho * uu, rho - 3 * rho * uu, rho * ux, -rho * ux, rho * uy,
+                     -rho * uy, rho * (ux * ux - uy * uy), rho * ux * uy])
+
+
+def test_mrt_rows_give_the_equilibrium_moments(po):
+    """Every row of the oracle's moment matrix (Eq. 5) maps the equilibrium of
+    Eq. 3 onto its closed-form moment, the rows are mutually orthogonal with
+    squared norms 9, 36, 36, 6, 12, 6, 12, 4, 4, and their entries are the
+    integers of the printed matrix (a wrong sign or a swapped entry in any row
+    breaks one of the three)."""
+    M, _ = po.mrt_matrix()
+    rng = np.random.default_rng(41)
+    for _ in range(200):
+        rho = 1 + 0.1 * rng.standard_normal()
+        u = 0.1 * rng.standard_normal(2)
+        assert np.allclose(M @ po.feq(rho, u[0], u[1]), _equilibrium_moments(rho, u[0], u[1]),
+                           atol=2e-15, rtol=0)
+    G = M @ M.T
+    assert np.array_equal(G, np.diag([9.0, 36, 36, 6, 12, 6, 12, 4, 4]))
+    assert np.array_equal(M, np.round(M)) and np.abs(M).max() == 4
+
+
+def test_mrt_relaxes_each_moment_at_its_own_rate(po):
+    """Eq. 2 in moment space: m' = m - S (m - m^eq) with the diagonal S of
+    Eq. 6, each moment at its own rate, m^eq from the closed form above (not
+    from the oracle's equilibrium); the conserved moments keep their values."""
+    M, _ = po.mrt_matrix()
+    tau = 0.7
+    rates = [1.0, 1.1, 1.25, 1.0, 1.8, 1.0, 1.8, 1 / tau, 1 / tau]
+    o = po.Oracle(8, 8, tau, collision=po.MRT, mrt_s=rates)
+    rng = np.random.default_rng(42)
+    conserved = [0, 3, 5]
+    for _ in range(100):
+        f = REST * (1 + 0.08 * rng.standard_normal(9))
+        m = M @ f
+        meq = _equilibrium_moments(m[0], m[3] / m[0], m[5] / m[0])
+        expect = m - np.array(rates) * (m - meq)
+        expect[conserved] = m[conserved]
+        assert np.allclose(M @ o.collide_node(f), expect, atol=2e-15, rtol=0)
+
+
 # ---------------------------------------------------------------- Eq. 1 + boundary rules
 
 def test_periodic_step_matches_numpy_roll(po):
@@ -339,6 +388,60 @@ def test_collision_force_closed_form(po):
     d = 2 * R + 0.5 * gap
     F = po.collision_force(xi, [d / math.sqrt(2), d / math.sqrt(2)], R, R, c, eps, gap)
     assert np.allclose(F, -0.25 * c / eps * np.array([1, 1]) / math.sqrt(2), rtol=1e-13)
+
+
+WALL_CASES = [  # side, bc tuple index, inward normal, gravity parallel to that side, side rule
+    ("west", 0, (1.0, 0.0), (0.0, -1e-4), "wall"),
+    ("east", 1, (-1.0, 0.0), (0.0, -1e-4), "wall"),
+    ("south", 2, (0.0, 1.0), (1e-4, 0.0), "wall"),
+    ("north", 3, (0.0, -1.0), (1e-4, 0.0), "wall"),
+    ("south_freeslip", 2, (0.0, 1.0), (1e-4, 0.0), "freeslip"),
+    ("north_freeslip", 3, (0.0, -1.0), (1e-4, 0.0), "freeslip"),
+]
+
+
+@pytest.mark.parametrize("side,idx,normal,g,rule", WALL_CASES, ids=[w[0] for w in WALL_CASES])
+def test_wall_collision_acts_through_a_mirror_particle(po, side, idx, normal, g, rule):
+    """Eq. 39 against a side: the wall sits half a spacing outside the first or
+    last node row (half-way bounce-back, Fig. 2) and acts through a mirror
+    particle of the same radius, so a circle whose surface is a gap h from the
+    wall feels c/eps ((2h - xi)/xi)^2 along the inward normal while 2h < xi,
+    c/eps at contact and nothing from h = xi/2 on (free-slip sides count as
+    walls).  With no correction sweeps, no fluid velocity and gravity parallel
+    to the wall, the first step's velocity change along the normal is that
+    force over M_s (Eqs. 37, 41)."""
+    nx, ny, R, rho_s = 40, 36, 5.0, 1.5
+    gap, eps = 0.1 * R, 0.01
+    V = math.pi * R * R
+    Ms = rho_s * V
+    c = (Ms - 1.0 * V) * math.hypot(*g)
+    side_bc = po.WALL if rule == "wall" else po.FREESLIP
+    bc = [po.PERIODIC] * 4
+    if idx < 2:
+        bc[0] = bc[1] = side_bc
+    else:
+        bc[2] = bc[3] = side_bc
+    a = 0 if idx < 2 else 1
+    lo, hi = -0.5, (nx if a == 0 else ny) - 0.5  # wall positions
+    for h in (0.0, 0.1 * gap, 0.3 * gap, 0.5 * gap - 1e-9, 0.5 * gap, 0.6 * gap, 2.0):
+        pos = [nx / 2.0, ny / 2.0]
+        pos[a] = lo + R + h if idx in (0, 2) else hi - R - h
+        o = po.Oracle(nx, ny, 0.8, bc=tuple(bc), ib_iters=0, gravity=g)
+        o.set_body(0, po.FREE, 32, xc=pos, radius=R, rho_s=rho_s)
+        o.step(1)
+        _, _, _, st = o.forces(0)
+        Fn = Ms * (st[2] * normal[0] + st[3] * normal[1])
+        expect = c / eps * ((2 * h - gap) / gap) ** 2 if 2 * h < gap else 0.0
+        assert abs(Fn - expect) <= 1e-12 * max(1.0, c / eps), (side, h, Fn, expect)
+
+
+def test_no_wall_force_across_periodic_sides(po):
+    """A circle next to a periodic seam feels no wall collision force."""
+    R, rho_s = 5.0, 1.5
+    o = po.Oracle(40, 36, 0.8, bc=(po.PERIODIC,) * 4, ib_iters=0, gravity=(0.0, -1e-4))
+    o.set_body(0, po.FREE, 32, xc=(R - 0.5, 18.0), radius=R, rho_s=rho_s)
+    o.step(1)
+    assert o.forces(0)[3][2] == 0.0
 
 
 def test_rigid_constant_force_is_a_parabola(po):
