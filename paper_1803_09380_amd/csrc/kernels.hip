@@ -25,11 +25,13 @@
 namespace lbmib {
 
 // Tilings 8..15 repeat 0..7 with non-temporal loads and stores (streamed
-// data is not kept in the caches).  None of them changes the arithmetic.
+// data is not kept in the caches); 16..19 are block tiles (tx = 0: ty waves
+// of one block each, rpt rounds).  None of them changes the arithmetic.
 const Tiling kTilings[kNumTilings] = {
     {64, 4, 1, 0}, {64, 4, 2, 0}, {128, 2, 2, 0}, {256, 1, 2, 0}, {256, 1, 4, 0}, {64, 4, 4, 0},
     {256, 1, 1, 0}, {128, 2, 1, 0}, {64, 4, 1, 1}, {64, 4, 2, 1}, {128, 2, 2, 1}, {256, 1, 2, 1},
-    {256, 1, 4, 1}, {64, 4, 4, 1}, {256, 1, 1, 1}, {128, 2, 1, 1}};
+    {256, 1, 4, 1}, {64, 4, 4, 1}, {256, 1, 1, 1}, {128, 2, 1, 1}, {0, 4, 1, 1}, {0, 4, 2, 1},
+    {0, 8, 1, 1}, {0, 4, 1, 0}};
 
 // Typed accessors: LDS-resident arrays are read with ds_read, device memory
 // with global loads and stores (never the flat path of generic pointers, whose
@@ -160,15 +162,70 @@ __device__ __forceinline__ void mrt(T h[9], T rho_base, const T rate[9], uint32_
 // wait on memory, and the latency-bound kernels would otherwise queue behind them.
 __device__ __forceinline__ void raise_wave_priority() { __builtin_amdgcn_s_setprio(2); }
 
-// At most seven waves per SIMD: the sweep streams at a higher rate than with
-// eight (measured), and each SIMD keeps a wave slot for the other kernels.
-template <typename T, int TX, int TY, int RPT, bool NTMP>
-__global__ void __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(1, 7)))
-    k_sweep(const SimDev* __restrict__ sims, const int4* __restrict__ tiles,
-            const BatchHeader* __restrict__ hdr, int ntiles_arg, int parity, int part) {
-    int t0 = blockIdx.x, t1 = hdr ? hdr->ntiles : ntiles_arg, dt = gridDim.x;
+// One node of the sweep: collision and streaming of node (x, y) of a
+// simulation whose stored row y = 0 starts at P (rows rs elements apart).
+template <typename T, bool NTMP>
+__device__ __forceinline__ void sweep_node(LBM_AS1 T* __restrict__ P, int64_t rs, int nx, int ny, int px, int py,
+                                           int x, int y, int sw, T rho_base, T omega, bool use_mrt,
+                                           const T rate[9], uint32_t& bad) {
+    constexpr int B = kBlk;
+    const int c0 = col_off(x);
+    LBM_AS1 T* __restrict__ R0 = P + (int64_t)y * rs;
+    T h[9];
+    if (!sw) {
+        // natural state: own slots; write f*_i into slot opp(i)
+#pragma unroll
+        for (int i = 0; i < 9; ++i) h[i] = ldg<NTMP>(&R0[c0 + i * B]);
+        if (use_mrt)
+            mrt<T>(h, rho_base, rate, bad);
+        else
+            bgk<T>(h, rho_base, omega, bad);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) stg<NTMP>(&R0[c0 + opp_of(i) * B], h[i]);
+        return;
+    }
+    // swapped state: f_i(x) = slot opp(i) of x - e_i; element offsets of
+    // x - 1 and x + 1 within a stored row, rows y - 1 and y + 1.  A wave's
+    // load shifted by one node in x takes one element from the cache line the
+    // neighbouring block's wave also reads, so those six loads stay cached
+    // (a non-temporal load lets the line go before the neighbour gets it).
+    const int cm = col_off(wrap(x - 1, nx, px)), cp = col_off(wrap(x + 1, nx, px));
+    LBM_AS1 T* __restrict__ Rm = P + (int64_t)wrap(y - 1, ny, py) * rs;
+    LBM_AS1 T* __restrict__ Rp = P + (int64_t)wrap(y + 1, ny, py) * rs;
+    h[0] = ldg<NTMP>(&R0[c0 + 0 * B]);
+    h[1] = ldg<false>(&R0[cm + 3 * B]);
+    h[2] = ldg<NTMP>(&Rm[c0 + 4 * B]);
+    h[3] = ldg<false>(&R0[cp + 1 * B]);
+    h[4] = ldg<NTMP>(&Rp[c0 + 2 * B]);
+    h[5] = ldg<false>(&Rm[cm + 7 * B]);
+    h[6] = ldg<false>(&Rm[cp + 8 * B]);
+    h[7] = ldg<false>(&Rp[cp + 5 * B]);
+    h[8] = ldg<false>(&Rp[cm + 6 * B]);
+    if (use_mrt)
+        mrt<T>(h, rho_base, rate, bad);
+    else
+        bgk<T>(h, rho_base, omega, bad);
+    // f*_i goes to slot i of x + e_i
+    stg<NTMP>(&R0[c0 + 0 * B], h[0]);
+    stg<NTMP>(&R0[cp + 1 * B], h[1]);
+    stg<NTMP>(&Rp[c0 + 2 * B], h[2]);
+    stg<NTMP>(&R0[cm + 3 * B], h[3]);
+    stg<NTMP>(&Rm[c0 + 4 * B], h[4]);
+    stg<NTMP>(&Rp[cp + 5 * B], h[5]);
+    stg<NTMP>(&Rp[cm + 6 * B], h[6]);
+    stg<NTMP>(&Rm[cm + 7 * B], h[7]);
+    stg<NTMP>(&Rm[cp + 8 * B], h[8]);
+}
+
+// Tile range of workgroup blockIdx.x: with a batch header and a grid that is a
+// multiple of 8, the tiles dealt to its XCD (part 0 or 1: the first or second
+// half of them); otherwise a grid-stride loop over every tile.
+__device__ __forceinline__ void tile_range(const BatchHeader* hdr, int ntiles_arg, int part, int& t0, int& t1,
+                                           int& dt) {
+    t0 = blockIdx.x;
+    t1 = hdr ? hdr->ntiles : ntiles_arg;
+    dt = gridDim.x;
     if (hdr && (gridDim.x & 7) == 0) {
-        // part 0 or 1: the first or second half of every XCD's tiles
         const int xcd = blockIdx.x & 7;
         int s = hdr->xcd_start[xcd], e = hdr->xcd_start[xcd + 1];
         if (part >= 0) {
@@ -182,15 +239,23 @@ __global__ void __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(1, 
         t1 = e;
         dt = gridDim.x >> 3;
     }
+}
+
+// At most seven waves per SIMD: the sweep streams at a higher rate than with
+// eight (measured), and each SIMD keeps a wave slot for the other kernels.
+// Rectangular tiles: TX x TY threads, RPT rows per thread, tile (sim, x0, y0).
+template <typename T, int TX, int TY, int RPT, bool NTMP>
+__global__ void __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(1, 7)))
+    k_sweep(const SimDev* __restrict__ sims, const int4* __restrict__ tiles,
+            const BatchHeader* __restrict__ hdr, int ntiles_arg, int parity, int part) {
+    int t0, t1, dt;
+    tile_range(hdr, ntiles_arg, part, t0, t1, dt);
     for (int t = t0; t < t1; t += dt) {
         const int4 tile = tiles[t];
         const SimDev& S = sims[tile.x];
         if (!S.active) continue;
         const int sw = parity >= 0 ? parity : S.swapped;
-        const int nx = S.nx, ny = S.ny, px = S.px, py = S.py;
-        const int64_t pl = S.plane;
-        const int pitch = S.pitch;
-        LBM_AS1 T* __restrict__ P = gptr(reinterpret_cast<T*>(S.pop)) + S.xoff + pitch;  // (x=0, y=0)
+        LBM_AS1 T* __restrict__ P = gptr(reinterpret_cast<T*>(S.pop)) + S.rstride;  // stored row of y = 0
         const T rho_base = T(S.rho_base), omega = T(S.omega);
         const bool use_mrt = S.collision != 0;
         T rate[9];
@@ -198,52 +263,55 @@ __global__ void __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(1, 
         for (int k = 0; k < 9; ++k) rate[k] = T(S.mrt_s[k]);
         const int x = tile.y + threadIdx.x;
         uint32_t bad = 0;
-        if (x < nx) {
-            const int xm = wrap(x - 1, nx, px), xp = wrap(x + 1, nx, px);
+        if (x < S.nx) {
 #pragma unroll
             for (int r = 0; r < RPT; ++r) {
                 const int y = tile.z + threadIdx.y * RPT + r;
-                if (y >= ny) break;
-                const int ym = wrap(y - 1, ny, py), yp = wrap(y + 1, ny, py);
-                const int r0 = y * pitch, rm = ym * pitch, rp = yp * pitch;
-                T h[9];
-                if (!sw) {
-                    // natural state: own slots; write f*_i into slot opp(i)
-#pragma unroll
-                    for (int i = 0; i < 9; ++i) h[i] = ldg<NTMP>(&P[i * pl + r0 + x]);
-                    if (use_mrt)
-                        mrt<T>(h, rho_base, rate, bad);
-                    else
-                        bgk<T>(h, rho_base, omega, bad);
-#pragma unroll
-                    for (int i = 0; i < 9; ++i) stg<NTMP>(&P[opp_of(i) * pl + r0 + x], h[i]);
-                } else {
-                    // swapped state: f_i(x) = slot opp(i) of x - e_i
-                    h[0] = ldg<NTMP>(&P[0 * pl + r0 + x]);
-                    h[1] = ldg<NTMP>(&P[3 * pl + r0 + xm]);
-                    h[2] = ldg<NTMP>(&P[4 * pl + rm + x]);
-                    h[3] = ldg<NTMP>(&P[1 * pl + r0 + xp]);
-                    h[4] = ldg<NTMP>(&P[2 * pl + rp + x]);
-                    h[5] = ldg<NTMP>(&P[7 * pl + rm + xm]);
-                    h[6] = ldg<NTMP>(&P[8 * pl + rm + xp]);
-                    h[7] = ldg<NTMP>(&P[5 * pl + rp + xp]);
-                    h[8] = ldg<NTMP>(&P[6 * pl + rp + xm]);
-                    if (use_mrt)
-                        mrt<T>(h, rho_base, rate, bad);
-                    else
-                        bgk<T>(h, rho_base, omega, bad);
-                    // f*_i goes to slot i of x + e_i
-                    stg<NTMP>(&P[0 * pl + r0 + x], h[0]);
-                    stg<NTMP>(&P[1 * pl + r0 + xp], h[1]);
-                    stg<NTMP>(&P[2 * pl + rp + x], h[2]);
-                    stg<NTMP>(&P[3 * pl + r0 + xm], h[3]);
-                    stg<NTMP>(&P[4 * pl + rm + x], h[4]);
-                    stg<NTMP>(&P[5 * pl + rp + xp], h[5]);
-                    stg<NTMP>(&P[6 * pl + rp + xm], h[6]);
-                    stg<NTMP>(&P[7 * pl + rm + xm], h[7]);
-                    stg<NTMP>(&P[8 * pl + rm + xp], h[8]);
-                }
+                if (y >= S.ny) break;
+                sweep_node<T, NTMP>(P, S.rstride, S.nx, S.ny, S.px, S.py, x, y, sw, rho_base, omega, use_mrt, rate,
+                                    bad);
             }
+        }
+        if (bad) atomicOr(S.status, ST_UNSTABLE);
+    }
+}
+
+// Block tiles: every wave takes whole blocks of kBlk nodes of one row; a tile
+// (sim, k0) is the W * R consecutive blocks k0 .. k0 + W R - 1 of the
+// simulation in row-major order (block k: row k / nbx, nodes
+// kBlk (k % nbx) ..), round r giving wave w block k0 + r W + w.  Short rows
+// then leave no whole waves idle, and a workgroup's blocks are adjacent in
+// memory.
+template <typename T, int W, int R, bool NTMP>
+__global__ void __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(1, 7)))
+    k_sweep_blk(const SimDev* __restrict__ sims, const int4* __restrict__ tiles,
+                const BatchHeader* __restrict__ hdr, int ntiles_arg, int parity, int part) {
+    int t0, t1, dt;
+    tile_range(hdr, ntiles_arg, part, t0, t1, dt);
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    for (int t = t0; t < t1; t += dt) {
+        const int4 tile = tiles[t];
+        const SimDev& S = sims[tile.x];
+        if (!S.active) continue;
+        const int sw = parity >= 0 ? parity : S.swapped;
+        LBM_AS1 T* __restrict__ P = gptr(reinterpret_cast<T*>(S.pop)) + S.rstride;
+        const T rho_base = T(S.rho_base), omega = T(S.omega);
+        const bool use_mrt = S.collision != 0;
+        T rate[9];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) rate[k] = T(S.mrt_s[k]);
+        const int nbx = (S.nx + kBlk - 1) / kBlk, nb = nbx * S.ny;
+        uint32_t bad = 0;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int k = tile.y + r * W + w;
+            if (k >= nb) break;
+            const int y = k / nbx;
+            const int x = (k - y * nbx) * kBlk + lane;
+            if (x < S.nx)
+                sweep_node<T, NTMP>(P, S.rstride, S.nx, S.ny, S.px, S.py, x, y, sw, rho_base, omega, use_mrt, rate,
+                                    bad);
         }
         if (bad) atomicOr(S.status, ST_UNSTABLE);
     }
@@ -1706,10 +1774,11 @@ __global__ void k_advance(SimDev* sims, const BatchHeader* hdr, int nsims_arg) {
     }
 }
 
+// Fields of rows y0 .. y0 + gridDim.y - 1, written from index 0 of the outputs.
 template <typename T>
-__global__ void k_fields(const SimDev* sim, int sw, double* rho, double* ux, double* uy) {
+__global__ void k_fields(const SimDev* sim, int sw, int y0, double* rho, double* ux, double* uy) {
     const SimDev& S = *sim;
-    const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
+    const int x = blockIdx.x * blockDim.x + threadIdx.x, y = y0 + (int)blockIdx.y;
     if (x >= S.nx) return;
     double h[9];
 #pragma unroll
@@ -1718,7 +1787,7 @@ __global__ void k_fields(const SimDev* sim, int sw, double* rho, double* ux, dou
     const double r = S.rho_base + Ssum;
     const double jx = (h[1] + h[5] + h[8]) - (h[3] + h[6] + h[7]);
     const double jy = (h[2] + h[5] + h[6]) - (h[4] + h[7] + h[8]);
-    const int64_t c = (int64_t)y * S.nx + x;
+    const int64_t c = (int64_t)(y - y0) * S.nx + x;
     if (rho) rho[c] = r;
     if (ux) ux[c] = jx / r;
     if (uy) uy[c] = jy / r;
@@ -1771,10 +1840,22 @@ static hipError_t sweep_t(const SimDev* sims, const int4* tiles, const BatchHead
     return hipGetLastError();
 }
 
+template <typename T, int W, int R, bool NTMP>
+static hipError_t sweep_b(const SimDev* sims, const int4* tiles, const BatchHeader* hdr, int ntiles, int grid,
+                          int parity, int part, hipStream_t st) {
+    hipLaunchKernelGGL((k_sweep_blk<T, W, R, NTMP>), dim3(grid), dim3(64 * W), 0, st, sims, tiles, hdr, ntiles,
+                       parity, part);
+    return hipGetLastError();
+}
+
 template <typename T>
 static hipError_t sweep_tt(int tiling, const SimDev* sims, const int4* tiles, const BatchHeader* hdr, int ntiles,
                            int grid, int parity, int part, hipStream_t st) {
     switch (tiling) {
+        case 16: return sweep_b<T, 4, 1, true>(sims, tiles, hdr, ntiles, grid, parity, part, st);
+        case 17: return sweep_b<T, 4, 2, true>(sims, tiles, hdr, ntiles, grid, parity, part, st);
+        case 18: return sweep_b<T, 8, 1, true>(sims, tiles, hdr, ntiles, grid, parity, part, st);
+        case 19: return sweep_b<T, 4, 1, false>(sims, tiles, hdr, ntiles, grid, parity, part, st);
         case 0: return sweep_t<T, 64, 4, 1, false>(sims, tiles, hdr, ntiles, grid, parity, part, st);
         case 1: return sweep_t<T, 64, 4, 2, false>(sims, tiles, hdr, ntiles, grid, parity, part, st);
         case 2: return sweep_t<T, 128, 2, 2, false>(sims, tiles, hdr, ntiles, grid, parity, part, st);
@@ -1867,7 +1948,12 @@ hipError_t launch_advance(SimDev* sims, const BatchHeader* hdr, int nsims, hipSt
 
 hipError_t launch_fields(bool f64, const SimDev* sim, int nx, int ny, int sw, double* rho, double* ux, double* uy,
                          hipStream_t stream) {
-    IO_LAUNCH(k_fields, sim, sw, rho, ux, uy);
+    IO_LAUNCH(k_fields, sim, sw, 0, rho, ux, uy);
+}
+hipError_t launch_fields_rows(bool f64, const SimDev* sim, int nx, int y0, int rows, int sw, double* rho, double* ux,
+                              double* uy, hipStream_t stream) {
+    const int ny = rows;
+    IO_LAUNCH(k_fields, sim, sw, y0, rho, ux, uy);
 }
 hipError_t launch_get_pop(bool f64, const SimDev* sim, int nx, int ny, int sw, double* f, hipStream_t stream) {
     IO_LAUNCH(k_get_pop, sim, sw, f);

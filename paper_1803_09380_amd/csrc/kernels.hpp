@@ -11,7 +11,7 @@ namespace lbmib {
 struct Tiling {
     int tx, ty, rpt, nontemporal;
 };
-constexpr int kNumTilings = 16;
+constexpr int kNumTilings = 20;
 extern const Tiling kTilings[kNumTilings];
 
 // Entries sorted in LDS when a plan is rebuilt on the device (16 per marker).
@@ -45,6 +45,9 @@ int ib_variant(bool f64, int max_markers);
 // Field and population I/O of one simulation (state `sw` = AA state now).
 hipError_t launch_fields(bool f64, const SimDev* sim, int nx, int ny, int sw, double* rho,
                          double* ux, double* uy, hipStream_t stream);
+// rows y0 .. y0 + rows - 1 only, written from index 0 of the outputs
+hipError_t launch_fields_rows(bool f64, const SimDev* sim, int nx, int y0, int rows, int sw, double* rho,
+                              double* ux, double* uy, hipStream_t stream);
 hipError_t launch_get_pop(bool f64, const SimDev* sim, int nx, int ny, int sw, double* f,
                           hipStream_t stream);
 hipError_t launch_set_pop(bool f64, const SimDev* sim, int nx, int ny, int sw, const double* f,

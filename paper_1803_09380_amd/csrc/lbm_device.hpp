@@ -1,12 +1,18 @@
 // Device-side descriptors and lattice helpers of the gfx950 IB-LBM library.
 //
-// Population storage (per simulation): nine planes, one per lattice direction,
-// each (ny + 2) rows of `pitch` elements.  Row r holds lattice row y = r - 1,
-// so rows y = -1 and y = ny are a ghost layer; within a row, x = 0 sits at
-// element `xoff` (a 128-byte boundary) and x = -1, x = nx are ghost cells.
-// The ghost layer receives populations that leave through a non-periodic side
-// and holds the post-stream values that the boundary kernel writes for the
-// next sweep to read.
+// Population storage (per simulation): row-blocked.  The lattice rows
+// y = -1 .. ny (rows -1 and ny are a ghost layer) are stored one after the
+// other, `rstride` elements each.  A row is a sequence of `nblk` blocks of
+// kBlk consecutive nodes; a block holds the nine populations of its nodes,
+// population i in elements i * kBlk .. i * kBlk + kBlk - 1.  Block 0 is a
+// ghost block whose last element is x = -1; block b >= 1 holds
+// x = kBlk (b - 1) .. kBlk b - 1, and x = nx (a ghost cell) lies in the last
+// block.  One wavefront's access to one population of one block is one
+// contiguous 256-byte (FP32) segment, as with separate planes, but the nine
+// segments a node's update touches sit together, which keeps the sweep's
+// HBM stream as local as a plain copy.  The ghost layer receives populations
+// that leave through a non-periodic side and holds the post-stream values
+// that the boundary kernel writes for the next sweep to read.
 //
 // In-place AA access pattern: `swapped` = 0 ("natural") means the post-stream
 // population f_i(x) lives in slot i of cell x; `swapped` = 1 means it lives
@@ -23,6 +29,12 @@
 namespace lbmib {
 
 constexpr int Q = 9;
+constexpr int kBlk = 64;  // nodes per block of the population layout
+
+// Blocks per stored row for nx nodes (ghost block, data blocks, x = nx inside).
+__host__ __device__ constexpr int blocks_per_row(int nx) { return ((nx + kBlk) / kBlk) + 1; }
+// Element offset of x within a stored row (population 0); x >= -1.
+__host__ __device__ __forceinline__ int col_off(int x) { return ((x + kBlk) / kBlk) * (Q * kBlk) + ((x + kBlk) % kBlk); }
 
 // D2Q9 order fixed by the j_x and j_y rows of the moment matrix (Eq. 5).
 __host__ __device__ constexpr int ex_of(int i) {
@@ -66,9 +78,9 @@ struct BodyDev {
 };
 
 struct SimDev {
-    void* pop;           // T* base of the nine planes
-    int64_t plane;       // elements per plane
-    int32_t pitch, xoff; // elements per row, offset of x = 0
+    void* pop;           // T* base of the stored rows
+    int64_t rstride;     // elements per stored row (nblk * 9 * kBlk)
+    int32_t nblk, pad0_; // blocks per stored row
     int32_t nx, ny;
     int32_t bc[4];       // W, E, S, N
     int32_t px, py;      // periodic axes
@@ -153,7 +165,7 @@ __device__ __forceinline__ int wrap(int v, int n, int periodic) {
 
 template <typename T>
 __device__ __forceinline__ T* slot(const SimDev& S, int i, int x, int y) {
-    return reinterpret_cast<T*>(S.pop) + (int64_t)i * S.plane + (int64_t)(y + 1) * S.pitch + S.xoff + x;
+    return reinterpret_cast<T*>(S.pop) + (int64_t)(y + 1) * S.rstride + col_off(x) + i * kBlk;
 }
 
 // Where the post-stream f_i(x, y) lives for AA state `sw`.

@@ -227,8 +227,17 @@ int perimeter_count(const SimDev& h) {
     return n;
 }
 
+// Sweep tiles of one simulation: (sim, x0, y0) for rectangular tilings;
+// (sim, first block, row of that block) for block tilings (tx = 0), whose
+// tiles are ty * rpt consecutive blocks of kBlk nodes in row-major order.
+// The third field is the row the tile starts in either way.
 void build_tiles(lbm_sim* s, int sim_index, int tiling, std::vector<int4>& out) {
     const Tiling& t = kTilings[tiling];
+    if (t.tx == 0) {
+        const int nbx = (s->p.nx + kBlk - 1) / kBlk, nb = nbx * s->p.ny, per = t.ty * t.rpt;
+        for (int k0 = 0; k0 < nb; k0 += per) out.push_back(make_int4(sim_index, k0, k0 / nbx, 0));
+        return;
+    }
     const int th = t.ty * t.rpt;
     for (int y0 = 0; y0 < s->p.ny; y0 += th)
         for (int x0 = 0; x0 < s->p.nx; x0 += t.tx) out.push_back(make_int4(sim_index, x0, y0, 0));
@@ -599,14 +608,10 @@ lbm_status lbm_create(const lbm_params* p, void* hip_stream, lbm_sim** out) {
         s->own_stream = true;
     }
     const int esz = s->f64 ? 8 : 4;
-    const int xoff = 128 / esz;
-    int pitch = xoff + p->nx + 1;
-    pitch = (pitch + xoff - 1) / xoff * xoff;
     SimDev& h = s->h;
     memset(&h, 0, sizeof h);
-    h.plane = (int64_t)pitch * (p->ny + 2);
-    h.pitch = pitch;
-    h.xoff = xoff;
+    h.nblk = blocks_per_row(p->nx);
+    h.rstride = (int64_t)h.nblk * Q * kBlk;
     h.nx = p->nx;
     h.ny = p->ny;
     h.bc[0] = p->bc_west;
@@ -635,7 +640,7 @@ lbm_status lbm_create(const lbm_params* p, void* hip_stream, lbm_sim** out) {
         lbm_destroy(s);
         return e;
     };
-    if (s->pop.alloc((size_t)h.plane * 9 * esz) != hipSuccess) return bail(LBM_ERR_NOMEM);
+    if (s->pop.alloc((size_t)h.rstride * (p->ny + 2) * esz) != hipSuccess) return bail(LBM_ERR_NOMEM);
     if (s->desc.alloc(sizeof(SimDev)) != hipSuccess || s->status.alloc(sizeof(uint32_t)) != hipSuccess)
         return bail(LBM_ERR_NOMEM);
     if (hipMemsetAsync(s->pop.p, 0, s->pop.bytes, s->stream) != hipSuccess ||
