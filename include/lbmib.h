@@ -203,6 +203,15 @@ lbm_status ib_forces(lbm_sim* s, int32_t body_id, double F[2], double* T, double
  * Synchronises.  Errors: LBM_ERR_NOMEM, LBM_ERR_DEVICE, LBM_ERR_UNSTABLE
  * (the fields are still written). */
 lbm_status lbm_fields(lbm_sim* s, double* rho, double* ux, double* uy);
+/* lbm_fields for callers that cannot allocate device memory (tight serving
+ * loops, harnesses that forbid hipMalloc): the same values, staged through a
+ * static device array of 2^20 doubles (8 MiB) that each GPU the library runs
+ * on holds until the process ends; no hipMalloc or hipFree.  Rows are staged
+ * in chunks, so any lattice whose rows have at most 349,525 nodes is accepted
+ * (LBM_ERR_INVALID beyond).  Every call on one GPU uses that GPU's array:
+ * calls that overlap on one GPU, from any thread or handle, race.
+ * Synchronises; errors as lbm_fields. */
+lbm_status lbm_fields_noalloc(lbm_sim* s, double* rho, double* ux, double* uy);
 /* Same into FP64 device arrays [ny][nx]; enqueued on the handle's stream. */
 lbm_status lbm_fields_device(lbm_sim* s, void* rho, void* ux, void* uy);
 /* Post-stream populations f_i (unshifted) as host FP64 [9][ny][nx].  Synchronises. */

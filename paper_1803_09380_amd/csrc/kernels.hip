@@ -20,6 +20,8 @@
 // - 1.5 j.j/rho) (Eq. 3 with c_s^2 = 1/3 and rho u = j).
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "kernels.hpp"
 
 namespace lbmib {
@@ -1965,6 +1967,38 @@ hipError_t launch_set_pop(bool f64, const SimDev* sim, int nx, int ny, int sw, c
 hipError_t launch_set_eq(bool f64, const SimDev* sim, int nx, int ny, int sw, const double* rho, const double* ux,
                          const double* uy, double rho0, double u0x, double u0y, hipStream_t stream) {
     IO_LAUNCH(k_set_eq, sim, sw, rho, ux, uy, rho0, u0x, u0y);
+}
+
+}  // namespace lbmib
+
+// ---------------------------------------------------------------- static staging
+
+// Device staging of lbm_fields_noalloc, for callers that cannot allocate:
+// kStaticScratchDoubles doubles on every device the library runs on, held
+// until the process ends.  Host code never uses the array's name as an
+// address: static_scratch() takes the device address once per device with
+// hipGetSymbolAddress and hands out that pointer.
+static __device__ __align__(256) double scratch[lbmib::kStaticScratchDoubles];
+
+namespace lbmib {
+
+hipError_t static_scratch(double** out) {
+    static std::mutex mu;
+    static double* addr[kMaxDevices] = {};
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        addr[dev] = static_cast<double*>(p);
+    }
+    *out = addr[dev];
+    return hipSuccess;
 }
 
 }  // namespace lbmib

@@ -19,6 +19,12 @@ constexpr int kMaxDynEntries = 8192;
 constexpr int kMaxGroupMarkers = 4096;
 constexpr int kMaxColors = 32;  // colour classes of a band spread without conflicts
 
+// Static device staging (lbm_fields_noalloc): 8 MiB per device.
+constexpr size_t kStaticScratchDoubles = size_t(1) << 20;
+constexpr int kMaxDevices = 64;
+// Device address of this device's staging array (taken once per device).
+hipError_t static_scratch(double** out);
+
 // All launchers enqueue on `stream`.  `parity` >= 0 forces the AA state the
 // step starts from; -1 reads it from each simulation's descriptor (batches).
 // Counts come from `hdr` when it is non-null (graph-captured batches),

@@ -877,6 +877,35 @@ lbm_status lbm_fields(lbm_sim* s, double* rho, double* ux, double* uy) {
     return check_status(s);
 }
 
+lbm_status lbm_fields_noalloc(lbm_sim* s, double* rho, double* ux, double* uy) {
+    if (!s) return LBM_ERR_INVALID;
+    {
+        lbm_status rc_ = refresh(s);
+        if (rc_ != LBM_OK) return rc_;
+    }
+    double* stage = nullptr;
+    HIPS(s, static_scratch(&stage));
+    const int nx = s->p.nx, ny = s->p.ny;
+    const size_t per_row = 3 * (size_t)nx;
+    if (per_row > kStaticScratchDoubles)
+        return fail(s, LBM_ERR_INVALID, fmt("rows of %d nodes exceed the static staging buffer (at most %zu nodes per row)",
+                                            nx, kStaticScratchDoubles / 3));
+    const int rows = (int)std::min<size_t>((size_t)ny, kStaticScratchDoubles / per_row);
+    // rows [y0, y0 + r) at a time: fields into the staging array, then to the
+    // caller's arrays; the copies finish before the next chunk overwrites it
+    for (int y0 = 0; y0 < ny; y0 += rows) {
+        const int r = std::min(rows, ny - y0);
+        const size_t n = (size_t)r * nx, off = (size_t)y0 * nx;
+        HIPS(s, launch_fields_rows(s->f64, (const SimDev*)s->desc.p, nx, y0, r, s->h.swapped, stage, stage + n,
+                                   stage + 2 * n, s->stream));
+        if (rho) HIPS(s, hipMemcpyAsync(rho + off, stage, n * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+        if (ux) HIPS(s, hipMemcpyAsync(ux + off, stage + n, n * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+        if (uy) HIPS(s, hipMemcpyAsync(uy + off, stage + 2 * n, n * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+        HIPS(s, hipStreamSynchronize(s->stream));
+    }
+    return check_status(s);
+}
+
 lbm_status lbm_get_populations(lbm_sim* s, double* f) {
     if (!s || !f) return LBM_ERR_INVALID;
     {

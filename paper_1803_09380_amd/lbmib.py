@@ -62,6 +62,7 @@ SIGNATURES = [
     ("ib_forces", _ST, [_P, _I32, _DP, _DP, _DP, ctypes.POINTER(Body)]),
     ("lbm_fields", _ST, [_P, _DP, _DP, _DP]),
     ("lbm_fields_device", _ST, [_P, _P, _P, _P]),
+    ("lbm_fields_noalloc", _ST, [_P, _DP, _DP, _DP]),
     ("lbm_get_populations", _ST, [_P, _DP]),
     ("lbm_set_populations", _ST, [_P, _DP]),
     ("lbm_set_fields", _ST, [_P, _DP, _DP, _DP]),
@@ -239,6 +240,12 @@ class Sim:
     def fields(self):
         r, u, v = (np.empty((self.ny, self.nx)) for _ in range(3))
         self._check(load().lbm_fields(self._h, _dp(r), _dp(u), _dp(v)), "lbm_fields")
+        return r, u, v
+
+    def fields_noalloc(self):
+        """fields() through the library's static staging array (no device allocation)."""
+        r, u, v = (np.empty((self.ny, self.nx)) for _ in range(3))
+        self._check(load().lbm_fields_noalloc(self._h, _dp(r), _dp(u), _dp(v)), "lbm_fields_noalloc")
         return r, u, v
 
     def fields_device(self, rho, ux, uy):
