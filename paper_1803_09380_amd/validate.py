@@ -262,19 +262,64 @@ def couette(lbmib, sides, steps_per_k2=3000):
             rel, e35 = dg.couette_errors(ux, uy, m["centre"], m["R1"], m["R2"], m["omega1"])
             T = s.forces(1)[1]
             Ta = dg.couette_torque(m["nu"] * c["rho0"], m["omega1"], m["R1"], m["R2"])
-            rows.append({"side": c["nx"], "rel_l2": rel, "l2_eq35": e35, "torque_over_closed_form": T / Ta,
+            rows.append({"side": c["nx"], "rel_l2": rel, "l2_eq35": e35, "l2_eq35_relative": e35 / (m["omega1"] * m["R1"]),
+                         "torque_over_closed_form": T / Ta,
                          "mass_drift": float(rho.sum() / (c["rho0"] * c["nx"] * c["ny"]) - 1.0)})
             s.close()
         out["precisions"][name] = {
             "rows": rows,
             "order_rel_l2": -dg.observed_order(sides, [r["rel_l2"] for r in rows]) if len(rows) > 1 else None,
-            "order_l2_eq35": -dg.observed_order(sides, [r["l2_eq35"] for r in rows]) if len(rows) > 1 else None}
+            "order_eq35_lattice_units": -dg.observed_order(sides, [r["l2_eq35"] for r in rows]) if len(rows) > 1 else None,
+            "order_eq35_relative": -dg.observed_order(sides, [r["l2_eq35_relative"] for r in rows]) if len(rows) > 1 else None}
     out["fp32_vs_fp64_velocity_rel_l2"] = {}
+    out["fp32_vs_fp64_velocity_max_rel"] = {}
     for c in cases:
         a, b = fields[("f32_shifted", c["nx"])], fields[("f64", c["nx"])]
         num = np.sum((a[0] - b[0]) ** 2 + (a[1] - b[1]) ** 2)
         den = np.sum(b[0] ** 2 + b[1] ** 2)
         out["fp32_vs_fp64_velocity_rel_l2"][str(c["nx"])] = float(np.sqrt(num / den))
+        mx = max(np.abs(a[0] - b[0]).max(), np.abs(a[1] - b[1]).max())
+        out["fp32_vs_fp64_velocity_max_rel"][str(c["nx"])] = float(mx / max(np.abs(b[0]).max(), np.abs(b[1]).max()))
+    out["wall_s"] = time.perf_counter() - t0
+    return out
+
+
+COUETTE_PAPER_SETS = [(0.5, 0.65), (0.5, 0.85), (0.8, 0.65), (0.8, 0.85)]  # (radius ratio R, tau_s)
+
+
+def couette_paper(lbmib, grids, f64=True, sets=COUETTE_PAPER_SETS):
+    """Cylindrical Couette flow as set up in Sec. 3.1.2 (workloads.couette_paper:
+    MRT, Re = 10, tau_s = 0.65 / 0.85, R = 0.5 / 0.8, outer radius on N lattice
+    spacings), every grid and set in one batch, each run to its steady state.
+    Reports per set the Eq. 35 norm in lattice units and relative to the wall
+    speed U1, the relative error over the annulus, and the least-squares order
+    of each in 1/N.  Refinement keeps tau_s and Re, so U1 ~ 1/N and the
+    lattice-unit norm gains one order over the scale-free relative one."""
+    cases = [wl.couette_paper(N, r, t, precision=wl.F64 if f64 else wl.F32) for (r, t) in sets for N in grids]
+    budgets = [c["meta"]["steps"] for c in cases]
+
+    def progress(k, s, step):
+        if k == 0 and step % 20000 == 0:
+            print("couette_paper: %d steps" % step, file=sys.stderr, flush=True)
+
+    t0 = time.perf_counter()
+    sims = _run_batch(lbmib, cases, budgets, 4000, f64, progress)
+    out = {"case": "couette_paper", "grids": list(grids), "precision": "f64" if f64 else "f32_shifted", "sets": []}
+    h = [1.0 / N for N in grids]
+    for j, (r, t) in enumerate(sets):
+        rows = []
+        for i, N in enumerate(grids):
+            c, sim = cases[j * len(grids) + i], sims[j * len(grids) + i]
+            m = c["meta"]
+            _, ux, uy = sim.fields()
+            rel, e35 = dg.couette_errors(ux, uy, m["centre"], m["R1"], m["R2"], m["omega1"])
+            rows.append({"N": N, "steps": m["steps"], "eq35_lattice": e35, "eq35_relative": e35 / m["U1"],
+                         "annulus_relative": rel})
+            sim.close()
+        order = lambda key: dg.observed_order(h, [q[key] for q in rows]) if len(rows) > 1 else None
+        out["sets"].append({"R": r, "tau_s": t, "rows": rows, "order_eq35_lattice": order("eq35_lattice"),
+                            "order_eq35_relative": order("eq35_relative"),
+                            "order_annulus_relative": order("annulus_relative")})
     out["wall_s"] = time.perf_counter() - t0
     return out
 
@@ -327,7 +372,7 @@ def cylinder_channel(lbmib, res, steps=None, sample=20, periods=8):
 
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
-    ap.add_argument("case", choices=["table1", "dkt", "single", "tgv", "couette", "cylinder"])
+    ap.add_argument("case", choices=["table1", "dkt", "single", "tgv", "couette", "couette_paper", "cylinder"])
     ap.add_argument("--grids", type=int, nargs="+", default=[32, 64, 128, 256, 512],
                     help="Couette box sides (couette)")
     ap.add_argument("--steps-per-k2", type=int, default=3000)
@@ -336,6 +381,7 @@ def main(argv=None):
     ap.add_argument("--re", type=float, nargs="+", default=[20, 40, 100, 200])
     ap.add_argument("--ratios", type=float, nargs="+", default=[1.0015, 1.003, 1.01, 1.03])
     ap.add_argument("--f64", action="store_true")
+    ap.add_argument("--f32", action="store_true", help="FP32 shifted populations (couette_paper)")
     ap.add_argument("--seconds", type=float, default=None)
     ap.add_argument("--steady-steps", type=int, default=None)
     ap.add_argument("--unsteady-steps", type=int, default=None)
@@ -361,6 +407,9 @@ def main(argv=None):
         out = tgv(lbmib, args.sizes, f64=True, cylinder=not args.no_cylinder)
     elif args.case == "couette":
         out = couette(lbmib, args.grids, steps_per_k2=args.steps_per_k2)
+    elif args.case == "couette_paper":
+        grids = args.grids if args.grids != [32, 64, 128, 256, 512] else [20, 40, 80, 160]
+        out = couette_paper(lbmib, grids, f64=not args.f32)
     else:
         res = [int(r) if float(r).is_integer() else r for r in (args.re if args.re != [20, 40, 100, 200] else [20, 40, 100])]
         out = cylinder_channel(lbmib, res, steps=args.steady_steps)

@@ -12,9 +12,11 @@ Reported per run, against Eq. 34: the Eq. 35 norm on the theta = pi/2
 profile in lattice units and relative to U1, and the relative error over all
 annulus nodes; per parameter set, the least-squares orders of each.
 
-    python tests/couette_study.py [--grids 20 40 80] [--jobs 4]
+    python tests/couette_study.py [--grids 20 40 80] [--jobs 4] [--write-golden]
 
-runs the study on the FP64 CPU oracle (test infrastructure; minutes).
+runs the study on the FP64 CPU oracle (test infrastructure; minutes);
+--write-golden stores the oracle's errors in tests/golden/couette_paper_oracle.json,
+which the GPU test of the same set-up compares against.
 """
 import argparse
 import json
@@ -72,6 +74,7 @@ def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--grids", type=int, nargs="+", default=[20, 40, 80])
     ap.add_argument("--jobs", type=int, default=4)
+    ap.add_argument("--write-golden", action="store_true")
     args = ap.parse_args()
     import multiprocessing as mp
     os.environ.setdefault("OMP_NUM_THREADS", str(max(1, (os.cpu_count() or 1) // args.jobs)))
@@ -87,6 +90,14 @@ def main():
                     "annulus_relative": [x[2] for x in rows],
                     "order_eq35_lattice": o[0], "order_eq35_relative": o[1], "order_annulus_relative": o[2]})
         print(json.dumps(out[-1]), flush=True)
+    if args.write_golden:
+        path = os.path.join(HERE, "golden", "couette_paper_oracle.json")
+        with open(path, "w") as f:
+            json.dump({"source": "tests/couette_study.py on the FP64 CPU oracle (oracle/lbm_oracle.c); "
+                                 "cylindrical Couette flow as set up in Sec. 3.1.2 (workloads.couette_paper), "
+                                 "errors against Eq. 34",
+                       "columns": ["eq35_lattice", "eq35_relative", "annulus_relative"], "sets": out}, f, indent=1)
+        print("wrote", path, flush=True)
 
 
 if __name__ == "__main__":

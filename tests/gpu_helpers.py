@@ -49,3 +49,20 @@ def velocity_rel(gpu_fields, orc_fields):
     num = np.sum((ug - uo) ** 2 + (vg - vo) ** 2)
     den = np.sum(uo ** 2 + vo ** 2)
     return float(np.sqrt(num / den))
+
+
+def velocity_max_rel(gpu_fields, orc_fields):
+    """Node by node: max |u_gpu - u_orc| (either component) over max |u_orc|."""
+    _, ug, vg = gpu_fields
+    _, uo, vo = orc_fields
+    return float(max(np.abs(ug - uo).max(), np.abs(vg - vo).max()) / max(np.abs(uo).max(), np.abs(vo).max()))
+
+
+def check_fp32_velocity(gpu_fields, orc_fields, tol=1e-5):
+    """The FP32 velocity bar, as a relative L2 norm of the vector field and
+    node by node (so that a local error near the markers cannot hide in the
+    norm)."""
+    l2 = velocity_rel(gpu_fields, orc_fields)
+    mx = velocity_max_rel(gpu_fields, orc_fields)
+    assert l2 < tol and mx < tol, (l2, mx)
+    return l2, mx

@@ -94,16 +94,56 @@ def test_taylor_green_with_cylinder_order():
     assert all(o > 2.7 for o in out["orders"]), out["orders"]
 
 
-def test_couette_second_order_on_the_gpu():
+def test_couette_eq35_second_order_only_in_lattice_units():
     """Sec. 3.1.2 under diffusive scaling (fixed tau and Re, wall speed ~ 1/side):
-    the absolute L2 norm of Eq. 35 falls at second order as the paper reports
-    (first order relative to the wall speed); FP32 stays within 1e-5 of FP64."""
+    the Eq. 35 norm in lattice velocity units falls at second order only because
+    the wall speed itself falls as 1/side; relative to the wall speed (the
+    scale-free measure, also the error in physical units) it falls at first
+    order, and so does the relative error over the annulus."""
     _say("couette 32, 64, 128 in FP64 and FP32")
     out = val.couette(lbmib, [32, 64, 128])
     p64, p32 = out["precisions"]["f64"], out["precisions"]["f32_shifted"]
-    _say("  orders eq35 %.3f / %.3f, relative %.3f" % (p64["order_l2_eq35"], p32["order_l2_eq35"], p64["order_rel_l2"]))
-    assert p64["order_l2_eq35"] > 1.9 and p32["order_l2_eq35"] > 1.9
-    assert 0.9 < p64["order_rel_l2"] < 1.1
+    _say("  orders eq35 lattice %.3f / %.3f, eq35 relative %.3f, annulus relative %.3f" % (
+        p64["order_eq35_lattice_units"], p32["order_eq35_lattice_units"], p64["order_eq35_relative"],
+        p64["order_rel_l2"]))
+    assert p64["order_eq35_lattice_units"] > 1.9 and p32["order_eq35_lattice_units"] > 1.9
+    assert 0.9 < p64["order_eq35_relative"] < 1.1 and 0.9 < p64["order_rel_l2"] < 1.1
     assert all(abs(r["mass_drift"]) < 1e-11 for r in p64["rows"])
     assert all(v < 1e-5 for v in out["fp32_vs_fp64_velocity_rel_l2"].values())
     assert abs(p64["rows"][-1]["torque_over_closed_form"] - 1.0) < 0.06
+
+
+def test_couette_fp32_within_1e5_of_fp64_at_256_and_512():
+    """Config 2's precision bar at its two largest grids: FP32 shifted
+    populations stay within 1e-5 of the FP64 path on the velocity field, in
+    relative L2 and node by node (max |du| over max |u|), after 48,000 steps
+    (256^2) and 192,000 steps (512^2)."""
+    _say("couette 256, 512 in FP64 and FP32")
+    out = val.couette(lbmib, [256, 512])
+    _say("  fp32 vs fp64: L2 %s, max %s" % (out["fp32_vs_fp64_velocity_rel_l2"], out["fp32_vs_fp64_velocity_max_rel"]))
+    assert all(v <= 1e-5 for v in out["fp32_vs_fp64_velocity_rel_l2"].values())
+    assert all(v <= 1e-5 for v in out["fp32_vs_fp64_velocity_max_rel"].values())
+
+
+def test_paper_couette_set_up_matches_the_oracle_and_is_first_order():
+    """The paper's own Couette set-up (Sec. 3.1.2: MRT, Re = 10, tau_s = 0.65 and
+    0.85, R = 0.5 and 0.8), N = 20, 40, 80, 160, FP64, each run to steady state.
+    The errors against Eq. 34 at N = 20 .. 80 equal the FP64 oracle's (stored by
+    tests/couette_study.py); the Eq. 35 norm falls at about second order in
+    lattice units and at about first order relative to the wall speed."""
+    import json
+    import os
+    _say("paper couette set-up, N = 20, 40, 80, 160, f64")
+    out = val.couette_paper(lbmib, [20, 40, 80, 160])
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "couette_paper_oracle.json")))
+    for got, ref in zip(out["sets"], gold["sets"]):
+        assert (got["R"], got["tau_s"]) == (ref["R"], ref["tau_s"])
+        for k, N in enumerate(ref["grids"]):
+            row = got["rows"][out["grids"].index(N)]
+            for col in ("eq35_lattice", "annulus_relative"):
+                assert abs(row[col] - ref[col][k]) <= 1e-9 * ref[col][k], (got["R"], got["tau_s"], N, col)
+        _say("  R %.1f tau %.2f: order lattice %.3f relative %.3f annulus %.3f" % (
+            got["R"], got["tau_s"], got["order_eq35_lattice"], got["order_eq35_relative"],
+            got["order_annulus_relative"]))
+        assert 1.7 < got["order_eq35_lattice"] < 2.2
+        assert 0.7 < got["order_eq35_relative"] < 1.2 and 0.7 < got["order_annulus_relative"] < 1.2

@@ -555,3 +555,38 @@ def test_couette_profile_torque_and_order(po):
     ratios = [res[s][2] / res[s][3] for s in (32, 48, 64)]
     assert all(r > 1.0 for r in ratios) and ratios[0] > ratios[1] > ratios[2]
     assert abs(ratios[2] - 1) < 0.15
+
+
+@pytest.mark.slow
+def test_paper_couette_set_up_is_first_order_relative_to_the_wall_speed(po):
+    """Sec. 3.1.2's own set-up (MRT, Re = 10; here tau_s = 0.85, R = 0.5, outer
+    radius on N = 20 and 40 spacings) against Eq. 34.  Refinement at fixed
+    tau_s and Re halves the lattice wall speed, so the Eq. 35 norm in lattice
+    units falls by about four while the error relative to the wall speed (and
+    over the annulus) only halves: second order in lattice units, first order
+    in the scale-free measure.  Forty sweeps instead of ten leave the errors
+    within 0.5% (the slip left at the markers is not what limits them); the
+    stored study (tests/golden/couette_paper_oracle.json, written by
+    tests/couette_study.py) holds the same numbers."""
+    import json
+    import os
+    import couette_study as cs
+    e20 = cs.run_oracle(20, 0.5, 0.85)
+    e40 = cs.run_oracle(40, 0.5, 0.85)
+    lattice = math.log2(e20[0] / e40[0])
+    relative = math.log2(e20[1] / e40[1])
+    annulus = math.log2(e20[2] / e40[2])
+    assert 1.8 < lattice < 2.2 and 0.8 < relative < 1.2 and 0.8 < annulus < 1.2, (lattice, relative, annulus)
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "couette_paper_oracle.json")))
+    ref = [s for s in gold["sets"] if (s["R"], s["tau_s"]) == (0.5, 0.85)][0]
+    assert abs(e20[0] - ref["eq35_lattice"][0]) <= 1e-12 * e20[0]
+    assert abs(e40[2] - ref["annulus_relative"][1]) <= 1e-12 * e40[2]
+    case = wl.couette_paper(20, 0.5, 0.85, ib_iters=40)
+    o = po.Oracle(case["nx"], case["ny"], case["tau"], bc=case["bc"], collision=po.MRT, mrt_s=case["mrt_s"],
+                  ib_iters=40)
+    for k, b in enumerate(case["bodies"]):
+        o.set_body(k, b["kind"], b["n"], xy=b["xy"], ds=b["ds"], xc=b["xc"], omega=b["omega"])
+    o.step(case["meta"]["steps"])
+    _, ux, uy = o.fields()
+    e20_40 = cs.errors(case, ux, uy)
+    assert abs(e20_40[1] / e20[1] - 1) < 5e-3
