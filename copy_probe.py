@@ -22,7 +22,7 @@ import subprocess
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(ROOT, "copy_probe.hip")
-LIB = os.path.join(ROOT, "copy_probe.so")
+LIB = os.path.join(ROOT, "libcopy_probe.so")
 VARIANTS = {0: "copy16_loop", 1: "copy16_loop_nt", 2: "copy16_chunk", 3: "copy16_chunk_nt", 4: "read16_nt",
             5: "write16_nt"}
 
@@ -42,7 +42,7 @@ def build():
 def _lib():
     import torch  # noqa: F401  (one HIP runtime for torch and the probe)
     if not os.path.exists(LIB):
-        raise RuntimeError("copy_probe.so is not built; run copy_probe.build()")
+        raise RuntimeError("libcopy_probe.so is not built; run copy_probe.build()")
     L = ctypes.CDLL(LIB)
     L.copy_probe_launch.restype = ctypes.c_int
     L.copy_probe_launch.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int,

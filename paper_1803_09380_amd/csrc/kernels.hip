@@ -88,17 +88,16 @@ __device__ __forceinline__ void bgk(T h[9], T rho_base, T omega, uint32_t& bad) 
     const T S = ((h[0] + h[1]) + (h[2] + h[3])) + ((h[4] + h[5]) + (h[6] + h[7])) + h[8];
     const T jx = (h[1] + h[5] + h[8]) - (h[3] + h[6] + h[7]);
     const T jy = (h[2] + h[5] + h[6]) - (h[4] + h[7] + h[8]);
-    const double Sd = S, jxd = jx, jyd = jy;
-    const double rho = double(rho_base) + Sd;
-    if (!(rho > 0.0) || !isfinite(jxd + jyd)) bad = 1u;
-    const double inv = 1.0 / rho;
-    const double ux = jxd * inv, uy = jyd * inv;
-    const double ju = 1.5 * (jxd * ux + jyd * uy);
+    const T rho = rho_base + S;
+    if (!(rho > T(0)) || !isfinite(jx + jy)) bad = 1u;
+    const T inv = T(1) / rho;
+    const T ux = jx * inv, uy = jy * inv;
+    const double ju = 1.5 * (double(jx) * double(ux) + double(jy) * double(uy));
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
-        const double ej = double(ex_of(i)) * jxd + double(ey_of(i)) * jyd;
-        const double eu = double(ex_of(i)) * ux + double(ey_of(i)) * uy;
-        const T heq = T(weight_of<double>(i) * (Sd + 3.0 * ej + 4.5 * ej * eu - ju));
+        const double ej = double(ex_of(i)) * double(jx) + double(ey_of(i)) * double(jy);
+        const double eu = double(ex_of(i)) * double(ux) + double(ey_of(i)) * double(uy);
+        const T heq = T(weight_of<double>(i) * (double(S) + 3.0 * ej + 4.5 * ej * eu - ju));
         h[i] = h[i] + omega * (heq - h[i]);
     }
 }
@@ -124,8 +123,9 @@ __host__ __device__ constexpr int mrt_norm2(int k) {
     return k == 0 ? 9 : k == 1 || k == 2 ? 36 : k == 3 || k == 5 ? 6 : k == 4 || k == 6 ? 12 : 4;
 }
 
-// As bgk(): the moments of h and their equilibria (and so m - m^eq) in FP64,
-// the relaxation back to the populations and the storage in T.
+// As bgk(): each moment of h and its equilibrium (and so m - m^eq) in FP64,
+// one moment at a time; the relaxation back to the populations and the
+// storage in T.
 template <typename T>
 __device__ __forceinline__ void mrt(T h[9], T rho_base, const T rate[9], uint32_t& bad) {
     const T S = ((h[0] + h[1]) + (h[2] + h[3])) + ((h[4] + h[5]) + (h[6] + h[7])) + h[8];
@@ -135,26 +135,27 @@ __device__ __forceinline__ void mrt(T h[9], T rho_base, const T rate[9], uint32_
     const double rho = double(rho_base) + Sd;
     if (!(rho > 0.0) || !isfinite(jxd + jyd)) bad = 1u;
     const double inv = 1.0 / rho;
-    const double jj = (jxd * jxd + jyd * jyd) * inv;
-    // equilibrium moments of h (Eq. 3 in moment space)
-    double meq[9];
-    meq[0] = Sd;
-    meq[1] = -2.0 * Sd + 3.0 * jj;
-    meq[2] = Sd - 3.0 * jj;
-    meq[3] = jxd;
-    meq[4] = -jxd;
-    meq[5] = jyd;
-    meq[6] = -jyd;
-    meq[7] = (jxd * jxd - jyd * jyd) * inv;
-    meq[8] = jxd * jyd * inv;
     T d[9];
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
+        if (k == 0 || k == 3 || k == 5) {  // conserved moments do not relax
+            d[k] = T(0);
+            continue;
+        }
         double m = 0.0;
 #pragma unroll
         for (int i = 0; i < 9; ++i)
             if (mrt_row(k, i) != 0) m += double(mrt_row(k, i)) * double(h[i]);
-        d[k] = (k == 0 || k == 3 || k == 5) ? T(0) : T(double(rate[k]) * (m - meq[k]) / double(mrt_norm2(k)));
+        // equilibrium moments of h (Eq. 3 in moment space)
+        const double jj = (jxd * jxd + jyd * jyd) * inv;
+        const double meq = k == 1   ? -2.0 * Sd + 3.0 * jj
+                           : k == 2 ? Sd - 3.0 * jj
+                           : k == 4 ? -jxd
+                           : k == 6 ? -jyd
+                           : k == 7 ? (jxd * jxd - jyd * jyd) * inv
+                                    : jxd * jyd * inv;
+        d[k] = T(double(rate[k]) * (m - meq) / double(mrt_norm2(k)));
+        __builtin_amdgcn_sched_barrier(0);
     }
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
@@ -174,13 +175,59 @@ __device__ __forceinline__ void mrt(T h[9], T rho_base, const T rate[9], uint32_
 // wait on memory, and the latency-bound kernels would otherwise queue behind them.
 __device__ __forceinline__ void raise_wave_priority() { __builtin_amdgcn_s_setprio(2); }
 
+// Wall (half-way bounce-back, Fig. 2) and free-slip (specular) rules for the
+// post-collision populations h that node (x, y) sends out of the lattice,
+// written where the next sweep reads the populations they become: the
+// reversed one at the same node, or the mirrored one at (x + e_x, y).  No
+// other thread reads or writes those slots during the sweep (their source
+// lies outside the lattice), so the sweep applies them itself.  A population
+// leaving through a west/east side follows that side's rule (corners
+// included); the inlet and outlet rules of those sides are left to
+// k_boundary.  In AA terms, after a natural sweep (sw = 0) the reversed
+// population lives in slot k of the ghost cell x + e_k and the mirrored one in
+// slot opp(mirror(k)) of (x, y + e_y); after a swapped sweep, in slot opp(k)
+// of the node itself and in slot mirror(k) of (x + e_x, y).  R0, Rs, Rn are
+// rows y, y - 1, y + 1 and c0, cl, cr the offsets of x, x - 1, x + 1 (wrapped
+// on periodic axes, ghost cells otherwise).
+template <typename T, bool NTMP>
+__device__ __forceinline__ void edge_rules(const SimDev& S, int x, int y, int sw, const T h[9],
+                                           LBM_AS1 T* __restrict__ R0, LBM_AS1 T* __restrict__ Rs,
+                                           LBM_AS1 T* __restrict__ Rn, int c0, int cl, int cr) {
+    constexpr int B = kBlk;
+    const bool wx = !S.px && x == 0, ex = !S.px && x == S.nx - 1;
+    const bool sy = !S.py && y == 0, ny = !S.py && y == S.ny - 1;
+#pragma unroll
+    for (int k = 1; k < 9; ++k) {
+        const bool outx = (ex_of(k) < 0 && wx) || (ex_of(k) > 0 && ex);
+        const bool outy = (ey_of(k) < 0 && sy) || (ey_of(k) > 0 && ny);
+        if (!outx && !outy) continue;
+        const int side = outx ? S.bc[ex_of(k) < 0 ? SIDE_W : SIDE_E] : S.bc[ey_of(k) < 0 ? SIDE_S : SIDE_N];
+        const int cx = ex_of(k) < 0 ? cl : (ex_of(k) > 0 ? cr : c0);
+        LBM_AS1 T* __restrict__ Ry = ey_of(k) < 0 ? Rs : (ey_of(k) > 0 ? Rn : R0);
+        if (side == BC_WALL) {
+            if (!sw)
+                stg<NTMP>(&Ry[cx + k * B], h[k]);
+            else
+                stg<NTMP>(&R0[c0 + opp_of(k) * B], h[k]);
+        } else if (side == BC_FREESLIP) {  // south/north only
+            if (!sw)
+                stg<NTMP>(&Ry[c0 + opp_of(mirror_y(k)) * B], h[k]);
+            else
+                stg<NTMP>(&R0[cx + mirror_y(k) * B], h[k]);
+        }
+    }
+}
+
 // One node of the sweep: collision and streaming of node (x, y) of a
 // simulation whose stored row y = 0 starts at P (rows rs elements apart).
 template <typename T, bool NTMP>
-__device__ __forceinline__ void sweep_node(LBM_AS1 T* __restrict__ P, int64_t rs, int nx, int ny, int px, int py,
-                                           int x, int y, int sw, T rho_base, T omega, bool use_mrt,
+__device__ __forceinline__ void sweep_node(const SimDev& S, LBM_AS1 T* __restrict__ P, int64_t rs, int nx, int ny,
+                                           int px, int py, int x, int y, int sw, T rho_base, T omega, bool use_mrt,
                                            const T rate[9], uint32_t& bad) {
     constexpr int B = kBlk;
+    const int em = S.edges;
+    const bool edge = em != 0 && (((em & 1) && x == 0) || ((em & 2) && x == nx - 1) || ((em & 4) && y == 0) ||
+                                  ((em & 8) && y == ny - 1));
     const int c0 = col_off(x);
     LBM_AS1 T* __restrict__ R0 = P + (int64_t)y * rs;
     T h[9];
@@ -194,6 +241,11 @@ __device__ __forceinline__ void sweep_node(LBM_AS1 T* __restrict__ P, int64_t rs
             bgk<T>(h, rho_base, omega, bad);
 #pragma unroll
         for (int i = 0; i < 9; ++i) stg<NTMP>(&R0[c0 + opp_of(i) * B], h[i]);
+        if (edge) {
+            LBM_AS1 T* __restrict__ Rs = P + (int64_t)wrap(y - 1, ny, py) * rs;
+            LBM_AS1 T* __restrict__ Rn = P + (int64_t)wrap(y + 1, ny, py) * rs;
+            edge_rules<T, NTMP>(S, x, y, 0, h, R0, Rs, Rn, c0, col_off(wrap(x - 1, nx, px)), col_off(wrap(x + 1, nx, px)));
+        }
         return;
     }
     // swapped state: f_i(x) = slot opp(i) of x - e_i; element offsets of
@@ -227,7 +279,11 @@ __device__ __forceinline__ void sweep_node(LBM_AS1 T* __restrict__ P, int64_t rs
     stg<NTMP>(&Rp[cm + 6 * B], h[6]);
     stg<NTMP>(&Rm[cm + 7 * B], h[7]);
     stg<NTMP>(&Rm[cp + 8 * B], h[8]);
+    if (edge) edge_rules<T, NTMP>(S, x, y, 1, h, R0, Rm, Rp, c0, cm, cp);
 }
+
+template <typename T, bool MRT>
+constexpr int kSweepMinWaves = MRT ? 1 : (sizeof(T) == 4 ? 7 : 6);
 
 // Tile range of workgroup blockIdx.x: with a batch header and a grid that is a
 // multiple of 8, the tiles dealt to its XCD (part 0 or 1: the first or second
@@ -254,10 +310,15 @@ __device__ __forceinline__ void tile_range(const BatchHeader* hdr, int ntiles_ar
 }
 
 // At most seven waves per SIMD: the sweep streams at a higher rate than with
-// eight (measured), and each SIMD keeps a wave slot for the other kernels.
+// eight (measured), and each SIMD keeps a wave slot for the other kernels.  At
+// least seven (FP32) or six (FP64) for BGK only: register budgets of 72 and
+// 80, which its code fits without spilling, and more waves in flight hide
+// more of the memory latency.
+// MRT = false: BGK only (the launch holds no MRT simulation), which leaves out
+// the MRT code and its registers; MRT = true: each simulation's own collision.
 // Rectangular tiles: TX x TY threads, RPT rows per thread, tile (sim, x0, y0).
-template <typename T, int TX, int TY, int RPT, bool NTMP>
-__global__ void __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(1, 7)))
+template <typename T, int TX, int TY, int RPT, bool NTMP, bool MRT>
+__global__ void __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(kSweepMinWaves<T, MRT>, 7)))
     k_sweep(const SimDev* __restrict__ sims, const int4* __restrict__ tiles,
             const BatchHeader* __restrict__ hdr, int ntiles_arg, int parity, int part) {
     int t0, t1, dt;
@@ -269,7 +330,7 @@ __global__ void __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(1, 
         const int sw = parity >= 0 ? parity : S.swapped;
         LBM_AS1 T* __restrict__ P = gptr(reinterpret_cast<T*>(S.pop)) + S.rstride;  // stored row of y = 0
         const T rho_base = T(S.rho_base), omega = T(S.omega);
-        const bool use_mrt = S.collision != 0;
+        const bool use_mrt = MRT && S.collision != 0;
         T rate[9];
 #pragma unroll
         for (int k = 0; k < 9; ++k) rate[k] = T(S.mrt_s[k]);
@@ -280,8 +341,8 @@ __global__ void __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(1, 
             for (int r = 0; r < RPT; ++r) {
                 const int y = tile.z + threadIdx.y * RPT + r;
                 if (y >= S.ny) break;
-                sweep_node<T, NTMP>(P, S.rstride, S.nx, S.ny, S.px, S.py, x, y, sw, rho_base, omega, use_mrt, rate,
-                                    bad);
+                sweep_node<T, NTMP>(S, P, S.rstride, S.nx, S.ny, S.px, S.py, x, y, sw, rho_base, omega, use_mrt,
+                                    rate, bad);
             }
         }
         if (bad) atomicOr(S.status, ST_UNSTABLE);
@@ -294,8 +355,8 @@ __global__ void __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(1, 
 // kBlk (k % nbx) ..), round r giving wave w block k0 + r W + w.  Short rows
 // then leave no whole waves idle, and a workgroup's blocks are adjacent in
 // memory.
-template <typename T, int W, int R, bool NTMP>
-__global__ void __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(1, 7)))
+template <typename T, int W, int R, bool NTMP, bool MRT>
+__global__ void __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(kSweepMinWaves<T, MRT>, 7)))
     k_sweep_blk(const SimDev* __restrict__ sims, const int4* __restrict__ tiles,
                 const BatchHeader* __restrict__ hdr, int ntiles_arg, int parity, int part) {
     int t0, t1, dt;
@@ -309,7 +370,7 @@ __global__ void __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(1, 
         const int sw = parity >= 0 ? parity : S.swapped;
         LBM_AS1 T* __restrict__ P = gptr(reinterpret_cast<T*>(S.pop)) + S.rstride;
         const T rho_base = T(S.rho_base), omega = T(S.omega);
-        const bool use_mrt = S.collision != 0;
+        const bool use_mrt = MRT && S.collision != 0;
         T rate[9];
 #pragma unroll
         for (int k = 0; k < 9; ++k) rate[k] = T(S.mrt_s[k]);
@@ -322,8 +383,8 @@ __global__ void __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(1, 
             const int y = k / nbx;
             const int x = (k - y * nbx) * kBlk + lane;
             if (x < S.nx)
-                sweep_node<T, NTMP>(P, S.rstride, S.nx, S.ny, S.px, S.py, x, y, sw, rho_base, omega, use_mrt, rate,
-                                    bad);
+                sweep_node<T, NTMP>(S, P, S.rstride, S.nx, S.ny, S.px, S.py, x, y, sw, rho_base, omega, use_mrt,
+                                    rate, bad);
         }
         if (bad) atomicOr(S.status, ST_UNSTABLE);
     }
@@ -331,30 +392,28 @@ __global__ void __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(1, 
 
 // ---------------------------------------------------------------- boundary rules
 
-// Perimeter node k of a simulation: south row, north row, then the west and
-// east columns without the corners already counted.
+// Perimeter node k of a prescribed-velocity box: south row, north row, then
+// the west and east columns without the corners already counted (the order of
+// lbm_set_boundary_velocity).
 __device__ __forceinline__ void perim_node(const SimDev& S, int k, int& x, int& y) {
     const int nx = S.nx, ny = S.ny;
-    if (!S.py) {
-        if (k < nx) {
-            x = k;
-            y = 0;
-            return;
-        }
-        if (k < 2 * nx) {
-            x = k - nx;
-            y = ny - 1;
-            return;
-        }
-        k -= 2 * nx;
+    if (k < nx) {
+        x = k;
+        y = 0;
+        return;
     }
-    const int ys = S.py ? 0 : 1, ncol = S.py ? ny : ny - 2;
-    if (k < ncol) {
+    if (k < 2 * nx) {
+        x = k - nx;
+        y = ny - 1;
+        return;
+    }
+    k -= 2 * nx;
+    if (k < ny - 2) {
         x = 0;
-        y = ys + k;
+        y = 1 + k;
     } else {
         x = nx - 1;
-        y = ys + k - ncol;
+        y = 1 + k - (ny - 2);
     }
 }
 
@@ -392,10 +451,10 @@ __global__ void __launch_bounds__(256)
         const int k = item.y + threadIdx.x;
         if (k >= S.nperim) continue;
         const int sw = 1 - (parity >= 0 ? parity : S.swapped);  // state after this step's sweep
-        int x, y;
-        perim_node(S, k, x, y);
         const int nx = S.nx, ny = S.ny;
+        int x, y;
         if (S.bc[SIDE_W] == BC_DIRICHLET) {
+            perim_node(S, k, x, y);
             // prescribed velocity: non-equilibrium extrapolation from the inward
             // neighbour (diagonal at corners), which is interior on both axes
             const int xn = x < 1 ? 1 : (x > nx - 2 ? nx - 2 : x);
@@ -415,7 +474,11 @@ __global__ void __launch_bounds__(256)
             }
             continue;
         }
-        if (x == 0 && S.bc[SIDE_W] == BC_VELOCITY) {
+        // inlet column (west) first, then the outlet column (east)
+        const bool inlet = S.bc[SIDE_W] == BC_VELOCITY;
+        x = inlet && k < ny ? 0 : nx - 1;
+        y = inlet && k >= ny ? k - ny : k;
+        if (x == 0) {
             // non-equilibrium extrapolation from column 1 (every population)
             T f1[9];
 #pragma unroll
@@ -432,7 +495,7 @@ __global__ void __launch_bounds__(256)
             }
             continue;
         }
-        if (x == nx - 1 && S.bc[SIDE_E] == BC_PRESSURE) {
+        if (S.bc[SIDE_E] == BC_PRESSURE) {
             // non-equilibrium extrapolation from column nx-2 at density rho0
             T f2[9];
 #pragma unroll
@@ -450,27 +513,11 @@ __global__ void __launch_bounds__(256)
             }
             continue;
         }
+        // zero-gradient outlet: the populations entering from the east copy the
+        // post-stream values of column nx-2
 #pragma unroll
-        for (int i = 1; i < 9; ++i) {
-            const int sx = wrap(x - ex_of(i), nx, S.px), sy = wrap(y - ey_of(i), ny, S.py);
-            const bool outx = sx < 0 || sx >= nx, outy = sy < 0 || sy >= ny;
-            if (!outx && !outy) continue;
-            T v;
-            if (outx) {
-                const int side = sx < 0 ? S.bc[SIDE_W] : S.bc[SIDE_E];
-                if (side == BC_WALL)
-                    v = ldm<false>(pc<T>(S, opp_of(i), x, y, sw));
-                else  // zero-gradient outlet (east, e_x = -1)
-                    v = post_stream<T>(S, i, nx - 2, y, sw);
-            } else {
-                const int side = sy < 0 ? S.bc[SIDE_S] : S.bc[SIDE_N];
-                if (side == BC_WALL)
-                    v = ldm<false>(pc<T>(S, opp_of(i), x, y, sw));
-                else  // specular reflection
-                    v = ldm<false>(pc<T>(S, mirror_y(i), wrap(x - ex_of(i), nx, S.px), y, sw));
-            }
-            stm<false>(loc<T>(S, i, x, y, sw), v);
-        }
+        for (int i = 1; i < 9; ++i)
+            if (ex_of(i) < 0) stm<false>(loc<T>(S, i, nx - 1, y, sw), post_stream<T>(S, i, nx - 2, y, sw));
     }
 }
 
@@ -1021,6 +1068,11 @@ __device__ __forceinline__ void spread_node(const Band<T> B, const T* w, int str
 #ifdef LBMIB_TRACE_IB
 // phase timestamps (100 MHz wall clock) of the first group, for profiling builds only
 __device__ long long lbmib_ib_trace[64];
+}  // namespace lbmib
+extern "C" int lbm_debug_ib_trace(long long* out) {
+    return hipMemcpyFromSymbol(out, HIP_SYMBOL(lbmib::lbmib_ib_trace), sizeof(long long) * 64) == hipSuccess ? 0 : 3;
+}
+namespace lbmib {
 #define IB_MARK(k)                                  \
     do {                                            \
         if (gi == 0 && tid == 0) {                  \
@@ -1847,55 +1899,58 @@ __global__ void k_set_eq(const SimDev* sim, int sw, const double* rho, const dou
 
 // ---------------------------------------------------------------- launchers
 
-template <typename T, int TX, int TY, int RPT, bool NTMP>
+template <typename T, bool MRT, int TX, int TY, int RPT, bool NTMP>
 static hipError_t sweep_t(const SimDev* sims, const int4* tiles, const BatchHeader* hdr, int ntiles, int grid,
                           int parity, int part, hipStream_t st) {
-    hipLaunchKernelGGL((k_sweep<T, TX, TY, RPT, NTMP>), dim3(grid), dim3(TX, TY), 0, st, sims, tiles, hdr, ntiles,
+    hipLaunchKernelGGL((k_sweep<T, TX, TY, RPT, NTMP, MRT>), dim3(grid), dim3(TX, TY), 0, st, sims, tiles, hdr, ntiles,
                        parity, part);
     return hipGetLastError();
 }
 
-template <typename T, int W, int R, bool NTMP>
+template <typename T, bool MRT, int W, int R, bool NTMP>
 static hipError_t sweep_b(const SimDev* sims, const int4* tiles, const BatchHeader* hdr, int ntiles, int grid,
                           int parity, int part, hipStream_t st) {
-    hipLaunchKernelGGL((k_sweep_blk<T, W, R, NTMP>), dim3(grid), dim3(64 * W), 0, st, sims, tiles, hdr, ntiles,
+    hipLaunchKernelGGL((k_sweep_blk<T, W, R, NTMP, MRT>), dim3(grid), dim3(64 * W), 0, st, sims, tiles, hdr, ntiles,
                        parity, part);
     return hipGetLastError();
 }
 
-template <typename T>
+template <typename T, bool MRT>
 static hipError_t sweep_tt(int tiling, const SimDev* sims, const int4* tiles, const BatchHeader* hdr, int ntiles,
                            int grid, int parity, int part, hipStream_t st) {
     switch (tiling) {
-        case 16: return sweep_b<T, 4, 1, true>(sims, tiles, hdr, ntiles, grid, parity, part, st);
-        case 17: return sweep_b<T, 4, 2, true>(sims, tiles, hdr, ntiles, grid, parity, part, st);
-        case 18: return sweep_b<T, 8, 1, true>(sims, tiles, hdr, ntiles, grid, parity, part, st);
-        case 19: return sweep_b<T, 4, 1, false>(sims, tiles, hdr, ntiles, grid, parity, part, st);
-        case 0: return sweep_t<T, 64, 4, 1, false>(sims, tiles, hdr, ntiles, grid, parity, part, st);
-        case 1: return sweep_t<T, 64, 4, 2, false>(sims, tiles, hdr, ntiles, grid, parity, part, st);
-        case 2: return sweep_t<T, 128, 2, 2, false>(sims, tiles, hdr, ntiles, grid, parity, part, st);
-        case 3: return sweep_t<T, 256, 1, 2, false>(sims, tiles, hdr, ntiles, grid, parity, part, st);
-        case 4: return sweep_t<T, 256, 1, 4, false>(sims, tiles, hdr, ntiles, grid, parity, part, st);
-        case 5: return sweep_t<T, 64, 4, 4, false>(sims, tiles, hdr, ntiles, grid, parity, part, st);
-        case 6: return sweep_t<T, 256, 1, 1, false>(sims, tiles, hdr, ntiles, grid, parity, part, st);
-        case 7: return sweep_t<T, 128, 2, 1, false>(sims, tiles, hdr, ntiles, grid, parity, part, st);
-        case 8: return sweep_t<T, 64, 4, 1, true>(sims, tiles, hdr, ntiles, grid, parity, part, st);
-        case 9: return sweep_t<T, 64, 4, 2, true>(sims, tiles, hdr, ntiles, grid, parity, part, st);
-        case 10: return sweep_t<T, 128, 2, 2, true>(sims, tiles, hdr, ntiles, grid, parity, part, st);
-        case 11: return sweep_t<T, 256, 1, 2, true>(sims, tiles, hdr, ntiles, grid, parity, part, st);
-        case 12: return sweep_t<T, 256, 1, 4, true>(sims, tiles, hdr, ntiles, grid, parity, part, st);
-        case 13: return sweep_t<T, 64, 4, 4, true>(sims, tiles, hdr, ntiles, grid, parity, part, st);
-        case 14: return sweep_t<T, 256, 1, 1, true>(sims, tiles, hdr, ntiles, grid, parity, part, st);
-        case 15: return sweep_t<T, 128, 2, 1, true>(sims, tiles, hdr, ntiles, grid, parity, part, st);
+        case 16: return sweep_b<T, MRT, 4, 1, true>(sims, tiles, hdr, ntiles, grid, parity, part, st);
+        case 17: return sweep_b<T, MRT, 4, 2, true>(sims, tiles, hdr, ntiles, grid, parity, part, st);
+        case 18: return sweep_b<T, MRT, 8, 1, true>(sims, tiles, hdr, ntiles, grid, parity, part, st);
+        case 19: return sweep_b<T, MRT, 4, 1, false>(sims, tiles, hdr, ntiles, grid, parity, part, st);
+        case 0: return sweep_t<T, MRT, 64, 4, 1, false>(sims, tiles, hdr, ntiles, grid, parity, part, st);
+        case 1: return sweep_t<T, MRT, 64, 4, 2, false>(sims, tiles, hdr, ntiles, grid, parity, part, st);
+        case 2: return sweep_t<T, MRT, 128, 2, 2, false>(sims, tiles, hdr, ntiles, grid, parity, part, st);
+        case 3: return sweep_t<T, MRT, 256, 1, 2, false>(sims, tiles, hdr, ntiles, grid, parity, part, st);
+        case 4: return sweep_t<T, MRT, 256, 1, 4, false>(sims, tiles, hdr, ntiles, grid, parity, part, st);
+        case 5: return sweep_t<T, MRT, 64, 4, 4, false>(sims, tiles, hdr, ntiles, grid, parity, part, st);
+        case 6: return sweep_t<T, MRT, 256, 1, 1, false>(sims, tiles, hdr, ntiles, grid, parity, part, st);
+        case 7: return sweep_t<T, MRT, 128, 2, 1, false>(sims, tiles, hdr, ntiles, grid, parity, part, st);
+        case 8: return sweep_t<T, MRT, 64, 4, 1, true>(sims, tiles, hdr, ntiles, grid, parity, part, st);
+        case 9: return sweep_t<T, MRT, 64, 4, 2, true>(sims, tiles, hdr, ntiles, grid, parity, part, st);
+        case 10: return sweep_t<T, MRT, 128, 2, 2, true>(sims, tiles, hdr, ntiles, grid, parity, part, st);
+        case 11: return sweep_t<T, MRT, 256, 1, 2, true>(sims, tiles, hdr, ntiles, grid, parity, part, st);
+        case 12: return sweep_t<T, MRT, 256, 1, 4, true>(sims, tiles, hdr, ntiles, grid, parity, part, st);
+        case 13: return sweep_t<T, MRT, 64, 4, 4, true>(sims, tiles, hdr, ntiles, grid, parity, part, st);
+        case 14: return sweep_t<T, MRT, 256, 1, 1, true>(sims, tiles, hdr, ntiles, grid, parity, part, st);
+        case 15: return sweep_t<T, MRT, 128, 2, 1, true>(sims, tiles, hdr, ntiles, grid, parity, part, st);
         default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_sweep(bool f64, int tiling, const SimDev* sims, const int4* tiles, const BatchHeader* hdr,
+hipError_t launch_sweep(bool f64, bool mrt, int tiling, const SimDev* sims, const int4* tiles, const BatchHeader* hdr,
                         int ntiles, int grid, int parity, hipStream_t stream, int part) {
     if (grid <= 0) return hipSuccess;
-    return f64 ? sweep_tt<double>(tiling, sims, tiles, hdr, ntiles, grid, parity, part, stream)
-               : sweep_tt<float>(tiling, sims, tiles, hdr, ntiles, grid, parity, part, stream);
+    if (mrt)
+        return f64 ? sweep_tt<double, true>(tiling, sims, tiles, hdr, ntiles, grid, parity, part, stream)
+                   : sweep_tt<float, true>(tiling, sims, tiles, hdr, ntiles, grid, parity, part, stream);
+    return f64 ? sweep_tt<double, false>(tiling, sims, tiles, hdr, ntiles, grid, parity, part, stream)
+               : sweep_tt<float, false>(tiling, sims, tiles, hdr, ntiles, grid, parity, part, stream);
 }
 
 hipError_t launch_boundary(bool f64, const SimDev* sims, const int2* items, const BatchHeader* hdr, int nitems,

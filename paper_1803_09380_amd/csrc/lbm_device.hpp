@@ -80,7 +80,8 @@ struct BodyDev {
 struct SimDev {
     void* pop;           // T* base of the stored rows
     int64_t rstride;     // elements per stored row (nblk * 9 * kBlk)
-    int32_t nblk, pad0_; // blocks per stored row
+    int32_t nblk;        // blocks per stored row
+    int32_t edges;       // bit per side (W, E, S, N) whose wall or free-slip rule the sweep applies
     int32_t nx, ny;
     int32_t bc[4];       // W, E, S, N
     int32_t px, py;      // periodic axes
@@ -98,7 +99,8 @@ struct SimDev {
     int64_t steps_left;  // batch: < 0 means unlimited
     int64_t steps_done;
     uint32_t* status;    // sticky status bits
-    int32_t nperim;      // boundary nodes that need a rule each step
+    int32_t nperim;      // boundary nodes the boundary kernel rebuilds each step (inlet and
+                         // outlet columns, or the perimeter of a prescribed-velocity box)
     int32_t nbody;
     int32_t ib_iters;    // correction sweeps per step
     int32_t pad_;

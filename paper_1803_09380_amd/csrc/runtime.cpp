@@ -116,6 +116,7 @@ struct Lane {
     int sim0 = 0, nsims = 0, ntiles = 0, nbc = 0, ngroups = 0, nchunks = 0;
     int max_group = 0;
     int grid_sweep = 0, grid_band = 0;
+    bool mrt = false;  // some simulation of the lane uses the MRT collision
     hipGraphExec_t graph1 = nullptr, graphK = nullptr;
     hipGraphExec_t graphA = nullptr, graphB = nullptr;  // one step split: sweep (two launches), the rest
     bool bnd_apart = false;  // graphB leaves out the boundary rules and the bookkeeping (run_interleaved)
@@ -220,10 +221,15 @@ bool bc_valid(const lbm_params* p) {
     return true;
 }
 
-int perimeter_count(const SimDev& h) {
+// Boundary nodes the boundary kernel rebuilds every step: the whole perimeter
+// of a prescribed-velocity box (2 nx + 2 (ny - 2) nodes, in the order of
+// lbm_set_boundary_velocity), else the inlet column and the outlet column.
+// Walls and free-slip sides need no kernel: the sweep applies their rules.
+int boundary_count(const SimDev& h) {
+    if (h.bc[SIDE_W] == BC_DIRICHLET) return 2 * h.nx + 2 * (h.ny - 2);
     int n = 0;
-    if (!h.py) n += 2 * h.nx;
-    if (!h.px) n += 2 * (h.py ? h.ny : h.ny - 2);
+    if (h.bc[SIDE_W] == BC_VELOCITY) n += h.ny;
+    if (h.bc[SIDE_E] == BC_OUTFLOW || h.bc[SIDE_E] == BC_PRESSURE) n += h.ny;
     return n;
 }
 
@@ -634,7 +640,9 @@ lbm_status lbm_create(const lbm_params* p, void* hip_stream, lbm_sim** out) {
     h.active = 1;
     h.steps_left = -1;
     h.ib_iters = p->ib_iters;
-    h.nperim = perimeter_count(h);
+    h.nperim = boundary_count(h);
+    for (int side = 0; side < 4; ++side)
+        if (h.bc[side] == BC_WALL || h.bc[side] == BC_FREESLIP) h.edges |= 1 << side;
     lbm_status rc = LBM_OK;
     auto bail = [&](lbm_status e) {
         lbm_destroy(s);
@@ -790,7 +798,7 @@ lbm_status lbm_step(lbm_sim* s, int32_t nsteps) {
     const int2* ch = (const int2*)s->chunks.p;
     for (int t = 0; t < nsteps; ++t) {
         const int parity = s->h.swapped;
-        HIPS(s, launch_sweep(s->f64, s->tiling, d, (const int4*)s->tiles.p, nullptr, ntiles, ntiles, parity, s->stream));
+        HIPS(s, launch_sweep(s->f64, s->h.collision != 0, s->tiling, d, (const int4*)s->tiles.p, nullptr, ntiles, ntiles, parity, s->stream));
         if (nbc) HIPS(s, launch_boundary(s->f64, d, (const int2*)s->bcitems.p, nullptr, nbc, nbc, parity, s->stream));
         if (ng) {
             HIPS(s, launch_band(s->f64, false, d, gdev, ch, nullptr, nch, nch, parity, s->stream));
@@ -1097,6 +1105,10 @@ lbm_status upload_tables(lbm_batch* b) {
         const int max_group = groups.empty() ? 0 : groups.front().M;
         bool changed = ib_variant(b->f64, max_group) != ib_variant(b->f64, L.max_group);
         L.max_group = max_group;
+        bool mrt = false;
+        for (int r = r0; r < r1; ++r) mrt = mrt || b->sims[b->order[r]]->h.collision != 0;
+        changed = changed || mrt != L.mrt;
+        L.mrt = mrt;
         BatchHeader h{};
         h.nsims = r1 - r0;
         h.nbc = (int)bc.size();
@@ -1160,7 +1172,7 @@ hipError_t launch_kind(lbm_batch* b, int l, int k, hipStream_t st) {
     SimDev* sims = (SimDev*)b->d_sims.p;
     const BatchHeader* hdr = (const BatchHeader*)L.d_hdr.p;
     switch (k) {
-        case 0: return launch_sweep(b->f64, b->tiling, sims, (const int4*)L.d_tiles.p, hdr, 0, L.grid_sweep, -1, st);
+        case 0: return launch_sweep(b->f64, L.mrt, b->tiling, sims, (const int4*)L.d_tiles.p, hdr, 0, L.grid_sweep, -1, st);
         case 1: return launch_boundary(b->f64, sims, (const int2*)L.d_bc.p, hdr, 0, b->grid_bc, -1, st);
         case 2:
             return launch_band(b->f64, false, sims, (const GroupDev*)L.d_groups.p, (const int2*)L.d_chunks.p, hdr, 0,
@@ -1229,8 +1241,8 @@ lbm_status run_interleaved(lbm_batch* b, int n) {
         const BatchHeader* hdr = (const BatchHeader*)Lt.d_hdr.p;
         const int4* tiles = (const int4*)Lt.d_tiles.p;
         HIPB(b, capture_fn(st1, [&]() {
-            hipError_t e = launch_sweep(b->f64, b->tiling, sims, tiles, hdr, 0, half, -1, st1, 0);
-            return e != hipSuccess ? e : launch_sweep(b->f64, b->tiling, sims, tiles, hdr, 0, half, -1, st1, 1);
+            hipError_t e = launch_sweep(b->f64, Lt.mrt, b->tiling, sims, tiles, hdr, 0, half, -1, st1, 0);
+            return e != hipSuccess ? e : launch_sweep(b->f64, Lt.mrt, b->tiling, sims, tiles, hdr, 0, half, -1, st1, 1);
         }, &Lt.graphA));
     }
     if (!Lt.graphB) {
@@ -1555,18 +1567,5 @@ lbm_status lbm_batch_profile(lbm_batch* b, int32_t nsteps, double ms[4], int64_t
     return LBM_OK;
 }
 
-#ifdef LBMIB_TRACE_IB
-}  // extern "C"
-namespace lbmib {
-extern __device__ long long lbmib_ib_trace[64];
-}
-extern "C" {
-// profiling builds only: phase timestamps of the first body group's last step
-lbm_status lbm_debug_ib_trace(long long* out) {
-    return hipMemcpyFromSymbol(out, HIP_SYMBOL(lbmib::lbmib_ib_trace), sizeof(long long) * 64) == hipSuccess
-               ? LBM_OK
-               : LBM_ERR_DEVICE;
-}
-#endif
 
 }  // extern "C"
