@@ -1150,6 +1150,27 @@ __device__ __forceinline__ void marker_outputs(const SimDev& S, const GroupDev& 
     for (int c = 0; c < 5; ++c) stm<false>(reinterpret_cast<T*>(G.m_wtot) + g * 5 + c, T(ds * (double)acc[c]));
 }
 
+// Eq. 28 at node (x, y): the populations corrected by the spread totals t
+// (ds-weighted sums of dm_x, dm_y, dPi_xx, dPi_xy, dPi_yy), in place.
+template <typename T>
+__device__ __forceinline__ void correct_node(const SimDev& S, int x, int y, int sw, const T t[5]) {
+    LBM_AS1 T* p[9];
+    T f[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        p[i] = gptr(loc<T>(S, i, x, y, sw));
+        f[i] = *p[i];
+    }
+    const T trB = T(1.5) * (t[2] + t[4]);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        const T ex = T(ex_of(i)), ey = T(ey_of(i));
+        const T d = weight_of<T>(i) *
+                    (T(3) * (ex * t[0] + ey * t[1]) + T(4.5) * (ex * ex * t[2] + T(2) * ex * ey * t[3] + ey * ey * t[4]) - trB);
+        *p[i] = f[i] + d;
+    }
+}
+
 // Steps 2-5 of a group's correction (gather, N sweeps on (rho, j), per-marker
 // totals of the sweeps) for one placement of its working arrays.  Groups with
 // fixed plans have their band records gathered beforehand (k_band_gather);
@@ -1526,6 +1547,281 @@ __device__ __forceinline__ void correct_group_col(const SimDev& S, const GroupDe
     IB_MARK(24);
 }
 
+// Correction of a group of free bodies planned, swept and applied inside the
+// workgroup, for groups whose stencils lie in one box of kBinCells nodes or
+// fewer inside the lattice (no wrap across a periodic side, no node outside):
+// the box's cells are counted, scanned and filled as in build_plan_binned, but
+// the plan (band nodes in ascending cell order, each node's entries in
+// ascending marker order, the band node of every stencil row) stays in LDS,
+// the weights of Eq. 15 are computed into LDS, and the final spread and Eq. 28
+// correction of the populations follow the sweeps in the same workgroup.  The
+// arithmetic and its order are those of correct_group and k_band_apply on the
+// same plan.  Returns false, having written nothing to device memory, when the
+// group does not qualify or its arrays do not fit the arena.
+template <typename T, int NT, int MPT>
+__device__ bool correct_free_lds(const SimDev& S, const GroupDev& G, const GroupLookup& L, char* arena, int* scan_tmp,
+                                 int* bbox, int sw, int gi) {
+    const int tid = threadIdx.x;
+    const int M = G.M, NE = 16 * M;
+    if (M == 0 || M > MPT * NT || NE > 0xFFFF) return false;
+    Bump bp;
+    bp.base = arena;
+    bp.off = 0;
+    int* mfx = reinterpret_cast<int*>(bp.take(4L * M));
+    int* mfy = reinterpret_cast<int*>(bp.take(4L * M));
+    T* phi = reinterpret_cast<T*>(bp.take(8L * M * sizeof(T)));
+    T* wt = reinterpret_cast<T*>(bp.take(2L * M * sizeof(T)));
+    T* tot = reinterpret_cast<T*>(bp.take(5L * M * sizeof(T)));
+    unsigned short* rows = reinterpret_cast<unsigned short*>(bp.take(2L * 4 * M));
+    unsigned short* ents = reinterpret_cast<unsigned short*>(bp.take(2L * NE));
+    if (!mfx || !mfy || !phi || !wt || !tot || !rows || !ents) return false;
+    // stencil corners and the weights of Eq. 15 (the same expressions as the
+    // weights of a plan in device memory); the box of the stencils by a
+    // reduction in each wave and one LDS atomic per wave
+    if (tid < 4) bbox[tid] = tid < 2 ? 0x7fffffff : -0x7fffffff;
+    __syncthreads();
+    int lx = 0x7fffffff, ly = 0x7fffffff, hx = -0x7fffffff, hy = -0x7fffffff;
+    for (int g = tid; g < M; g += NT) {
+        int body;
+        const int mi = lookup(L, g, body);
+        const double X = S.mX[mi], Y = S.mY[mi];
+        const double fxd = floor(X) - 1.0, fyd = floor(Y) - 1.0;
+        const int fx = (int)fxd, fy = (int)fyd;
+        mfx[g] = fx;
+        mfy[g] = fy;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            phi[g * 8 + q] = delta_w<T>(S.delta, T(fxd + q - X));
+            phi[g * 8 + 4 + q] = delta_w<T>(S.delta, T(fyd + q - Y));
+        }
+        lx = min(lx, fx);
+        ly = min(ly, fy);
+        hx = max(hx, fx + 3);
+        hy = max(hy, fy + 3);
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        lx = min(lx, __shfl_xor(lx, off, 64));
+        ly = min(ly, __shfl_xor(ly, off, 64));
+        hx = max(hx, __shfl_xor(hx, off, 64));
+        hy = max(hy, __shfl_xor(hy, off, 64));
+    }
+    if ((tid & 63) == 0 && lx <= hx) {
+        atomicMin(&bbox[0], lx);
+        atomicMin(&bbox[1], ly);
+        atomicMax(&bbox[2], hx);
+        atomicMax(&bbox[3], hy);
+    }
+    __syncthreads();
+    IB_MARK(1);
+    const int x0 = bbox[0], y0 = bbox[1];
+    const long W = (long)bbox[2] - x0 + 1, H = (long)bbox[3] - y0 + 1;
+    const long ncell_l = W * H;
+    // band nodes: at most one per cell and per entry
+    const long nbmax = ncell_l < NE ? ncell_l : NE;
+    unsigned short* run16 = reinterpret_cast<unsigned short*>(bp.take(2L * (nbmax + 1)));
+    int* cells = reinterpret_cast<int*>(bp.take(4L * nbmax));
+    // the counts and fill positions of the plan build share their space with
+    // the band records of the sweeps
+    const long plan_bytes = 8L * ncell_l, rec_bytes = 4L * nbmax * (long)sizeof(T);
+    char* shared = reinterpret_cast<char*>(bp.take(plan_bytes > rec_bytes ? plan_bytes : rec_bytes));
+    if (x0 < 0 || y0 < 0 || bbox[2] >= S.nx || bbox[3] >= S.ny || ncell_l > kBinCells || !run16 || !cells ||
+        !shared)
+        return false;
+    const int ncell = (int)ncell_l, Wi = (int)W;
+    int* count = reinterpret_cast<int*>(shared);  // per box cell: entries, then band node
+    int* start = count + ncell;                   // per box cell: first entry, then fill position
+    for (int c = tid; c < ncell; c += NT) count[c] = 0;
+    __syncthreads();
+    for (int e = tid; e < NE; e += NT) {
+        const int g = e >> 4, sl = e & 15;
+        atomicAdd(&count[(mfy[g] + (sl >> 2) - y0) * Wi + (mfx[g] + (sl & 3) - x0)], 1);
+    }
+    __syncthreads();
+    // one scan of (band nodes << 16 | entries): both totals fit 16 bits
+    const int per = (ncell + NT - 1) / NT;
+    const int c0 = tid * per, c1 = min(ncell, c0 + per);
+    int packed = 0;
+    for (int c = c0; c < c1; ++c) packed += (count[c] > 0 ? 1 << 16 : 0) + count[c];
+    int ptotal;
+    const int pbase = block_scan<NT>(packed, scan_tmp, &ptotal);
+    int ebase = pbase & 0xffff, nbase = pbase >> 16;
+    const int nband = ptotal >> 16;
+    for (int c = c0; c < c1; ++c) {
+        const int n = count[c];
+        start[c] = ebase;
+        if (n > 0) {
+            cells[nbase] = c;
+            run16[nbase] = (unsigned short)ebase;
+            count[c] = nbase;
+            ++nbase;
+        }
+        ebase += n;
+    }
+    if (tid == 0) run16[nband] = (unsigned short)NE;
+    __syncthreads();
+    IB_MARK(30);
+    for (int e = tid; e < NE; e += NT) {
+        const int g = e >> 4, sl = e & 15;
+        const int slot = atomicAdd(&start[(mfy[g] + (sl >> 2) - y0) * Wi + (mfx[g] + (sl & 3) - x0)], 1);
+        ents[slot] = (unsigned short)e;  // e = 16 * marker + (ky << 2 | kx)
+    }
+    // band node of the first cell of each stencil row: its four cells are
+    // consecutive cells of the box, all in the band, so consecutive band nodes
+    for (int i = tid; i < 4 * M; i += NT) {
+        const int g = i >> 2, ky = i & 3;
+        rows[i] = (unsigned short)count[(mfy[g] + ky - y0) * Wi + (mfx[g] - x0)];
+    }
+    __syncthreads();
+    // each run ends at its cell's fill position; order it by marker
+    for (int k = tid; k < nband; k += NT) {
+        const int e0 = run16[k], e1 = run16[k + 1];
+        for (int a = e0 + 1; a < e1; ++a) {
+            const unsigned short v = ents[a];
+            int b = a - 1;
+            while (b >= e0 && ents[b] > v) {
+                ents[b + 1] = ents[b];
+                --b;
+            }
+            ents[b + 1] = v;
+        }
+    }
+    __syncthreads();
+    IB_MARK(2);
+    // band records from the post-stream populations (over the counts, which
+    // are no longer needed), four nodes per thread in flight
+    T* node = reinterpret_cast<T*>(shared);
+    const T rho_base = T(S.rho_base);
+    for (int k0 = tid; k0 < nband; k0 += 4 * NT) {
+        T h[4][9];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int k = k0 + u * NT;
+            if (k < nband) {
+                const int c = cells[k];
+                const int x = x0 + c % Wi, y = y0 + c / Wi;
+#pragma unroll
+                for (int i = 0; i < 9; ++i) h[u][i] = ldm<false>(loc<T>(S, i, x, y, sw));
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int k = k0 + u * NT;
+            if (k < nband) stm<true>(reinterpret_cast<nv4<T>*>(node) + k, band_record<T>(h[u], rho_base));
+        }
+    }
+    Band<T> B;
+    B.node = node;
+    B.wt = wt;
+    B.run16 = run16;
+    B.run32 = nullptr;
+    B.rows = rows;
+    B.mn32 = nullptr;
+    B.phi = phi;
+    B.ent16 = ents;
+    B.entpk = nullptr;
+    T mu[MPT], mv[MPT], mds[MPT];
+    T acc[MPT][5];
+#pragma unroll
+    for (int q = 0; q < MPT; ++q) {
+        const int g = tid + q * NT;
+        mu[q] = mv[q] = mds[q] = T(0);
+        if (g < M) {
+            int body;
+            const int mi = lookup(L, g, body);
+            mu[q] = T(ldm<false>(S.mU + mi));
+            mv[q] = T(ldm<false>(S.mV + mi));
+            mds[q] = T(ldm<false>(S.mds + mi));
+        }
+#pragma unroll
+        for (int c = 0; c < 5; ++c) acc[q][c] = T(0);
+    }
+    __syncthreads();
+    IB_MARK(3);
+    const int iters = S.ib_iters;
+    for (int n = 0; n < iters; ++n) {
+#pragma unroll
+        for (int q = 0; q < MPT; ++q) {
+            const int g = tid + q * NT;
+            if (g < M) {
+                T dmx, dmy, dpxx, dpxy, dpyy, rs;
+                interp_marker<T, true, true>(B, g, mu[q], mv[q], dmx, dmy, dpxx, dpxy, dpyy, rs);
+                acc[q][0] += dmx;
+                acc[q][1] += dmy;
+                acc[q][2] += dpxx;
+                acc[q][3] += dpxy;
+                acc[q][4] += dpyy;
+                stm<true>(wt + 2 * g, mds[q] * dmx);
+                stm<true>(wt + 2 * g + 1, mds[q] * dmy);
+            }
+        }
+        __syncthreads();
+        // Eqs. 26-27 on the momentum: j(x) += sum_l D(x - X_l) ds_l dm_l, ascending l
+        for (int k = tid; k < nband; k += NT) {
+            T inc[2];
+            spread_node<T, true, true, 2>(B, wt, 2, run16[k], run16[k + 1], inc);
+            nv2<T>* jp = reinterpret_cast<nv2<T>*>(node + 4 * k + 2);
+            nv2<T> j = ldm<true>(jp);
+            j.x += inc[0];
+            j.y += inc[1];
+            stm<true>(jp, j);
+        }
+        __syncthreads();
+        IB_MARK(4 + (n < 20 ? n : 19));
+    }
+    // mismatch left after the sweeps, per-marker force and torque (device
+    // memory, for the FP64 reductions) and the totals of the sweeps (LDS)
+#pragma unroll
+    for (int q = 0; q < MPT; ++q) {
+        const int g = tid + q * NT;
+        if (g < M) {
+            T dmx, dmy, dpxx, dpxy, dpyy, rs;
+            interp_marker<T, true, true>(B, g, mu[q], mv[q], dmx, dmy, dpxx, dpxy, dpyy, rs);
+            int body;
+            const int mi = lookup(L, g, body);
+            const double ds = ldm<false>(S.mds + mi);
+            const BodyDev& Bd = S.bodies[body];
+            const double Fx = -ds * (double)acc[q][0], Fy = -ds * (double)acc[q][1];
+            const double r2 = (double)dmx * (double)dmx + (double)dmy * (double)dmy;
+            double* mr = G.m_red + g * 5;
+            mr[0] = Fx;
+            mr[1] = Fy;
+            mr[2] = (S.mX[mi] - Bd.xc[0]) * Fy - (S.mY[mi] - Bd.xc[1]) * Fx;
+            mr[3] = r2;
+            mr[4] = sqrt(r2) / (double)rs;
+#pragma unroll
+            for (int c = 0; c < 5; ++c) stm<true>(tot + g * 5 + c, T(ds * (double)acc[q][c]));
+        }
+    }
+    __syncthreads();
+    IB_MARK(24);
+    // final spread of the totals and Eq. 28 at every band node
+    for (int k = tid; k < nband; k += NT) {
+        T t[5];
+        spread_node<T, true, true, 5>(B, tot, 5, run16[k], run16[k + 1], t);
+        const int c = cells[k];
+        correct_node<T>(S, x0 + c % Wi, y0 + c / Wi, sw, t);
+    }
+    (void)gi;
+    return true;
+}
+
+// Final spread of a rebuilt plan in device memory and Eq. 28 at its band
+// nodes, inside the workgroup that corrected the group (after correct_group).
+template <typename T, int NT>
+__device__ void apply_rebuilt(const SimDev& S, const GroupDev& G, int nband, int sw) {
+    Band<T> B;
+    B.entpk = G.ent_D;
+    B.run32 = G.node_run;
+    for (int k = threadIdx.x; k < nband; k += NT) {
+        T t[5];
+        spread_node<T, false, false, 5>(B, reinterpret_cast<const T*>(G.m_wtot), 5, ldm<false>(G.node_run + k),
+                                        ldm<false>(G.node_run + k + 1), t);
+        const int cell = ldm<false>(G.node_cell + k);
+        correct_node<T>(S, cell % S.nx, cell / S.nx, sw, t);
+    }
+}
+
 template <typename T, int NT, int MPT>
 __global__ void __launch_bounds__(NT)
     k_ib(const SimDev* __restrict__ sims, GroupDev* __restrict__ groups, const BatchHeader* __restrict__ hdr,
@@ -1548,115 +1844,136 @@ __global__ void __launch_bounds__(NT)
         const int M = G.M;
         int nband = G.nband, nent = G.nent;
         IB_MARK(0);
-        if (G.dynamic && !build_plan_binned<NT>(S, G, reinterpret_cast<int*>(arena), scan_tmp, bbox, nband, nent))
-            build_plan<NT>(S, G, reinterpret_cast<unsigned long long*>(arena), scan_tmp, nband, nent);
-        if (tid == 0) {
-            int base = 0;
-            L.nb = G.nbody;
-            for (int b = 0; b < G.nbody; ++b) {
-                const BodyDev& Bd = S.bodies[G.body[b]];
-                L.body[b] = G.body[b];
-                L.m0[b] = Bd.m0;
-                L.gbase[b] = base;
-                base += Bd.n;
+        // body lookup of the group: the first wave reads every body at once
+        // and scans their marker counts
+        if (tid < 64) {
+            const int nb = G.nbody;
+            int n = 0;
+            if (tid < nb) {
+                const int b = G.body[tid];
+                const BodyDev& Bd = S.bodies[b];
+                L.body[tid] = b;
+                L.m0[tid] = Bd.m0;
+                n = Bd.n;
             }
-            L.gbase[G.nbody] = base;
-        }
-        T* phi_g = reinterpret_cast<T*>(G.m_phi);
-        // stencil weights of Eq. 15: phi per marker, D per stencil entry (static plans: once)
-        const bool fresh = G.dynamic || G.flags[0] == 0;
-        __syncthreads();
-        if (fresh) {
-            for (int g = tid; g < M; g += NT) {
-                int body;
-                const int mi = lookup(L, g, body);
-                const double X = S.mX[mi], Y = S.mY[mi];
-                const double fx = floor(X) - 1.0, fy = floor(Y) - 1.0;
+            int incl = n;
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    phi_g[g * 8 + q] = delta_w<T>(S.delta, T(fx + q - X));
-                    phi_g[g * 8 + 4 + q] = delta_w<T>(S.delta, T(fy + q - Y));
+            for (int off = 1; off < 8; off <<= 1) {
+                const int y = __shfl_up(incl, off, 64);
+                if (tid >= off) incl += y;
+            }
+            if (tid <= nb) L.gbase[tid] = incl - n;
+            if (tid == 0) L.nb = nb;
+        }
+        __syncthreads();
+        IB_MARK(31);
+        if (G.dynamic && correct_free_lds<T, NT, MPT>(S, G, L, arena, scan_tmp, bbox, sw, gi)) {
+            __syncthreads();
+            IB_MARK(25);
+        } else {
+            if (G.dynamic && !build_plan_binned<NT>(S, G, reinterpret_cast<int*>(arena), scan_tmp, bbox, nband, nent))
+                build_plan<NT>(S, G, reinterpret_cast<unsigned long long*>(arena), scan_tmp, nband, nent);
+            IB_MARK(30);
+            T* phi_g = reinterpret_cast<T*>(G.m_phi);
+            // stencil weights of Eq. 15: phi per marker, D per stencil entry (static plans: once)
+            const bool fresh = G.dynamic || G.flags[0] == 0;
+            __syncthreads();
+            if (fresh) {
+                for (int g = tid; g < M; g += NT) {
+                    int body;
+                    const int mi = lookup(L, g, body);
+                    const double X = S.mX[mi], Y = S.mY[mi];
+                    const double fx = floor(X) - 1.0, fy = floor(Y) - 1.0;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        phi_g[g * 8 + q] = delta_w<T>(S.delta, T(fx + q - X));
+                        phi_g[g * 8 + 4 + q] = delta_w<T>(S.delta, T(fy + q - Y));
+                    }
+                }
+                __syncthreads();
+                for (int e = tid; e < nent; e += NT) {
+                    const int p = G.ent[e];
+                    const int g = p >> 4;
+                    store_entry<T>(G.ent_D, e, g, phi_g[g * 8 + (p & 3)] * phi_g[g * 8 + 4 + ((p >> 2) & 3)]);
+                }
+                if (!G.dynamic)
+                    for (int g = tid; g < M; g += NT)
+                        stm<false>(reinterpret_cast<nv2<unsigned>*>(G.m_rows) + g, stencil_rows(G, g));
+                __syncthreads();
+                if (tid == 0 && !G.dynamic) G.flags[0] = 1;
+            }
+            IB_MARK(1);
+            // placement of the working arrays (the same decision on every thread):
+            // the segment band when the plan has one and it fits, else the entry band
+            bool done = false;
+            // (two markers per thread at most: larger groups never fit the class band)
+            constexpr int MPTC = MPT < 2 ? MPT : 2;
+            if (G.ncolor > 0 && M <= MPTC * NT) {
+                Bump cb;
+                cb.base = arena;
+                cb.off = 0;
+                ColBand<T> CB;
+                CB.inv = reinterpret_cast<T*>(cb.take((long)nband * sizeof(T)));
+                CB.j = reinterpret_cast<nv2<T>*>(cb.take(2L * nband * sizeof(T)));
+                CB.wt = reinterpret_cast<T*>(cb.take(2L * M * sizeof(T)));
+                CB.phi = reinterpret_cast<T*>(cb.take(8L * M * sizeof(T)));
+                CB.rows = reinterpret_cast<unsigned short*>(cb.take(2L * 4 * M));
+                if (CB.inv && CB.j && CB.wt && CB.phi && CB.rows) {
+                    if (tid <= G.ncolor) coff_s[tid] = G.coff[tid];
+                    __syncthreads();
+                    correct_group_col<T, NT, MPTC>(S, G, L, CB, coff_s, phi_g, M, nband, gi);
+                    done = true;
                 }
             }
-            __syncthreads();
-            for (int e = tid; e < nent; e += NT) {
-                const int p = G.ent[e];
-                const int g = p >> 4;
-                store_entry<T>(G.ent_D, e, g, phi_g[g * 8 + (p & 3)] * phi_g[g * 8 + 4 + ((p >> 2) & 3)]);
+            Bump bump;
+            bump.base = arena;
+            bump.off = 0;
+            Band<T> B;
+            T* lnode = reinterpret_cast<T*>(bump.take(4L * nband * sizeof(T)));
+            T* lwt = reinterpret_cast<T*>(bump.take(2L * M * sizeof(T)));
+            unsigned short* lrun = reinterpret_cast<unsigned short*>(bump.take(2L * (nband + 1)));
+            unsigned short* lrows = reinterpret_cast<unsigned short*>(bump.take(2L * 4 * M));
+            const bool core = nband < 0xFFFF && nent < 0xFFFF && lnode && lwt && lrun && lrows;
+            T* lphi = core ? reinterpret_cast<T*>(bump.take(8L * M * sizeof(T))) : nullptr;
+            unsigned short* lent = core ? reinterpret_cast<unsigned short*>(bump.take(2L * nent)) : nullptr;
+            const bool extra = core && lphi && lent && M < 4096;
+            B.mn32 = G.mnode;
+            B.entpk = G.ent_D;
+            B.run32 = G.node_run;
+            if (core) {
+                B.node = lnode;
+                B.wt = lwt;
+                B.run16 = lrun;
+                B.rows = lrows;
+            } else {
+                B.node = reinterpret_cast<T*>(G.node4);
+                B.wt = reinterpret_cast<T*>(G.m_wtot);
+                B.run16 = nullptr;
+                B.rows = nullptr;
             }
-            if (!G.dynamic)
-                for (int g = tid; g < M; g += NT)
-                    stm<false>(reinterpret_cast<nv2<unsigned>*>(G.m_rows) + g, stencil_rows(G, g));
+            if (extra) {
+                B.phi = lphi;
+                B.ent16 = lent;
+            } else {
+                B.phi = phi_g;
+                B.ent16 = nullptr;
+            }
+            if (done) {
+                // corrected on the class band
+            } else if (extra) {
+                correct_group<T, NT, MPT, true, true>(S, G, L, B, phi_g, M, nband, nent, sw, gi);
+            } else if (core) {
+                correct_group<T, NT, MPT, true, false>(S, G, L, B, phi_g, M, nband, nent, sw, gi);
+            } else {
+                correct_group<T, NT, MPT, false, false>(S, G, L, B, phi_g, M, nband, nent, sw, gi);
+            }
             __syncthreads();
-            if (tid == 0 && !G.dynamic) G.flags[0] = 1;
-        }
-        IB_MARK(1);
-        // placement of the working arrays (the same decision on every thread):
-        // the segment band when the plan has one and it fits, else the entry band
-        bool done = false;
-        // (two markers per thread at most: larger groups never fit the class band)
-        constexpr int MPTC = MPT < 2 ? MPT : 2;
-        if (G.ncolor > 0 && M <= MPTC * NT) {
-            Bump cb;
-            cb.base = arena;
-            cb.off = 0;
-            ColBand<T> CB;
-            CB.inv = reinterpret_cast<T*>(cb.take((long)nband * sizeof(T)));
-            CB.j = reinterpret_cast<nv2<T>*>(cb.take(2L * nband * sizeof(T)));
-            CB.wt = reinterpret_cast<T*>(cb.take(2L * M * sizeof(T)));
-            CB.phi = reinterpret_cast<T*>(cb.take(8L * M * sizeof(T)));
-            CB.rows = reinterpret_cast<unsigned short*>(cb.take(2L * 4 * M));
-            if (CB.inv && CB.j && CB.wt && CB.phi && CB.rows) {
-                if (tid <= G.ncolor) coff_s[tid] = G.coff[tid];
+            if (G.dynamic) {
+                apply_rebuilt<T, NT>(S, G, nband, sw);
                 __syncthreads();
-                correct_group_col<T, NT, MPTC>(S, G, L, CB, coff_s, phi_g, M, nband, gi);
-                done = true;
             }
+            IB_MARK(25);
         }
-        Bump bump;
-        bump.base = arena;
-        bump.off = 0;
-        Band<T> B;
-        T* lnode = reinterpret_cast<T*>(bump.take(4L * nband * sizeof(T)));
-        T* lwt = reinterpret_cast<T*>(bump.take(2L * M * sizeof(T)));
-        unsigned short* lrun = reinterpret_cast<unsigned short*>(bump.take(2L * (nband + 1)));
-        unsigned short* lrows = reinterpret_cast<unsigned short*>(bump.take(2L * 4 * M));
-        const bool core = nband < 0xFFFF && nent < 0xFFFF && lnode && lwt && lrun && lrows;
-        T* lphi = core ? reinterpret_cast<T*>(bump.take(8L * M * sizeof(T))) : nullptr;
-        unsigned short* lent = core ? reinterpret_cast<unsigned short*>(bump.take(2L * nent)) : nullptr;
-        const bool extra = core && lphi && lent && M < 4096;
-        B.mn32 = G.mnode;
-        B.entpk = G.ent_D;
-        B.run32 = G.node_run;
-        if (core) {
-            B.node = lnode;
-            B.wt = lwt;
-            B.run16 = lrun;
-            B.rows = lrows;
-        } else {
-            B.node = reinterpret_cast<T*>(G.node4);
-            B.wt = reinterpret_cast<T*>(G.m_wtot);
-            B.run16 = nullptr;
-            B.rows = nullptr;
-        }
-        if (extra) {
-            B.phi = lphi;
-            B.ent16 = lent;
-        } else {
-            B.phi = phi_g;
-            B.ent16 = nullptr;
-        }
-        if (done) {
-            // corrected on the class band
-        } else if (extra) {
-            correct_group<T, NT, MPT, true, true>(S, G, L, B, phi_g, M, nband, nent, sw, gi);
-        } else if (core) {
-            correct_group<T, NT, MPT, true, false>(S, G, L, B, phi_g, M, nband, nent, sw, gi);
-        } else {
-            correct_group<T, NT, MPT, false, false>(S, G, L, B, phi_g, M, nband, nent, sw, gi);
-        }
-        __syncthreads();
-        IB_MARK(25);
         // FP64 reductions per body (order fixed by the marker index)
         for (int b = 0; b < G.nbody; ++b) {
             const int nb = L.gbase[b + 1] - L.gbase[b];
@@ -1752,10 +2069,9 @@ __global__ void __launch_bounds__(NT)
 
 // ---------------------------------------------------------------- bookkeeping and I/O
 
-// Work of the band kernels: chunks of 256 band nodes, (group, first node).
-// A group with a fixed plan has nband nodes; a group whose plan is rebuilt on
-// the device has at most cap_nodes, and the count of the current step is
-// left by k_ib in flags[1].
+// Work of the band kernels: chunks of 256 band nodes (group, first node) of
+// the groups with fixed plans; k_ib gathers and applies the bands of the
+// groups whose plans it rebuilds.
 
 // Band records (rho, 1/rho, j) of the groups with fixed plans, from the
 // post-stream populations, before the correction sweeps.
@@ -1784,8 +2100,9 @@ __global__ void __launch_bounds__(256)
 
 // Final spread of the summed corrections and correction of the populations
 // (Eqs. 26-27; Eq. 28 is linear in dm and dPi, so the N sweeps' deviations
-// are spread once from their per-marker totals), one band node per thread;
-// each node sums its stencil entries in ascending marker order.
+// are spread once from their per-marker totals), one band node per thread of
+// the groups with fixed plans (k_ib applies rebuilt plans itself); each node
+// sums its stencil entries in ascending marker order.
 template <typename T>
 __global__ void __launch_bounds__(256)
     k_band_apply(const SimDev* __restrict__ sims, const GroupDev* __restrict__ groups,
@@ -1796,10 +2113,9 @@ __global__ void __launch_bounds__(256)
         const int2 ch = chunks[c];
         const GroupDev& G = groups[ch.x];
         const SimDev& S = sims[G.sim];
-        if (!S.active) continue;
-        const int nband = G.dynamic ? ldm<false>(G.flags + 1) : G.nband;
+        if (!S.active || G.dynamic) continue;  // rebuilt plans are applied by k_ib itself
         const int k = ch.y + threadIdx.x;
-        if (k >= nband) continue;
+        if (k >= G.nband) continue;
         const int sw = 1 - (parity >= 0 ? parity : S.swapped);
         Band<T> B;
         B.entpk = G.ent_D;
@@ -1808,22 +2124,7 @@ __global__ void __launch_bounds__(256)
         spread_node<T, false, false, 5>(B, reinterpret_cast<const T*>(G.m_wtot), 5, ldm<false>(G.node_run + k),
                                         ldm<false>(G.node_run + k + 1), t);
         const int cell = ldm<false>(G.node_cell + k);
-        const int x = cell % S.nx, y = cell / S.nx;
-        LBM_AS1 T* p[9];
-        T f[9];
-#pragma unroll
-        for (int i = 0; i < 9; ++i) {
-            p[i] = gptr(loc<T>(S, i, x, y, sw));
-            f[i] = *p[i];
-        }
-        const T trB = T(1.5) * (t[2] + t[4]);
-#pragma unroll
-        for (int i = 0; i < 9; ++i) {
-            const T ex = T(ex_of(i)), ey = T(ey_of(i));
-            const T d = weight_of<T>(i) *
-                        (T(3) * (ex * t[0] + ey * t[1]) + T(4.5) * (ex * ex * t[2] + T(2) * ex * ey * t[3] + ey * ey * t[4]) - trB);
-            *p[i] = f[i] + d;
-        }
+        correct_node<T>(S, cell % S.nx, cell / S.nx, sw, t);
     }
 }
 

@@ -154,7 +154,8 @@ struct lbm_batch {
     DevBuf d_sims;
     size_t cap_sims = 0;
     Lane lane[2];
-    int lanes_req = 0;              // 0 automatic, 1 one lane, 2 two free-running, 3 two interleaved (upload_tables)
+    int lanes_req = 0;              // 0 automatic, 1 one lane, 2 two free-running, 3 two interleaved,
+                                    // 4 two interleaved halves of equal node count (upload_tables)
     bool interleave = false;        // two lanes in use are interleaved step by step
     int nlanes = 1;                 // lanes in use
     int tiling = kTileDefault;
@@ -250,10 +251,11 @@ void build_tiles(lbm_sim* s, int sim_index, int tiling, std::vector<int4>& out) 
 }
 
 // Chunks of 256 band nodes of one group for the band kernels: all nodes of a
-// fixed plan, the capacity of a plan rebuilt on the device.
+// fixed plan; none for a plan rebuilt on the device (k_ib gathers and applies
+// those bands itself).
 void build_chunks(const GroupDev& d, int group_index, std::vector<int2>& out) {
-    const int cap = d.dynamic ? d.cap_nodes : d.nband;
-    for (int k = 0; k < cap; k += 256) out.push_back(make_int2(group_index, k));
+    if (d.dynamic) return;
+    for (int k = 0; k < d.nband; k += 256) out.push_back(make_int2(group_index, k));
 }
 
 void build_bc(lbm_sim* s, int sim_index, std::vector<int2>& out) {
@@ -970,6 +972,62 @@ size_t lbm_device_bytes(const lbm_sim* s) {
     return b;
 }
 
+// Mirrors the allocations of lbm_create, rebuild_ib and the per-simulation
+// tables above, taking every plan at its largest size: a group of M markers
+// has at most 16 M band nodes and stencil entries, and the groups partition
+// the bodies, so per-group constants count once per body.
+size_t lbm_device_bytes_bound(const lbm_params* p, int32_t nbodies, const int32_t* markers) {
+    if (!p || p->nx < 1 || p->ny < 1 || nbodies < 0 || nbodies > LBM_MAX_BODIES || (nbodies > 0 && !markers))
+        return 0;
+    const size_t tsz = p->precision == LBM_F64 ? sizeof(double) : sizeof(float);
+    SimDev h{};
+    h.nx = p->nx;
+    h.ny = p->ny;
+    h.bc[SIDE_W] = p->bc_west;
+    h.bc[SIDE_E] = p->bc_east;
+    h.bc[SIDE_S] = p->bc_south;
+    h.bc[SIDE_N] = p->bc_north;
+    const size_t nperim = (size_t)boundary_count(h);
+    size_t b = (size_t)blocks_per_row(p->nx) * Q * kBlk * (size_t)(p->ny + 2) * tsz;  // populations
+    b += sizeof(SimDev) + sizeof(uint32_t);
+    if (p->bc_west == LBM_BC_DIRICHLET) b += sizeof(double) * 2 * nperim;
+    const Tiling& t = kTilings[kTileDefault];
+    size_t ntiles;
+    if (t.tx == 0) {
+        const size_t nb = (size_t)((p->nx + kBlk - 1) / kBlk) * p->ny, per = (size_t)t.ty * t.rpt;
+        ntiles = (nb + per - 1) / per;
+    } else {
+        const size_t th = (size_t)t.ty * t.rpt;
+        ntiles = ((p->ny + th - 1) / th) * ((p->nx + t.tx - 1) / t.tx);
+    }
+    b += sizeof(int4) * std::max<size_t>(1, ntiles);
+    b += sizeof(int2) * std::max<size_t>(1, (nperim + 255) / 256);
+    size_t M = 0, nb = 0;
+    for (int k = 0; k < nbodies; ++k) {
+        if (markers[k] < 0) return 0;
+        if (markers[k] > 0) {
+            M += (size_t)markers[k];
+            ++nb;
+        }
+    }
+    b += sizeof(BodyDev) * LBM_MAX_BODIES + sizeof(double) * 5 * std::max<size_t>(1, M);
+    b += sizeof(GroupDev) * std::max<size_t>(1, nb);
+    b += sizeof(int2) * (16 * M / 256 + nb + 1);  // band chunks
+    // per group of Mg markers, with cn = max(1, band nodes) <= 16 Mg + 1
+    const size_t per_marker = sizeof(int) * 16 * 2          // node_cell, node_run
+                              + sizeof(int) * 16 * 2        // ent, mnode
+                              + tsz * 4 * 16                // node4
+                              + 2 * tsz * 16                // ent_D
+                              + tsz * (8 + 5)               // m_phi, m_wtot
+                              + sizeof(unsigned short) * 4  // m_rows
+                              + sizeof(double) * 5          // m_red
+                              + sizeof(unsigned short) * 2; // cord
+    const size_t per_group = sizeof(int) * 3 + sizeof(int) * 2 + sizeof(int) * 4 + tsz * 4 + 2 * tsz + tsz * 13 +
+                             sizeof(unsigned short) * 4 + sizeof(double) * 5 + sizeof(int) * (kMaxColors + 1);
+    b += per_marker * M + per_group * nb;
+    return b;
+}
+
 int32_t lbm_tiling_count(void) { return kNumTilings; }
 
 lbm_status lbm_tiling_info(int32_t k, int32_t* tx, int32_t* ty, int32_t* rpt) {
@@ -1036,7 +1094,8 @@ hipError_t ensure_cap(DevBuf& buf, size_t& cap, size_t need, bool& grew) {
 // Unless one lane is requested, the simulations whose largest body group
 // exceeds kHeavyGroupMarkers form lane 0 when that leaves both lanes non-empty
 // and lane 0 with at most half of the nodes; otherwise one lane holds
-// everything.
+// everything.  Lanes = 4 splits them into two lanes of about equal node count
+// instead.
 lbm_status upload_tables(lbm_batch* b) {
     const int n = (int)b->sims.size();
     std::vector<int> heavy, light;
@@ -1052,16 +1111,40 @@ lbm_status upload_tables(lbm_batch* b) {
             light.push_back(k);
         }
     }
-    const bool two = b->lanes_req != 1 && !heavy.empty() && !light.empty() && 2 * heavy_cells <= cells;
+    // lanes 4: halves of equal node count (largest first, each to the lane
+    // with fewer nodes so far), interleaved, so that one half's correction
+    // runs under the other half's sweep
+    const bool halves = b->lanes_req == 4 && n >= 2;
+    const bool by_weight = !halves && b->lanes_req != 1 && b->lanes_req != 4 && !heavy.empty() && !light.empty() &&
+                           2 * heavy_cells <= cells;
+    const bool two = by_weight || halves;
     const int nl = two ? 2 : 1;
-    const bool il = two && (b->lanes_req == 3 || (b->lanes_req == 0 && cells >= kInterleaveMinCells));
+    const bool il = two && (b->lanes_req >= 3 || (b->lanes_req == 0 && cells >= kInterleaveMinCells));
     if (nl != b->nlanes || il != b->interleave) drop_graphs(b);
     b->nlanes = nl;
     b->interleave = il;
     b->order.clear();
-    if (two) {
+    int lane0_sims = n;  // simulations of lane 0 (the first ones in b->order)
+    if (by_weight) {
         b->order = heavy;
         b->order.insert(b->order.end(), light.begin(), light.end());
+        lane0_sims = (int)heavy.size();
+    } else if (halves) {
+        std::vector<int> idx(n);
+        for (int k = 0; k < n; ++k) idx[k] = k;
+        auto cells_of = [&](int k) { return (int64_t)b->sims[k]->p.nx * b->sims[k]->p.ny; };
+        std::stable_sort(idx.begin(), idx.end(), [&](int a, int c) { return cells_of(a) > cells_of(c); });
+        std::vector<int> half[2];
+        int64_t sum[2] = {0, 0};
+        for (int k : idx) {
+            const int l = sum[1] < sum[0] ? 1 : 0;
+            half[l].push_back(k);
+            sum[l] += cells_of(k);
+        }
+        for (int l = 0; l < 2; ++l) std::sort(half[l].begin(), half[l].end());  // admission order within a lane
+        b->order = half[0];
+        b->order.insert(b->order.end(), half[1].begin(), half[1].end());
+        lane0_sims = (int)half[0].size();
     } else {
         for (int k = 0; k < n; ++k) b->order.push_back(k);
     }
@@ -1072,7 +1155,7 @@ lbm_status upload_tables(lbm_batch* b) {
     if (grew_sims) drop_graphs(b);
     if (!sims.empty())
         HIPB(b, hipMemcpyAsync(b->d_sims.p, sims.data(), sizeof(SimDev) * sims.size(), hipMemcpyHostToDevice, b->stream));
-    const int lane_begin[3] = {0, two ? (int)heavy.size() : n, n};
+    const int lane_begin[3] = {0, lane0_sims, n};
     for (int l = 0; l < 2; ++l) {
         Lane& L = b->lane[l];
         const int r0 = l < nl ? lane_begin[l] : n, r1 = l < nl ? lane_begin[l + 1] : n;
@@ -1137,6 +1220,9 @@ lbm_status upload_tables(lbm_batch* b) {
             L.grid_band = h.nchunks + h.nchunks / 4 + 8;
             changed = true;
         }
+        // a kind of kernel with no work in the lane is left out of its graphs
+        changed = changed || (h.nbc > 0) != (L.nbc > 0) || (h.nchunks > 0) != (L.nchunks > 0) ||
+                  (h.ngroups > 0) != (L.ngroups > 0);
         bool grew = false;
         HIPB(b, ensure_cap<int4>(L.d_tiles, L.cap_tiles, tl.size(), grew));
         HIPB(b, ensure_cap<int2>(L.d_bc, L.cap_bc, bc.size(), grew));
@@ -1171,6 +1257,10 @@ hipError_t launch_kind(lbm_batch* b, int l, int k, hipStream_t st) {
     const Lane& L = b->lane[l];
     SimDev* sims = (SimDev*)b->d_sims.p;
     const BatchHeader* hdr = (const BatchHeader*)L.d_hdr.p;
+    // kinds with no work in the lane are not launched (upload_tables drops
+    // the captured graphs when that changes)
+    if ((k == 1 && L.nbc == 0) || ((k == 2 || k == 4) && L.nchunks == 0) || (k == 3 && L.ngroups == 0))
+        return hipSuccess;
     switch (k) {
         case 0: return launch_sweep(b->f64, L.mrt, b->tiling, sims, (const int4*)L.d_tiles.p, hdr, 0, L.grid_sweep, -1, st);
         case 1: return launch_boundary(b->f64, sims, (const int2*)L.d_bc.p, hdr, 0, b->grid_bc, -1, st);
@@ -1525,7 +1615,7 @@ lbm_status lbm_batch_autotune(lbm_batch* b, int32_t trials, int32_t* chosen) {
 }
 
 lbm_status lbm_batch_set_lanes(lbm_batch* b, int32_t lanes) {
-    if (!b || lanes < 0 || lanes > 3) return LBM_ERR_INVALID;
+    if (!b || lanes < 0 || lanes > 4) return LBM_ERR_INVALID;
     lbm_status rc = sync_back(b);
     if (rc != LBM_OK) return rc;
     b->lanes_req = lanes;

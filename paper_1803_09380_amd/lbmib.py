@@ -67,6 +67,7 @@ SIGNATURES = [
     ("lbm_set_populations", _ST, [_P, _DP]),
     ("lbm_set_fields", _ST, [_P, _DP, _DP, _DP]),
     ("lbm_device_bytes", _SZ, [_P]),
+    ("lbm_device_bytes_bound", _SZ, [ctypes.POINTER(Params), _I32, ctypes.POINTER(_I32)]),
     ("lbm_batch_create", _ST, [_I32, _SZ, _P, ctypes.POINTER(_P)]),
     ("lbm_batch_destroy", None, [_P]),
     ("lbm_batch_admit", _ST, [_P, _P, _I64]),
@@ -134,6 +135,42 @@ def _stream_handle(stream):
     return ctypes.c_void_p(int(stream))
 
 
+def make_params(nx, ny, tau, rho0=1.0, precision=F64, bc=(PERIODIC,) * 4, u_in=(0.0, 0.0), u_init=(0.0, 0.0),
+                ib_iters=10, gravity=(0.0, 0.0), collision=BGK, mrt_s=None, delta=4):
+    p = Params()
+    p.nx, p.ny, p.tau, p.rho0, p.precision = nx, ny, tau, rho0, precision
+    p.bc_west, p.bc_east, p.bc_south, p.bc_north = bc
+    p.u_in[:] = u_in
+    p.u_init[:] = u_init
+    p.ib_iters = ib_iters
+    p.gravity[:] = gravity
+    p.collision = collision
+    p.mrt_s[:] = mrt_s if mrt_s is not None else [1.0 / tau] * 9
+    p.delta = delta
+    return p
+
+
+def _case_params(case, precision=None, collision=None, mrt_s=None, delta=None):
+    if collision is None:
+        mrt_s = case.get("mrt_s") if mrt_s is None else mrt_s
+        collision = BGK if mrt_s is None else MRT
+    return make_params(case["nx"], case["ny"], case["tau"], rho0=case["rho0"],
+                       precision=case["precision"] if precision is None else precision, bc=case["bc"],
+                       u_in=case["u_in"], u_init=case["u_init"], ib_iters=case["ib_iters"],
+                       gravity=case["gravity"], collision=collision, mrt_s=mrt_s,
+                       delta=case.get("delta", 4) if delta is None else delta)
+
+
+def device_bytes_bound(case, precision=None):
+    """lbm_device_bytes_bound for a workloads.py case: an upper bound on the
+    device memory of Sim.from_case(case, precision), computed on the host
+    without creating anything."""
+    p = _case_params(case, precision)
+    n = len(case["bodies"])
+    counts = (_I32 * max(1, n))(*[int(b["n"]) for b in case["bodies"]])
+    return int(load().lbm_device_bytes_bound(ctypes.byref(p), n, counts))
+
+
 class Sim:
     """One simulation (lbm_sim)."""
 
@@ -141,16 +178,8 @@ class Sim:
                  u_init=(0.0, 0.0), ib_iters=10, gravity=(0.0, 0.0), stream=None, collision=BGK,
                  mrt_s=None, delta=4):
         L = load()
-        p = Params()
-        p.nx, p.ny, p.tau, p.rho0, p.precision = nx, ny, tau, rho0, precision
-        p.bc_west, p.bc_east, p.bc_south, p.bc_north = bc
-        p.u_in[:] = u_in
-        p.u_init[:] = u_init
-        p.ib_iters = ib_iters
-        p.gravity[:] = gravity
-        p.collision = collision
-        p.mrt_s[:] = mrt_s if mrt_s is not None else [1.0 / tau] * 9
-        p.delta = delta
+        p = make_params(nx, ny, tau, rho0=rho0, precision=precision, bc=bc, u_in=u_in, u_init=u_init,
+                        ib_iters=ib_iters, gravity=gravity, collision=collision, mrt_s=mrt_s, delta=delta)
         h = _P()
         rc = L.lbm_create(ctypes.byref(p), _stream_handle(stream), ctypes.byref(h))
         if rc != OK:
@@ -362,8 +391,9 @@ class Batch:
 
     def set_lanes(self, n):
         """0: automatic, 1: one lane, 2: two lanes replayed independently,
-        3: two lanes interleaved step by step (two lanes need a heavy/light
-        split of the members)."""
+        3: two lanes interleaved step by step (2 and 3 need a heavy/light
+        split of the members), 4: two interleaved halves of equal node count
+        (at least two members)."""
         rc = load().lbm_batch_set_lanes(self._h, n)
         if rc != OK:
             raise LbmError(rc, "lbm_batch_set_lanes")

@@ -44,6 +44,11 @@ class GpuExecutor:
     def create(self, req):
         return self.lbmib.Sim.from_case(req.case, precision=self.precision)
 
+    def bytes_needed(self, req):
+        """Device memory a request will hold, bounded on the host before
+        anything is created."""
+        return self.lbmib.device_bytes_bound(req.case, self.precision)
+
     def bytes(self, handle):
         return handle.device_bytes
 
@@ -112,16 +117,19 @@ class Server:
 
     def _try_admit(self, waiting):
         """Admit waiting requests in arrival order while the budget allows;
-        stops at the first one that does not fit (no overtaking)."""
+        stops at the first one that does not fit (no overtaking).  The fit is
+        decided on the executor's host-side bound of the request's memory, so
+        a request that has to wait costs no device allocation; once admitted
+        it is charged what it actually holds."""
         while waiting:
             req = waiting[0]
+            need = self.ex.bytes_needed(req)
+            if self.budget and self.used + need > self.budget:
+                if not self.live and need > self.budget:
+                    raise ValueError("request %d needs %d bytes, above the whole budget" % (req.rid, need))
+                return
             handle = self.ex.create(req)
             nb = self.ex.bytes(handle)
-            if self.budget and self.used + nb > self.budget:
-                self.ex.discard(handle)
-                if not self.live and nb > self.budget:
-                    raise ValueError("request %d needs %d bytes, above the whole budget" % (req.rid, nb))
-                return
             if not self.ex.admit(req, handle):
                 self.ex.discard(handle)
                 return

@@ -148,6 +148,20 @@ def test_hbm_budget_refuses_admission():
     assert b.admit(b2)
 
 
+def test_device_bytes_bound_holds():
+    """The host-side bound is never below what a created simulation holds,
+    and within 1 % of it for the served 400 x 4000 box."""
+    _say("device bytes bound")
+    cases = _cases() + [wl.settling(nx=400, ny=4000, D=30.0, density_ratio=1.3, two=True, lower=(200.0, 300.0))]
+    for prec in (lbmib.F32_SHIFTED, lbmib.F64):
+        for c in cases:
+            s = gpu_from_case(c, precision=prec)
+            actual, bound = s.device_bytes, lbmib.device_bytes_bound(c, prec)
+            assert actual <= bound, (c["nx"], c["ny"], prec, actual, bound)
+            s.close()
+        assert bound < 1.01 * actual
+
+
 def test_precision_mismatch_is_rejected():
     s = gpu_from_case(wl.couette(32), precision=lbmib.F64)
     b = lbmib.Batch(lbmib.F32_SHIFTED)
@@ -193,10 +207,10 @@ def test_two_lanes_give_the_same_bits():
     """The member with a large body group goes to its own lane on a second
     stream; every member's result is the same with one lane, with two lanes,
     and alone."""
-    _say("lanes: one vs two (free-running, interleaved) vs alone, 17 steps")
+    _say("lanes: one vs two (free-running, interleaved, equal halves) vs alone, 17 steps")
     cases = _lane_cases()
     res = {}
-    for lanes in (1, 2, 3):
+    for lanes in (1, 2, 3, 4):
         sims = [gpu_from_case(c, precision=lbmib.F32_SHIFTED) for c in cases]
         b = lbmib.Batch(lbmib.F32_SHIFTED)
         for s in sims:
@@ -209,7 +223,7 @@ def test_two_lanes_give_the_same_bits():
         b.close()
     alone = gpu_from_case(cases[0], precision=lbmib.F32_SHIFTED)
     alone.step(17)
-    for lanes in (2, 3):
+    for lanes in (2, 3, 4):
         for x, y in zip(res[1], res[lanes]):
             _same(x, y)
         _same(res[lanes][0], _state(alone, 2))
@@ -278,7 +292,7 @@ def test_lane_requests():
     b.set_lanes(3)
     assert b.lanes == 2
     with pytest.raises(lbmib.LbmError):
-        b.set_lanes(4)
+        b.set_lanes(5)
     b.close()
     small = [gpu_from_case(c, precision=lbmib.F32_SHIFTED) for c in _cases()]
     b = lbmib.Batch(lbmib.F32_SHIFTED)
@@ -286,10 +300,12 @@ def test_lane_requests():
         assert b.admit(s)
     b.set_lanes(3)
     assert b.lanes == 1
+    b.set_lanes(4)  # equal halves need no heavy member
+    assert b.lanes == 2
     b.close()
 
 
-@pytest.mark.parametrize("lanes", [2, 3])
+@pytest.mark.parametrize("lanes", [2, 3, 4])
 def test_lanes_survive_admission_and_retirement(lanes):
     _say("lanes %d with admission and retirement" % lanes)
     lc = _lane_cases()
@@ -306,7 +322,7 @@ def test_lanes_survive_admission_and_retirement(lanes):
     b.sync()
     assert big.step_count == 7 and all(s.step_count == 14 for s in small)
     b.retire(big)
-    assert b.lanes == 1
+    assert b.lanes == (2 if lanes == 4 else 1)
     b.step(3)
     b.sync()
     assert all(s.step_count == 17 for s in small)

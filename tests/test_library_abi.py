@@ -9,6 +9,7 @@ import subprocess
 import pytest
 
 from paper_1803_09380_amd import lbmib
+from paper_1803_09380_amd import workloads as wl
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "lbmib.h")
@@ -76,3 +77,28 @@ def test_binding_layout_matches_the_c_header(struct, cls, tmp_path):
 
 def test_version_string():
     assert lbmib.version().startswith("lbmib-gfx950")
+
+
+def test_device_bytes_bound_is_host_arithmetic():
+    """The bound needs no device: the population array of the row-blocked
+    layout (rows -1 .. ny, blocks of 64 nodes with 9 populations, a ghost
+    block and the x = nx ghost) plus a small IB term; invalid arguments give 0."""
+    case = wl.settling(nx=400, ny=4000, D=40.0, density_ratio=1.2, two=True, lower=(200.0, 300.0))
+    nblk = (400 + 64) // 64 + 1
+    pop = nblk * 9 * 64 * (4000 + 2) * 4
+    b32 = lbmib.device_bytes_bound(case, lbmib.F32_SHIFTED)
+    assert pop < b32 < 1.01 * pop
+    b64 = lbmib.device_bytes_bound(case, lbmib.F64)
+    assert 2 * pop < b64 < 1.01 * 2 * pop
+    L = lbmib.load()
+    p = lbmib.make_params(64, 64, 0.8)
+    counts = (ctypes.c_int32 * 9)(*([10] * 9))
+    assert L.lbm_device_bytes_bound(None, 0, None) == 0
+    assert L.lbm_device_bytes_bound(ctypes.byref(p), 9, counts) == 0
+    assert L.lbm_device_bytes_bound(ctypes.byref(p), 1, None) == 0
+    neg = (ctypes.c_int32 * 1)(-1)
+    assert L.lbm_device_bytes_bound(ctypes.byref(p), 1, neg) == 0
+    # more markers never lower the bound
+    one = (ctypes.c_int32 * 1)(100)
+    two = (ctypes.c_int32 * 1)(200)
+    assert L.lbm_device_bytes_bound(ctypes.byref(p), 1, two) > L.lbm_device_bytes_bound(ctypes.byref(p), 1, one)

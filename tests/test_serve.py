@@ -29,7 +29,11 @@ class MockExecutor:
         self.trace = []
 
     def create(self, req):
+        self.trace.append(("create", req.rid, self.clock()))
         return {"rid": req.rid, "nodes": req.case["nx"] * req.case["ny"], "left": req.steps, "ran": 0}
+
+    def bytes_needed(self, req):
+        return req.case["nx"] * req.case["ny"] * self.bpn
 
     def bytes(self, h):
         return h["nodes"] * self.bpn
@@ -130,3 +134,20 @@ def test_idle_server_waits_for_the_next_arrival():
     reqs = [Request(0, 5.0, wl.settling(nx=100, ny=400, D=12.0, lower=(50.0, 350.0)), 50)]
     done = srv.run(reqs)
     assert done[0].t_admit >= 5.0
+
+
+def test_no_request_is_created_while_admission_is_blocked():
+    """A request that does not fit the budget waits without a device
+    allocation: each request is created once, when it is admitted."""
+    clk = VirtualClock()
+    ex = MockExecutor(clk)
+    per = 100 * 400 * 36
+    srv = Server(ex, hbm_budget=2 * per, chunk=25, clock=clk, sleep=clk.sleep)
+    done = srv.run(_reqs(8, rate=1000.0, steps=150))
+    assert len(done) == 8
+    creates = [rid for kind, rid, _ in ex.trace if kind == "create"]
+    admits = [rid for kind, rid, _ in ex.trace if kind == "admit"]
+    assert creates == admits == list(range(8))
+    # every create is immediately followed by its admit
+    kinds = [(kind, rid) for kind, rid, _ in ex.trace if kind in ("create", "admit")]
+    assert all(kinds[2 * k] == ("create", k) and kinds[2 * k + 1] == ("admit", k) for k in range(8))
