@@ -9,10 +9,15 @@ kernels).  One step = collide-stream sweep, boundary rules, 10 correction
 sweeps with FP64 force/torque reductions, bookkeeping, for every member.
 
 Printed (one JSON line): aggregate MLUPS of the batched FP32 path over exactly
---steps timed steps, the sweep kernel's HBM roofline fraction (per-launch
-duration from HIP events on the batch stream), the plain per-simulation FP64
-GPU path on a sample of the same set, and the FP64 CPU oracle timed on the
-host cores on a bounded sample.
+--steps timed steps; the sweep kernel's HBM roofline fraction (per-launch
+duration from HIP events on the batch stream) against the datasheet peak and
+against the best copy measured here (copy_probe.py), and the whole step's
+fraction at 72 B per node update; the plain per-simulation FP64 GPU path on a
+sample of the same set; the set with the MRT collision; the served stream
+(arrival-bound and overloaded); and the FP64 CPU oracle timed on the host
+cores (one thread and every thread, CPU model stated) on a bounded sample,
+with every GPU path's error against it on seeded members of the same
+workloads.
 """
 import argparse
 import json
@@ -34,6 +39,12 @@ SWEEP_BYTES_F64 = 144
 # kernel source they were taken on (its SHA-256 is recorded with them).
 PMC_FILE = os.path.join(ROOT, "profiles", "k_sweep_f32_batched256_pmc.txt")
 KERNEL_SRC = os.path.join(ROOT, "paper_1803_09380_amd", "csrc", "kernels.hip")
+
+
+def frac_of_peak(mlups):
+    """Fraction of the HBM peak that `mlups` FP32 node updates per second
+    would move at the sweep's 72 algorithmic bytes each."""
+    return None if mlups is None else round(mlups * SWEEP_BYTES_F32 / 1e3 / HBM_PEAK_GBS, 4)
 
 
 def sweep_traffic(tiling):
@@ -74,35 +85,175 @@ def _oracle_from_case(po, case):
     return o
 
 
-def run_cpu_baseline(cases, seconds):
-    threads = max(1, min(16, os.cpu_count() or 1))
-    os.environ["OMP_NUM_THREADS"] = str(threads)
-    sys.path.insert(0, os.path.join(ROOT, "oracle"))
-    import pyoracle as po
-    po.build()
-    updates = 0
-    used = 0.0
-    members = 0
-    steps_each = []
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def _host_threads():
+    """Threads the oracle may use: the host cores this process may run on,
+    at most 16 (one GPU's share of the host)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def _oracle_sample(po, cases, seconds, max_steps=200):
+    """Time the oracle on members of `cases` one at a time, in seed order,
+    until `seconds` of host time are used (each member at least 5 steps)."""
+    updates, used, steps_each = 0, 0.0, []
     for case in cases:
         if used >= seconds:
             break
         o = _oracle_from_case(po, case)
-        n = 0
-        t0 = time.perf_counter()
+        n, t0 = 0, time.perf_counter()
         while True:
             o.step(5)
             n += 5
             el = time.perf_counter() - t0
-            if el > seconds / 4 or used + el >= seconds or n >= 200:
+            if el > seconds / 4 or used + el >= seconds or n >= max_steps:
                 break
         used += el
         updates += case["nx"] * case["ny"] * n
-        members += 1
         steps_each.append(n)
-    return {"value": updates / used / 1e6, "unit": "MLUPS", "cores": threads, "kind": "oracle",
-            "sample": "%d members of the set (first in seed order), %s steps each, %.1f s of host time, "
-                      "FP64, IB sweeps serial, collide/stream OpenMP" % (members, steps_each, used)}
+    return {"updates": updates, "seconds": used, "members": len(steps_each), "steps": steps_each}
+
+
+def _cpu_configs():
+    """Seeded cases of the other configurations, each timed on a bounded
+    number of steps: (name, case, steps)."""
+    from paper_1803_09380_amd import workloads as wl
+    out = [("couette64", wl.couette(64), 2000), ("couette256", wl.couette(256), 100),
+           ("cylinder1600x800_re20", wl.cylinder(Re=20.0), 20)]
+    for k, r in enumerate(wl.arrivals(seed=0, rate=20.0, count=4, steps=2000)):
+        out.append(("served_request%d" % k, r["case"], 10))
+    return out
+
+
+def cpu_worker(spec):
+    """Child process of the CPU baseline: OMP_NUM_THREADS is fixed by the
+    parent.  Prints one JSON line."""
+    sys.path.insert(0, os.path.join(ROOT, "oracle"))
+    import pyoracle as po
+    po.build()
+    from paper_1803_09380_amd import workloads as wl
+    if spec["kind"] == "batch":
+        cases = wl.batch(seed=spec["seed"], count=spec["sims"], precision=wl.F32)
+        res = _oracle_sample(po, cases[:16], spec["seconds"])
+    else:
+        res = {}
+        for name, case, steps in _cpu_configs():
+            o = _oracle_from_case(po, case)
+            o.step(1)
+            t0 = time.perf_counter()
+            o.step(steps)
+            el = time.perf_counter() - t0
+            res[name] = {"mlups": round(case["nx"] * case["ny"] * steps / el / 1e6, 3), "steps": steps,
+                         "nodes": case["nx"] * case["ny"], "seconds": round(el, 3)}
+    print(json.dumps(res), flush=True)
+
+
+def _run_worker(spec, threads):
+    import subprocess
+    env = dict(os.environ, OMP_NUM_THREADS=str(threads), OMP_PROC_BIND="false")
+    out = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-worker", json.dumps(spec)],
+                         stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True, env=env, check=True)
+    return json.loads(out.stdout.strip().splitlines()[-1])
+
+
+def run_cpu_baseline(args):
+    """The FP64 oracle on the host cores: the first members of the set one at
+    a time, single-threaded and with every thread this process may use (in
+    child processes, before the GPU is touched); optionally the other
+    configurations on bounded step counts."""
+    threads = _host_threads()
+    spec = {"kind": "batch", "seed": args.seed, "sims": args.sims, "seconds": args.cpu_seconds / 2}
+    one = _run_worker(spec, 1)
+    alln = _run_worker(spec, threads) if threads > 1 else one
+    res = {"value": round(alln["updates"] / alln["seconds"] / 1e6, 3), "unit": "MLUPS", "cores": threads,
+           "kind": "oracle",
+           "sample": "first %d members of the set one at a time, %s steps each, %.1f s of host time "
+                     "(FP64; collide/stream OpenMP over %d threads, correction serial)"
+                     % (alln["members"], alln["steps"], alln["seconds"], threads),
+           "single_thread": {"value": round(one["updates"] / one["seconds"] / 1e6, 3), "unit": "MLUPS",
+                             "sample": "first %d members, %s steps each, %.1f s"
+                                       % (one["members"], one["steps"], one["seconds"])},
+           "cpu_model": _cpu_model()}
+    if args.cpu_configs:
+        res["configs"] = {"threads_1": _run_worker({"kind": "configs"}, 1)}
+        if threads > 1:
+            res["configs"]["threads_%d" % threads] = _run_worker({"kind": "configs"}, threads)
+    return res
+
+
+def _vel_err(g, o):
+    import numpy as np
+    _, ug, vg = g
+    _, uo, vo = o
+    l2 = float(np.sqrt(np.sum((ug - uo) ** 2 + (vg - vo) ** 2) / np.sum(uo ** 2 + vo ** 2)))
+    mx = float(max(np.abs(ug - uo).max(), np.abs(vg - vo).max()) / max(np.abs(uo).max(), np.abs(vo).max()))
+    return {"velocity_rel_l2": l2, "velocity_max_rel": mx}
+
+
+def oracle_errors(cases, lbmib, wl, steps=100):
+    """Part of the CPU-baseline leg: each GPU path against the FP64 oracle on
+    the same seeded input -- the smallest Couette and the smallest cylinder of
+    the set (FP32 shifted as batched, and FP64 as the plain path), the
+    smallest Couette with the MRT rates, and one served request (a 400 x 4000
+    box, 10 steps).  A member gives the same bits alone and in the batch, so
+    it runs alone here."""
+    sys.path.insert(0, os.path.join(ROOT, "oracle"))
+    import pyoracle as po
+    po.build()
+    cou = min((c for c in cases if c["bodies"] and c["bc"][0] == wl.PERIODIC), key=lambda c: c["nx"] * c["ny"])
+    cyl = min((c for c in cases if c["bc"][0] != wl.PERIODIC), key=lambda c: c["nx"] * c["ny"])
+    out = {"steps": steps}
+    for name, case in (("couette_%dx%d" % (cou["nx"], cou["ny"]), cou),
+                       ("cylinder_%dx%d" % (cyl["nx"], cyl["ny"]), cyl)):
+        o = _oracle_from_case(po, case)
+        o.step(steps)
+        of = o.fields()
+        row = {}
+        for pname, prec in (("fp32_shifted", lbmib.F32_SHIFTED), ("fp64", lbmib.F64)):
+            g = lbmib.Sim.from_case(case, precision=prec)
+            g.step(steps)
+            row[pname] = _vel_err(g.fields(), of)
+            g.close()
+        out[name] = row
+    rates = wl.mrt_rates(cou["tau"])
+    o = po.Oracle(cou["nx"], cou["ny"], cou["tau"], rho0=cou["rho0"], bc=cou["bc"], u_in=cou["u_in"],
+                  u_init=cou["u_init"], ib_iters=cou["ib_iters"], gravity=cou["gravity"], collision=po.MRT,
+                  mrt_s=rates)
+    for k, b in enumerate(cou["bodies"]):
+        o.set_body(k, po.FIXED, b["n"], xy=b["xy"], uv=b["uv"], ds=b["ds"], xc=b["xc"], U=b["U"],
+                   omega=b["omega"], theta=b["theta"])
+    o.step(steps)
+    g = lbmib.Sim.from_case(cou, precision=lbmib.F32_SHIFTED, mrt_s=rates)
+    g.step(steps)
+    out["mrt_fp32_shifted"] = _vel_err(g.fields(), o.fields())
+    g.close()
+    req = wl.arrivals(seed=0, rate=20.0, count=1, steps=2000)[0]["case"]
+    o = _oracle_from_case(po, req)
+    o.step(10)
+    g = lbmib.Sim.from_case(req, precision=lbmib.F32_SHIFTED)
+    g.step(10)
+    import numpy as np
+    e = _vel_err(g.fields(), o.fields())
+    Fg, Fo = g.forces(0)[0], o.forces(0)[0]
+    e["force_rel"] = float(np.abs(Fg - Fo).max() / max(np.abs(Fo).max(), 1e-300))
+    e["steps"] = 10
+    out["served_request_fp32_shifted"] = e
+    g.close()
+    return out
 
 
 def plain_mlups(args, cases, lbmib, precision):
@@ -194,8 +345,14 @@ def main():
     ap.add_argument("--profile-steps", type=int, default=20)
     ap.add_argument("--fp64-sample", type=int, default=16)
     ap.add_argument("--fp64-steps", type=int, default=50)
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds", type=float, default=16.0,
+                    help="host time of the oracle sample, split between one thread and all threads")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-configs", action="store_true",
+                    help="also time the oracle on the other configurations (bounded steps; minutes)")
+    ap.add_argument("--cpu-only", action="store_true",
+                    help="print the CPU baseline alone (with --cpu-configs: every configuration) and stop")
+    ap.add_argument("--cpu-worker", default=None, help=argparse.SUPPRESS)
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default sweep tiling instead of timing the candidates on the set")
     ap.add_argument("--tiling", type=int, default=-1)
@@ -212,6 +369,9 @@ def main():
                     help="time the batched set only (for profiler runs): no CPU baseline, FP64 sample, "
                          "accuracy or serving legs")
     args = ap.parse_args()
+    if args.cpu_worker is not None:
+        cpu_worker(json.loads(args.cpu_worker))
+        return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: every simulation of the set fits one MI355X and the set "
               "shards by simulation with no communication; --gpus %d is not supported" % args.gpus,
@@ -229,7 +389,10 @@ def main():
         args.mrt_steps = 0
     cpu = None
     if not args.no_cpu:
-        cpu = run_cpu_baseline(cases, args.cpu_seconds)
+        cpu = run_cpu_baseline(args)
+        if args.cpu_only:
+            print(json.dumps({"cpu_baseline": cpu}), flush=True)
+            return
 
     import numpy as np
     import torch
@@ -306,6 +469,7 @@ def main():
         srv.run(reqs)
         ex.close()
         serving = srv.stats.summary()
+        serving["frac_of_peak"] = frac_of_peak(serving["aggregate_mlups"])
         serving.update({"arrivals": "Poisson, mean 20/s, seed %d" % args.seed, "lattice": "400x4000 closed box",
                         "steps_per_request": args.serve_steps, "hbm_budget_bytes": budget,
                         "particles": "1 or 2 free circles, D 16..40, density ratio 1.01..1.5"})
@@ -325,9 +489,22 @@ def main():
         srv.run(reqs)
         ex.close()
         overload = srv.stats.summary()
+        overload["frac_of_peak"] = frac_of_peak(overload["aggregate_mlups"])
         overload.update({"arrivals": "Poisson, mean 20/s, seed %d" % (args.seed + 1),
                          "lattice": "400x4000 closed box", "steps_per_request": 10 * args.serve_steps,
                          "hbm_budget_bytes": budget, "budget_requests": 8})
+
+    # ---- measured HBM copy (hand-written 16-byte copies and torch's) beside the datasheet peak
+    copy = None
+    if not args.only_batch:
+        import copy_probe
+        copy = copy_probe.measure(mib=1024, reps=10)
+
+    # ---- CPU-baseline leg, second part: every GPU path against the FP64 oracle
+    vs_oracle = None
+    if cpu is not None:
+        vs_oracle = oracle_errors(cases, lbmib, wl)
+        cpu["gpu_vs_oracle"] = vs_oracle
 
     out = {
         "metric": METRIC,
@@ -354,6 +531,12 @@ def main():
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": None if traffic is None else int(traffic),
             "traffic_over_algorithmic": None if traffic is None else round(traffic / (SWEEP_BYTES_F32 * pcells), 3),
+            "measured_copy_gbs": None if copy is None else copy["best_copy_gbs"],
+            "measured_copy": None if copy is None else copy["best_copy"],
+            "frac_of_measured_copy": None if copy is None else round(achieved / copy["best_copy_gbs"], 4),
+            "torch_copy_gbs": None if copy is None else round(copy["torch_copy_gbs"], 1),
+            "step_frac": frac_of_peak(mlups),
+            "step_frac_note": "whole step (sweep, boundary, correction, bookkeeping) at 72 B per node update",
             "kernel": "k_sweep<float>", "launch_ms": round(sweep_ms, 4),
             "bytes_per_cell": SWEEP_BYTES_F32, "cells_per_launch": pcells,
             "step_split_ms": {"sweep": round(ms[0] / args.profile_steps, 4),
@@ -368,7 +551,8 @@ def main():
             "speedup_fp32_batched": round(f32_sample_mlups / f64_mlups, 2),
             "fp32_plain_same_sample": round(f32_plain_mlups, 1),
             "speedup_of_batching_fp32": round(f32_sample_mlups / f32_plain_mlups, 2)},
-        "accuracy": None if err is None else {"fp32_vs_fp64_velocity_rel_l2": err, "case": "couette64, 2000 steps"},
+        "accuracy": None if err is None else {"fp32_vs_fp64_velocity_rel_l2": err, "case": "couette64, 2000 steps",
+                                              "vs_fp64_oracle": vs_oracle},
         "mrt": mrt,
         "unstable_members": unstable,
         "serving": serving,
