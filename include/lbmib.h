@@ -271,11 +271,11 @@ int32_t lbm_batch_get_tiling(const lbm_batch* b);
  * streams: those whose largest body group has more than 400 markers, and the
  * rest, when both are non-empty and the first holds at most half of the nodes.
  * lanes = 2 replays each lane's captured graphs of several steps on its own
- * stream, independently; lanes = 3 interleaves the lanes step by step (the
- * second lane's sweep runs as two launches, the first lane's step waits for
- * the second lane's previous sweep, and when no band of the second lane comes
- * within three nodes of a non-periodic side its boundary rules run on a third
- * stream beside its correction; steps are launched one by one from the host).
+ * stream, independently; lanes = 3 interleaves the lanes step by step, their
+ * sweeps in turn (the second lane's sweep of a step waits for the first
+ * lane's, the first lane's next sweep for the second lane's), so that each
+ * lane's boundary rules and correction run while the other lane sweeps;
+ * steps are launched one by one from the host.
  * lanes = 4 interleaves two lanes the same way but splits the simulations
  * into two halves of about equal node count instead (at least two
  * simulations), so that either half's correction can run under the other

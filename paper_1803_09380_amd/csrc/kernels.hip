@@ -676,13 +676,16 @@ __device__ void build_plan(const SimDev& S, const GroupDev& G, unsigned long lon
 constexpr int kBinCells = 16384;
 // LDS arena of the correction kernel (plan build, then the band's working arrays)
 constexpr int kIbArenaBytes = 148 * 1024;
+// ... and of the lean correction kernel (dynamic LDS, so that the compiler
+// budgets registers for four waves per SIMD)
+constexpr int kIbLeanArenaBytes = 96 * 1024;
 
 template <int NT>
-__device__ bool build_plan_binned(const SimDev& S, const GroupDev& G, int* lds, int* scan_tmp, int* bbox,
-                                  int& nband_out, int& nent_out) {
+__device__ bool build_plan_binned(const SimDev& S, const GroupDev& G, int* lds, int arena_bytes, int* scan_tmp,
+                                  int* bbox, int& nband_out, int& nent_out) {
     const int tid = threadIdx.x;
     const int M = G.M, NE = 16 * M;
-    if (M == 0 || 2L * M * (int)sizeof(int) > kIbArenaBytes) return false;
+    if (M == 0 || 2L * M * (int)sizeof(int) > arena_bytes) return false;
     if (tid == 0) {
         bbox[0] = 0x7fffffff;
         bbox[1] = 0x7fffffff;
@@ -715,7 +718,7 @@ __device__ bool build_plan_binned(const SimDev& S, const GroupDev& G, int* lds, 
     const int x0 = bbox[0], y0 = bbox[1];
     const long W = (long)bbox[2] - x0 + 1, H = (long)bbox[3] - y0 + 1;
     const long words = 2L * M + 2 * W * H + NE;
-    if (W * H > kBinCells || words * (long)sizeof(int) > kIbArenaBytes || (S.px && W >= S.nx) || (S.py && H >= S.ny))
+    if (W * H > kBinCells || words * (long)sizeof(int) > arena_bytes || (S.px && W >= S.nx) || (S.py && H >= S.ny))
         return false;
     const int ncell = (int)(W * H);
     int* count = lds + 2 * M;  // per box cell: entries, then band-node index
@@ -849,14 +852,15 @@ __device__ void collision_force(double xi0, double xi1, double xj0, double xj1, 
 // indices (16-bit), the per-marker phi values and the stencil entries are
 // placed here while they fit; the rest stay in the group's global scratch
 // (generic pointers serve both).  A plan rebuilt on the device first uses the
-// arena (kIbArenaBytes) for its sort keys or bins.
+// arena for its sort keys or bins.
 
 struct Bump {
     char* base;
     int off;
+    int cap;  // arena bytes
     __device__ void* take(long bytes) {
         const long a = (bytes + 15) & ~15L;
-        if (off + a <= kIbArenaBytes) {
+        if (off + a <= cap) {
             void* p = base + off;
             off += (int)a;
             return p;
@@ -1559,14 +1563,15 @@ __device__ __forceinline__ void correct_group_col(const SimDev& S, const GroupDe
 // same plan.  Returns false, having written nothing to device memory, when the
 // group does not qualify or its arrays do not fit the arena.
 template <typename T, int NT, int MPT>
-__device__ bool correct_free_lds(const SimDev& S, const GroupDev& G, const GroupLookup& L, char* arena, int* scan_tmp,
-                                 int* bbox, int sw, int gi) {
+__device__ bool correct_free_lds(const SimDev& S, const GroupDev& G, const GroupLookup& L, char* arena,
+                                 int arena_bytes, int* scan_tmp, int* bbox, int sw, int gi) {
     const int tid = threadIdx.x;
     const int M = G.M, NE = 16 * M;
     if (M == 0 || M > MPT * NT || NE > 0xFFFF) return false;
     Bump bp;
     bp.base = arena;
     bp.off = 0;
+    bp.cap = arena_bytes;
     int* mfx = reinterpret_cast<int*>(bp.take(4L * M));
     int* mfy = reinterpret_cast<int*>(bp.take(4L * M));
     T* phi = reinterpret_cast<T*>(bp.take(8L * M * sizeof(T)));
@@ -1822,11 +1827,12 @@ __device__ void apply_rebuilt(const SimDev& S, const GroupDev& G, int nband, int
     }
 }
 
+// The correction of every group of a launch, one workgroup per group at a
+// time (k_ib and k_ib_lean).
 template <typename T, int NT, int MPT>
-__global__ void __launch_bounds__(NT)
-    k_ib(const SimDev* __restrict__ sims, GroupDev* __restrict__ groups, const BatchHeader* __restrict__ hdr,
-         int ngroups_arg, int parity) {
-    __shared__ __align__(16) char arena[kIbArenaBytes];
+__device__ __forceinline__ void ib_groups(const SimDev* __restrict__ sims, GroupDev* __restrict__ groups,
+                                          const BatchHeader* __restrict__ hdr, int ngroups_arg, int parity,
+                                          char* arena, int arena_bytes) {
     __shared__ double part[4 * 5];
     __shared__ int scan_tmp[NT];
     __shared__ double body_out[8][5];
@@ -1867,11 +1873,11 @@ __global__ void __launch_bounds__(NT)
         }
         __syncthreads();
         IB_MARK(31);
-        if (G.dynamic && correct_free_lds<T, NT, MPT>(S, G, L, arena, scan_tmp, bbox, sw, gi)) {
+        if (G.dynamic && correct_free_lds<T, NT, MPT>(S, G, L, arena, arena_bytes, scan_tmp, bbox, sw, gi)) {
             __syncthreads();
             IB_MARK(25);
         } else {
-            if (G.dynamic && !build_plan_binned<NT>(S, G, reinterpret_cast<int*>(arena), scan_tmp, bbox, nband, nent))
+            if (G.dynamic && !build_plan_binned<NT>(S, G, reinterpret_cast<int*>(arena), arena_bytes, scan_tmp, bbox, nband, nent))
                 build_plan<NT>(S, G, reinterpret_cast<unsigned long long*>(arena), scan_tmp, nband, nent);
             IB_MARK(30);
             T* phi_g = reinterpret_cast<T*>(G.m_phi);
@@ -1912,6 +1918,7 @@ __global__ void __launch_bounds__(NT)
                 Bump cb;
                 cb.base = arena;
                 cb.off = 0;
+                cb.cap = arena_bytes;
                 ColBand<T> CB;
                 CB.inv = reinterpret_cast<T*>(cb.take((long)nband * sizeof(T)));
                 CB.j = reinterpret_cast<nv2<T>*>(cb.take(2L * nband * sizeof(T)));
@@ -1928,6 +1935,7 @@ __global__ void __launch_bounds__(NT)
             Bump bump;
             bump.base = arena;
             bump.off = 0;
+            bump.cap = arena_bytes;
             Band<T> B;
             T* lnode = reinterpret_cast<T*>(bump.take(4L * nband * sizeof(T)));
             T* lwt = reinterpret_cast<T*>(bump.take(2L * M * sizeof(T)));
@@ -2065,6 +2073,27 @@ __global__ void __launch_bounds__(NT)
         __syncthreads();
         IB_MARK(27);
     }
+}
+
+template <typename T, int NT, int MPT>
+__global__ void __launch_bounds__(NT)
+    k_ib(const SimDev* __restrict__ sims, GroupDev* __restrict__ groups, const BatchHeader* __restrict__ hdr,
+         int ngroups_arg, int parity) {
+    __shared__ __align__(16) char arena[kIbArenaBytes];
+    ib_groups<T, NT, MPT>(sims, groups, hdr, ngroups_arg, parity, arena, kIbArenaBytes);
+}
+
+// One wave per SIMD and at most 128 VGPRs: a workgroup of this form finds room
+// on a CU as soon as two sweep waves per SIMD have finished there, so the
+// correction of one lane runs while the other lane's sweep streams (a
+// 768-thread k_ib needs a CU with no sweep wave left).  For groups of at most
+// MPT * 256 markers.
+template <typename T, int MPT>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8)))
+    k_ib_lean(const SimDev* __restrict__ sims, GroupDev* __restrict__ groups, const BatchHeader* __restrict__ hdr,
+              int ngroups_arg, int parity) {
+    extern __shared__ __align__(16) char lean_arena[];  // kIbLeanArenaBytes at launch
+    ib_groups<T, 256, MPT>(sims, groups, hdr, ngroups_arg, parity, lean_arena, kIbLeanArenaBytes);
 }
 
 // ---------------------------------------------------------------- bookkeeping and I/O
@@ -2271,7 +2300,22 @@ static hipError_t ib_t(const SimDev* sims, GroupDev* groups, const BatchHeader* 
     return hipGetLastError();
 }
 
-int ib_variant(bool f64, int max_markers) { return f64 ? (max_markers <= 8 * 256 ? 0 : 1) : (max_markers <= 3 * 768 ? 2 : 3); }
+template <typename T, int MPT>
+static hipError_t ib_lean_t(const SimDev* sims, GroupDev* groups, const BatchHeader* hdr, int ngroups, int grid,
+                            int parity, hipStream_t stream) {
+    static const hipError_t attr =
+        hipFuncSetAttribute(reinterpret_cast<const void*>(&k_ib_lean<T, MPT>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, kIbLeanArenaBytes);
+    if (attr != hipSuccess) return attr;
+    hipLaunchKernelGGL((k_ib_lean<T, MPT>), dim3(grid), dim3(256), kIbLeanArenaBytes, stream, sims, groups, hdr,
+                       ngroups, parity);
+    return hipGetLastError();
+}
+
+int ib_variant(bool f64, int max_markers) {
+    if (f64) return max_markers <= 8 * 256 ? 0 : 1;
+    return max_markers <= 256 ? 4 : max_markers <= 512 ? 5 : max_markers <= 3 * 768 ? 2 : 3;
+}
 
 hipError_t launch_ib(bool f64, int max_markers, const SimDev* sims, GroupDev* groups, const BatchHeader* hdr,
                      int ngroups, int grid, int parity, hipStream_t stream) {
@@ -2281,6 +2325,8 @@ hipError_t launch_ib(bool f64, int max_markers, const SimDev* sims, GroupDev* gr
     if (f64)
         return max_markers <= 8 * 256 ? ib_t<double, 256, 8>(sims, groups, hdr, ngroups, grid, parity, stream)
                                       : ib_t<double, 256, 16>(sims, groups, hdr, ngroups, grid, parity, stream);
+    if (max_markers <= 256) return ib_lean_t<float, 1>(sims, groups, hdr, ngroups, grid, parity, stream);
+    if (max_markers <= 512) return ib_lean_t<float, 2>(sims, groups, hdr, ngroups, grid, parity, stream);
     return max_markers <= 3 * 768 ? ib_t<float, 768, 3>(sims, groups, hdr, ngroups, grid, parity, stream)
                                   : ib_t<float, 512, 8>(sims, groups, hdr, ngroups, grid, parity, stream);
 }

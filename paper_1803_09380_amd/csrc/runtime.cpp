@@ -118,8 +118,7 @@ struct Lane {
     int grid_sweep = 0, grid_band = 0;
     bool mrt = false;  // some simulation of the lane uses the MRT collision
     hipGraphExec_t graph1 = nullptr, graphK = nullptr;
-    hipGraphExec_t graphA = nullptr, graphB = nullptr;  // one step split: sweep (two launches), the rest
-    bool bnd_apart = false;  // graphB leaves out the boundary rules and the bookkeeping (run_interleaved)
+    hipGraphExec_t graphA = nullptr, graphB = nullptr;  // one step split: the sweep, the rest (run_interleaved)
     void drop() {
         for (hipGraphExec_t* g : {&graph1, &graphK, &graphA, &graphB}) {
             if (*g) (void)hipGraphExecDestroy(*g);
@@ -145,10 +144,8 @@ struct lbm_batch {
     hipStream_t stream = nullptr;   // the caller's (or an own) stream: lane 0
     bool own_stream = false;
     hipStream_t stream2 = nullptr;  // lane 1, owned
-    hipStream_t stream3 = nullptr;  // lane 1's boundary rules beside its correction, owned
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
-    hipEvent_t ev_sweep = nullptr;  // lane 1's sweep of the current step is done
-    hipEvent_t ev_bnd = nullptr;    // lane 1's boundary rules of the current step are done
+    hipEvent_t ev_sweep0 = nullptr, ev_sweep1 = nullptr;  // lane 0's, lane 1's sweep of the current step is done
     std::vector<lbm_sim*> sims;
     std::vector<int> order;         // simulation table row -> index into sims
     DevBuf d_sims;
@@ -161,16 +158,24 @@ struct lbm_batch {
     int tiling = kTileDefault;
     int grid_bc = 0, grid_ib = 0;
     int graphK_steps = 8;
+    // interleaved lanes: graphs of 1 and graphK_steps steps of both lanes
+    hipGraphExec_t il_graph1 = nullptr, il_graphK = nullptr;
+    void drop_il() {
+        for (hipGraphExec_t* g : {&il_graph1, &il_graphK}) {
+            if (*g) (void)hipGraphExecDestroy(*g);
+            *g = nullptr;
+        }
+    }
     size_t bytes = 0;
     std::string err;
     ~lbm_batch() {
         lane[0].drop();
         lane[1].drop();
+        drop_il();
         if (ev_fork) (void)hipEventDestroy(ev_fork);
         if (ev_join) (void)hipEventDestroy(ev_join);
-        if (ev_sweep) (void)hipEventDestroy(ev_sweep);
-        if (ev_bnd) (void)hipEventDestroy(ev_bnd);
-        if (stream3) (void)hipStreamDestroy(stream3);
+        if (ev_sweep0) (void)hipEventDestroy(ev_sweep0);
+        if (ev_sweep1) (void)hipEventDestroy(ev_sweep1);
         if (stream2) (void)hipStreamDestroy(stream2);
     }
 };
@@ -1058,6 +1063,7 @@ lbm_status hipfailb(lbm_batch* b, hipError_t e, const char* where) {
 void drop_graphs(lbm_batch* b) {
     b->lane[0].drop();
     b->lane[1].drop();
+    b->drop_il();
 }
 
 // Copy the per-simulation step state (AA state, counters) of the device table
@@ -1232,7 +1238,10 @@ lbm_status upload_tables(lbm_batch* b) {
             HIPB(b, L.d_hdr.alloc(sizeof(BatchHeader)));
             grew = true;
         }
-        if (grew || changed || L.sim0 != r0) L.drop();
+        if (grew || changed || L.sim0 != r0) {
+            L.drop();
+            b->drop_il();
+        }
         L.sim0 = r0;
         if (!tl.empty()) HIPB(b, hipMemcpyAsync(L.d_tiles.p, tl.data(), sizeof(int4) * tl.size(), hipMemcpyHostToDevice, b->stream));
         if (!bc.empty()) HIPB(b, hipMemcpyAsync(L.d_bc.p, bc.data(), sizeof(int2) * bc.size(), hipMemcpyHostToDevice, b->stream));
@@ -1308,68 +1317,45 @@ lbm_status ensure_lane_stream(lbm_batch* b) {
     HIPB(b, hipStreamCreateWithFlags(&b->stream2, hipStreamNonBlocking));
     HIPB(b, hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming));
     HIPB(b, hipEventCreateWithFlags(&b->ev_join, hipEventDisableTiming));
-    HIPB(b, hipEventCreateWithFlags(&b->ev_sweep, hipEventDisableTiming));
-    HIPB(b, hipStreamCreateWithFlags(&b->stream3, hipStreamNonBlocking));
-    HIPB(b, hipEventCreateWithFlags(&b->ev_bnd, hipEventDisableTiming));
+    HIPB(b, hipEventCreateWithFlags(&b->ev_sweep0, hipEventDisableTiming));
+    HIPB(b, hipEventCreateWithFlags(&b->ev_sweep1, hipEventDisableTiming));
     return LBM_OK;
 }
 
-// Two lanes, interleaved step by step.  Lane 1's sweep is split into two
-// launches (halves of every XCD's tiles) and lane 0's step t waits for lane 1's
-// sweep of step t - 1, so lane 0's sweep runs during lane 1's boundary and
-// correction kernels.  A correction workgroup needs a whole CU (its register
-// file and most of its LDS), which a running sweep never leaves free; lane 0's
-// correction finds free CUs where lane 1's first sweep launch drains.
+// Two lanes, interleaved step by step with their sweeps in turn: lane 1's
+// sweep of step t waits for lane 0's sweep of step t, and lane 0's sweep of
+// step t + 1 for lane 1's sweep of step t, so each lane's boundary rules and
+// correction run while the other lane's sweep streams (a lean correction
+// workgroup finds room on a CU beside sweep waves; a 768-thread one waits for
+// a whole CU).  Steps of both lanes, with these dependencies, are captured
+// into one graph (of 1 and of graphK_steps steps) spanning the two streams.
+hipError_t enqueue_interleaved(lbm_batch* b, int n) {
+    hipStream_t st[2] = {b->stream, b->stream2};
+    hipError_t e = hipEventRecord(b->ev_fork, st[0]);
+    if (e == hipSuccess) e = hipStreamWaitEvent(st[1], b->ev_fork, 0);
+    for (int t = 0; t < n && e == hipSuccess; ++t) {
+        if (t > 0) e = hipStreamWaitEvent(st[0], b->ev_sweep1, 0);
+        if (e == hipSuccess) e = launch_kind(b, 0, 0, st[0]);
+        if (e == hipSuccess) e = hipEventRecord(b->ev_sweep0, st[0]);
+        for (int k = 1; k < 6 && e == hipSuccess; ++k) e = launch_kind(b, 0, k, st[0]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(st[1], b->ev_sweep0, 0);
+        if (e == hipSuccess) e = launch_kind(b, 1, 0, st[1]);
+        if (e == hipSuccess) e = hipEventRecord(b->ev_sweep1, st[1]);
+        for (int k = 1; k < 6 && e == hipSuccess; ++k) e = launch_kind(b, 1, k, st[1]);
+    }
+    if (e == hipSuccess) e = hipEventRecord(b->ev_join, st[1]);
+    if (e == hipSuccess) e = hipStreamWaitEvent(st[0], b->ev_join, 0);
+    return e;
+}
+
 lbm_status run_interleaved(lbm_batch* b, int n) {
-    hipStream_t st0 = b->stream, st1 = b->stream2;
-    Lane& H = b->lane[0];
-    Lane& Lt = b->lane[1];
-    if (!H.graph1) HIPB(b, capture(b, 0, 1, st0, &H.graph1));
-    if (!Lt.graphA) {
-        const int half = 8 * ((Lt.grid_sweep / 8 + 1) / 2);
-        SimDev* sims = (SimDev*)b->d_sims.p;
-        const BatchHeader* hdr = (const BatchHeader*)Lt.d_hdr.p;
-        const int4* tiles = (const int4*)Lt.d_tiles.p;
-        HIPB(b, capture_fn(st1, [&]() {
-            hipError_t e = launch_sweep(b->f64, Lt.mrt, b->tiling, sims, tiles, hdr, 0, half, -1, st1, 0);
-            return e != hipSuccess ? e : launch_sweep(b->f64, Lt.mrt, b->tiling, sims, tiles, hdr, 0, half, -1, st1, 1);
-        }, &Lt.graphA));
-    }
-    if (!Lt.graphB) {
-        // lane 1's boundary rules run beside its correction when no band of
-        // its simulations comes near a non-periodic side
-        Lt.bnd_apart = true;
-        for (int r = Lt.sim0; r < Lt.sim0 + Lt.nsims; ++r)
-            Lt.bnd_apart = Lt.bnd_apart && !b->sims[b->order[r]]->band_near_edge;
-        const int k0 = Lt.bnd_apart ? 2 : 1, k1 = Lt.bnd_apart ? 5 : 6;
-        HIPB(b, capture_fn(st1, [&]() {
-            for (int k = k0; k < k1; ++k) {
-                hipError_t e = launch_kind(b, 1, k, st1);
-                if (e != hipSuccess) return e;
-            }
-            return hipSuccess;
-        }, &Lt.graphB));
-    }
-    HIPB(b, hipEventRecord(b->ev_fork, st0));
-    HIPB(b, hipStreamWaitEvent(st1, b->ev_fork, 0));
-    for (int t = 0; t < n; ++t) {
-        if (t > 0) HIPB(b, hipStreamWaitEvent(st0, b->ev_sweep, 0));
-        HIPB(b, hipGraphLaunch(H.graph1, st0));
-        HIPB(b, hipGraphLaunch(Lt.graphA, st1));
-        HIPB(b, hipEventRecord(b->ev_sweep, st1));
-        if (Lt.bnd_apart) {
-            HIPB(b, hipStreamWaitEvent(b->stream3, b->ev_sweep, 0));
-            HIPB(b, launch_kind(b, 1, 1, b->stream3));
-            HIPB(b, hipEventRecord(b->ev_bnd, b->stream3));
-        }
-        HIPB(b, hipGraphLaunch(Lt.graphB, st1));
-        if (Lt.bnd_apart) {
-            HIPB(b, hipStreamWaitEvent(st1, b->ev_bnd, 0));
-            HIPB(b, launch_kind(b, 1, 5, st1));
-        }
-    }
-    HIPB(b, hipEventRecord(b->ev_join, st1));
-    HIPB(b, hipStreamWaitEvent(st0, b->ev_join, 0));
+    hipStream_t st0 = b->stream;
+    if (!b->il_graph1) HIPB(b, capture_fn(st0, [&]() { return enqueue_interleaved(b, 1); }, &b->il_graph1));
+    if (!b->il_graphK)
+        HIPB(b, capture_fn(st0, [&]() { return enqueue_interleaved(b, b->graphK_steps); }, &b->il_graphK));
+    int left = n;
+    for (; left >= b->graphK_steps; left -= b->graphK_steps) HIPB(b, hipGraphLaunch(b->il_graphK, st0));
+    for (; left > 0; --left) HIPB(b, hipGraphLaunch(b->il_graph1, st0));
     return LBM_OK;
 }
 
