@@ -1811,10 +1811,39 @@ __device__ bool correct_free_lds(const SimDev& S, const GroupDev& G, const Group
     return true;
 }
 
-// Final spread of a rebuilt plan in device memory and Eq. 28 at its band
-// nodes, inside the workgroup that corrected the group (after correct_group).
+// Band records of a plan in device memory (node cells, records in node4),
+// from the post-stream populations, four nodes per thread in flight.
 template <typename T, int NT>
-__device__ void apply_rebuilt(const SimDev& S, const GroupDev& G, int nband, int sw) {
+__device__ void gather_band(const SimDev& S, const GroupDev& G, int nband, int sw) {
+    const T rho_base = T(S.rho_base);
+    nv4<T>* node4 = reinterpret_cast<nv4<T>*>(G.node4);
+    for (int k0 = threadIdx.x; k0 < nband; k0 += 4 * NT) {
+        T h[4][9];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int k = k0 + u * NT;
+            if (k < nband) {
+                const int cell = ldm<false>(G.node_cell + k);
+                const int x = cell % S.nx, y = cell / S.nx;
+#pragma unroll
+                for (int i = 0; i < 9; ++i) h[u][i] = ldm<false>(loc<T>(S, i, x, y, sw));
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int k = k0 + u * NT;
+            if (k < nband) stm<false>(node4 + k, band_record<T>(h[u], rho_base));
+        }
+    }
+}
+
+// Final spread of a plan in device memory and Eq. 28 at its band nodes,
+// inside the workgroup that corrected the group (after correct_group or
+// correct_group_col, which leave the per-marker totals in m_wtot).  Groups
+// never share a band node, and every (node, population) pair has a slot of
+// its own in either AA state, so the groups of a launch apply side by side.
+template <typename T, int NT>
+__device__ void apply_band(const SimDev& S, const GroupDev& G, int nband, int sw) {
     Band<T> B;
     B.entpk = G.ent_D;
     B.run32 = G.node_run;
@@ -1909,6 +1938,12 @@ __device__ __forceinline__ void ib_groups(const SimDev* __restrict__ sims, Group
                 if (tid == 0 && !G.dynamic) G.flags[0] = 1;
             }
             IB_MARK(1);
+            // band records (rho, 1/rho, j) of a fixed plan from the post-stream
+            // populations (a rebuilt plan gathers its own in correct_group)
+            if (!G.dynamic && G.in_kernel) {
+                gather_band<T, NT>(S, G, nband, sw);
+                __syncthreads();
+            }
             // placement of the working arrays (the same decision on every thread):
             // the segment band when the plan has one and it fits, else the entry band
             bool done = false;
@@ -1976,8 +2011,8 @@ __device__ __forceinline__ void ib_groups(const SimDev* __restrict__ sims, Group
                 correct_group<T, NT, MPT, false, false>(S, G, L, B, phi_g, M, nband, nent, sw, gi);
             }
             __syncthreads();
-            if (G.dynamic) {
-                apply_rebuilt<T, NT>(S, G, nband, sw);
+            if (G.in_kernel) {
+                apply_band<T, NT>(S, G, nband, sw);
                 __syncthreads();
             }
             IB_MARK(25);
@@ -2099,8 +2134,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))
 // ---------------------------------------------------------------- bookkeeping and I/O
 
 // Work of the band kernels: chunks of 256 band nodes (group, first node) of
-// the groups with fixed plans; k_ib gathers and applies the bands of the
-// groups whose plans it rebuilds.
+// the groups with large fixed plans, whose band one workgroup would gather and
+// apply slowly (each node's populations lie in nine cache lines); k_ib
+// gathers and applies every other band itself.
 
 // Band records (rho, 1/rho, j) of the groups with fixed plans, from the
 // post-stream populations, before the correction sweeps.
@@ -2114,7 +2150,7 @@ __global__ void __launch_bounds__(256)
         const int2 ch = chunks[c];
         const GroupDev& G = groups[ch.x];
         const SimDev& S = sims[G.sim];
-        if (!S.active || G.dynamic) continue;
+        if (!S.active || G.in_kernel) continue;
         const int k = ch.y + threadIdx.x;
         if (k >= G.nband) continue;
         const int sw = 1 - (parity >= 0 ? parity : S.swapped);
@@ -2130,8 +2166,8 @@ __global__ void __launch_bounds__(256)
 // Final spread of the summed corrections and correction of the populations
 // (Eqs. 26-27; Eq. 28 is linear in dm and dPi, so the N sweeps' deviations
 // are spread once from their per-marker totals), one band node per thread of
-// the groups with fixed plans (k_ib applies rebuilt plans itself); each node
-// sums its stencil entries in ascending marker order.
+// the groups with large fixed plans (k_ib applies the others itself); each
+// node sums its stencil entries in ascending marker order.
 template <typename T>
 __global__ void __launch_bounds__(256)
     k_band_apply(const SimDev* __restrict__ sims, const GroupDev* __restrict__ groups,
@@ -2142,7 +2178,7 @@ __global__ void __launch_bounds__(256)
         const int2 ch = chunks[c];
         const GroupDev& G = groups[ch.x];
         const SimDev& S = sims[G.sim];
-        if (!S.active || G.dynamic) continue;  // rebuilt plans are applied by k_ib itself
+        if (!S.active || G.in_kernel) continue;  // applied by k_ib itself
         const int k = ch.y + threadIdx.x;
         if (k >= G.nband) continue;
         const int sw = 1 - (parity >= 0 ? parity : S.swapped);
@@ -2312,21 +2348,20 @@ static hipError_t ib_lean_t(const SimDev* sims, GroupDev* groups, const BatchHea
     return hipGetLastError();
 }
 
-int ib_variant(bool f64, int max_markers) {
+int ib_variant(bool f64, int max_markers, bool lean) {
     if (f64) return max_markers <= 8 * 256 ? 0 : 1;
-    return max_markers <= 256 ? 4 : max_markers <= 512 ? 5 : max_markers <= 3 * 768 ? 2 : 3;
+    return lean && max_markers <= 256 ? 4 : max_markers <= 3 * 768 ? 2 : 3;
 }
 
 hipError_t launch_ib(bool f64, int max_markers, const SimDev* sims, GroupDev* groups, const BatchHeader* hdr,
-                     int ngroups, int grid, int parity, hipStream_t stream) {
+                     int ngroups, int grid, int parity, hipStream_t stream, bool lean) {
     if (grid <= 0) return hipSuccess;
     if (max_markers > kMaxGroupMarkers) return hipErrorInvalidValue;
     // each thread keeps up to MPT markers' running sums in registers
     if (f64)
         return max_markers <= 8 * 256 ? ib_t<double, 256, 8>(sims, groups, hdr, ngroups, grid, parity, stream)
                                       : ib_t<double, 256, 16>(sims, groups, hdr, ngroups, grid, parity, stream);
-    if (max_markers <= 256) return ib_lean_t<float, 1>(sims, groups, hdr, ngroups, grid, parity, stream);
-    if (max_markers <= 512) return ib_lean_t<float, 2>(sims, groups, hdr, ngroups, grid, parity, stream);
+    if (lean && max_markers <= 256) return ib_lean_t<float, 1>(sims, groups, hdr, ngroups, grid, parity, stream);
     return max_markers <= 3 * 768 ? ib_t<float, 768, 3>(sims, groups, hdr, ngroups, grid, parity, stream)
                                   : ib_t<float, 512, 8>(sims, groups, hdr, ngroups, grid, parity, stream);
 }

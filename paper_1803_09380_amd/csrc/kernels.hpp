@@ -38,9 +38,11 @@ hipError_t launch_sweep(bool f64, bool mrt, int tiling, const SimDev* sims, cons
 hipError_t launch_boundary(bool f64, const SimDev* sims, const int2* items, const BatchHeader* hdr,
                            int nitems, int grid, int parity, hipStream_t stream);
 // max_markers: the largest group's marker count (selects how many markers
-// each thread carries; the results do not depend on it).
+// each thread carries; the results do not depend on it).  lean: FP32 groups of
+// at most 256 markers run in the 256-thread kernel that fits beside sweep
+// waves (for lanes whose corrections overlap another lane's sweep).
 hipError_t launch_ib(bool f64, int max_markers, const SimDev* sims, GroupDev* groups, const BatchHeader* hdr,
-                     int ngroups, int grid, int parity, hipStream_t stream);
+                     int ngroups, int grid, int parity, hipStream_t stream, bool lean = false);
 // Band kernels over chunks of 256 band nodes (group, first node): apply =
 // false gathers the band records of fixed-plan groups before k_ib, apply =
 // true spreads the per-marker totals and corrects the populations after it.
@@ -48,7 +50,7 @@ hipError_t launch_band(bool f64, bool apply, const SimDev* sims, const GroupDev*
                        const BatchHeader* hdr, int nchunks, int grid, int parity, hipStream_t stream);
 hipError_t launch_advance(SimDev* sims, const BatchHeader* hdr, int nsims, hipStream_t stream);
 // which k_ib instance launch_ib picks for a largest group of max_markers
-int ib_variant(bool f64, int max_markers);
+int ib_variant(bool f64, int max_markers, bool lean);
 // Field and population I/O of one simulation (state `sw` = AA state now).
 hipError_t launch_fields(bool f64, const SimDev* sim, int nx, int ny, int sw, double* rho,
                          double* ux, double* uy, hipStream_t stream);

@@ -138,6 +138,10 @@ struct GroupDev {
     // band nodes: no two markers of a class share a band node, so a class
     // spreads into the band without conflicts (ncolor = 0: no such plan).
     int32_t ncolor;
+    // 1: the correction workgroup gathers and applies the band itself (plans
+    // rebuilt on the device, and fixed plans of at most kFuseBandNodes nodes);
+    // 0: the band kernels do, over all CUs
+    int32_t in_kernel;
     unsigned short* cord;     // [2 M] group marker at each position (by class, then marker),
                               // then the position of each group marker
     int32_t* coff;            // [ncolor + 1] first position of each class

@@ -132,6 +132,12 @@ struct Lane {
 // the other lane's lighter work does (between its two sweep launches when the
 // lanes are interleaved).
 constexpr int kHeavyGroupMarkers = 400;
+// Fixed plans of at most this many band nodes are gathered and applied by
+// their correction workgroup; larger ones by the band kernels over all CUs (a
+// node's nine populations lie in nine cache lines, which one CU fetches at a
+// fraction of the chip's rate: 5,000 nodes took 50 us each way in one
+// workgroup against a few us spread over the chip).
+constexpr int kFuseBandNodes = 1024;
 // Two interleaved lanes are launched step by step from the host; below this
 // many nodes the automatic choice replays each lane's graphs of several steps
 // independently instead.
@@ -158,20 +164,11 @@ struct lbm_batch {
     int tiling = kTileDefault;
     int grid_bc = 0, grid_ib = 0;
     int graphK_steps = 8;
-    // interleaved lanes: graphs of 1 and graphK_steps steps of both lanes
-    hipGraphExec_t il_graph1 = nullptr, il_graphK = nullptr;
-    void drop_il() {
-        for (hipGraphExec_t* g : {&il_graph1, &il_graphK}) {
-            if (*g) (void)hipGraphExecDestroy(*g);
-            *g = nullptr;
-        }
-    }
     size_t bytes = 0;
     std::string err;
     ~lbm_batch() {
         lane[0].drop();
         lane[1].drop();
-        drop_il();
         if (ev_fork) (void)hipEventDestroy(ev_fork);
         if (ev_join) (void)hipEventDestroy(ev_join);
         if (ev_sweep0) (void)hipEventDestroy(ev_sweep0);
@@ -255,11 +252,10 @@ void build_tiles(lbm_sim* s, int sim_index, int tiling, std::vector<int4>& out) 
         for (int x0 = 0; x0 < s->p.nx; x0 += t.tx) out.push_back(make_int4(sim_index, x0, y0, 0));
 }
 
-// Chunks of 256 band nodes of one group for the band kernels: all nodes of a
-// fixed plan; none for a plan rebuilt on the device (k_ib gathers and applies
-// those bands itself).
+// Chunks of 256 band nodes of one group for the band kernels: the groups
+// whose correction workgroup does not gather and apply its band itself.
 void build_chunks(const GroupDev& d, int group_index, std::vector<int2>& out) {
-    if (d.dynamic) return;
+    if (d.in_kernel) return;
     for (int k = 0; k < d.nband; k += 256) out.push_back(make_int2(group_index, k));
 }
 
@@ -513,6 +509,7 @@ lbm_status rebuild_ib(lbm_sim* s) {
             }
         }
         d.ncolor = cord.empty() ? 0 : (int)coff.size() - 1;
+        d.in_kernel = d.dynamic || nband <= kFuseBandNodes ? 1 : 0;
         d.cap_nodes = std::max(1, nband);
         HIPS(s, G->node_cell.alloc(sizeof(int) * d.cap_nodes));
         HIPS(s, G->node_run.alloc(sizeof(int) * (d.cap_nodes + 1)));
@@ -1063,7 +1060,6 @@ lbm_status hipfailb(lbm_batch* b, hipError_t e, const char* where) {
 void drop_graphs(lbm_batch* b) {
     b->lane[0].drop();
     b->lane[1].drop();
-    b->drop_il();
 }
 
 // Copy the per-simulation step state (AA state, counters) of the device table
@@ -1192,7 +1188,7 @@ lbm_status upload_tables(lbm_batch* b) {
         std::vector<int2> chunks;
         for (size_t gi = 0; gi < groups.size(); ++gi) build_chunks(groups[gi], (int)gi, chunks);
         const int max_group = groups.empty() ? 0 : groups.front().M;
-        bool changed = ib_variant(b->f64, max_group) != ib_variant(b->f64, L.max_group);
+        bool changed = ib_variant(b->f64, max_group, il) != ib_variant(b->f64, L.max_group, il);
         L.max_group = max_group;
         bool mrt = false;
         for (int r = r0; r < r1; ++r) mrt = mrt || b->sims[b->order[r]]->h.collision != 0;
@@ -1238,10 +1234,7 @@ lbm_status upload_tables(lbm_batch* b) {
             HIPB(b, L.d_hdr.alloc(sizeof(BatchHeader)));
             grew = true;
         }
-        if (grew || changed || L.sim0 != r0) {
-            L.drop();
-            b->drop_il();
-        }
+        if (grew || changed || L.sim0 != r0) L.drop();
         L.sim0 = r0;
         if (!tl.empty()) HIPB(b, hipMemcpyAsync(L.d_tiles.p, tl.data(), sizeof(int4) * tl.size(), hipMemcpyHostToDevice, b->stream));
         if (!bc.empty()) HIPB(b, hipMemcpyAsync(L.d_bc.p, bc.data(), sizeof(int2) * bc.size(), hipMemcpyHostToDevice, b->stream));
@@ -1276,7 +1269,9 @@ hipError_t launch_kind(lbm_batch* b, int l, int k, hipStream_t st) {
         case 2:
             return launch_band(b->f64, false, sims, (const GroupDev*)L.d_groups.p, (const int2*)L.d_chunks.p, hdr, 0,
                                L.grid_band, -1, st);
-        case 3: return launch_ib(b->f64, L.max_group, sims, (GroupDev*)L.d_groups.p, hdr, 0, b->grid_ib, -1, st);
+        case 3:
+            return launch_ib(b->f64, L.max_group, sims, (GroupDev*)L.d_groups.p, hdr, 0, b->grid_ib, -1, st,
+                             b->interleave);
         case 4:
             return launch_band(b->f64, true, sims, (const GroupDev*)L.d_groups.p, (const int2*)L.d_chunks.p, hdr, 0,
                                L.grid_band, -1, st);
@@ -1327,35 +1322,37 @@ lbm_status ensure_lane_stream(lbm_batch* b) {
 // step t + 1 for lane 1's sweep of step t, so each lane's boundary rules and
 // correction run while the other lane's sweep streams (a lean correction
 // workgroup finds room on a CU beside sweep waves; a 768-thread one waits for
-// a whole CU).  Steps of both lanes, with these dependencies, are captured
-// into one graph (of 1 and of graphK_steps steps) spanning the two streams.
-hipError_t enqueue_interleaved(lbm_batch* b, int n) {
-    hipStream_t st[2] = {b->stream, b->stream2};
-    hipError_t e = hipEventRecord(b->ev_fork, st[0]);
-    if (e == hipSuccess) e = hipStreamWaitEvent(st[1], b->ev_fork, 0);
-    for (int t = 0; t < n && e == hipSuccess; ++t) {
-        if (t > 0) e = hipStreamWaitEvent(st[0], b->ev_sweep1, 0);
-        if (e == hipSuccess) e = launch_kind(b, 0, 0, st[0]);
-        if (e == hipSuccess) e = hipEventRecord(b->ev_sweep0, st[0]);
-        for (int k = 1; k < 6 && e == hipSuccess; ++k) e = launch_kind(b, 0, k, st[0]);
-        if (e == hipSuccess) e = hipStreamWaitEvent(st[1], b->ev_sweep0, 0);
-        if (e == hipSuccess) e = launch_kind(b, 1, 0, st[1]);
-        if (e == hipSuccess) e = hipEventRecord(b->ev_sweep1, st[1]);
-        for (int k = 1; k < 6 && e == hipSuccess; ++k) e = launch_kind(b, 1, k, st[1]);
-    }
-    if (e == hipSuccess) e = hipEventRecord(b->ev_join, st[1]);
-    if (e == hipSuccess) e = hipStreamWaitEvent(st[0], b->ev_join, 0);
-    return e;
-}
-
+// a whole CU).  Each lane replays two graphs per step, its sweep and the rest
+// of its step; the events that order the lanes are recorded and waited on
+// outside any capture.
 lbm_status run_interleaved(lbm_batch* b, int n) {
-    hipStream_t st0 = b->stream;
-    if (!b->il_graph1) HIPB(b, capture_fn(st0, [&]() { return enqueue_interleaved(b, 1); }, &b->il_graph1));
-    if (!b->il_graphK)
-        HIPB(b, capture_fn(st0, [&]() { return enqueue_interleaved(b, b->graphK_steps); }, &b->il_graphK));
-    int left = n;
-    for (; left >= b->graphK_steps; left -= b->graphK_steps) HIPB(b, hipGraphLaunch(b->il_graphK, st0));
-    for (; left > 0; --left) HIPB(b, hipGraphLaunch(b->il_graph1, st0));
+    hipStream_t st[2] = {b->stream, b->stream2};
+    for (int l = 0; l < 2; ++l) {
+        Lane& L = b->lane[l];
+        if (!L.graphA) HIPB(b, capture_fn(st[l], [&]() { return launch_kind(b, l, 0, st[l]); }, &L.graphA));
+        if (!L.graphB)
+            HIPB(b, capture_fn(st[l], [&]() {
+                for (int k = 1; k < 6; ++k) {
+                    hipError_t e = launch_kind(b, l, k, st[l]);
+                    if (e != hipSuccess) return e;
+                }
+                return hipSuccess;
+            }, &L.graphB));
+    }
+    HIPB(b, hipEventRecord(b->ev_fork, st[0]));
+    HIPB(b, hipStreamWaitEvent(st[1], b->ev_fork, 0));
+    for (int t = 0; t < n; ++t) {
+        if (t > 0) HIPB(b, hipStreamWaitEvent(st[0], b->ev_sweep1, 0));
+        HIPB(b, hipGraphLaunch(b->lane[0].graphA, st[0]));
+        HIPB(b, hipEventRecord(b->ev_sweep0, st[0]));
+        HIPB(b, hipGraphLaunch(b->lane[0].graphB, st[0]));
+        HIPB(b, hipStreamWaitEvent(st[1], b->ev_sweep0, 0));
+        HIPB(b, hipGraphLaunch(b->lane[1].graphA, st[1]));
+        HIPB(b, hipEventRecord(b->ev_sweep1, st[1]));
+        HIPB(b, hipGraphLaunch(b->lane[1].graphB, st[1]));
+    }
+    HIPB(b, hipEventRecord(b->ev_join, st[1]));
+    HIPB(b, hipStreamWaitEvent(st[0], b->ev_join, 0));
     return LBM_OK;
 }
 

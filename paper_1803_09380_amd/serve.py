@@ -32,13 +32,17 @@ class Request:
 class GpuExecutor:
     """Executor over lbmib.Batch (one precision, one HBM budget)."""
 
-    def __init__(self, precision, hbm_budget, tiling=None):
+    def __init__(self, precision, hbm_budget, tiling=None, lanes=None):
+        """lanes: the batch's lane mode (lbmib.Batch.set_lanes), None for the
+        library's choice."""
         from . import lbmib
         self.lbmib = lbmib
         self.batch = lbmib.Batch(precision, hbm_budget=hbm_budget)
         self.precision = precision
         if tiling is not None:
             self.batch.set_tiling(tiling)
+        if lanes is not None:
+            self.batch.set_lanes(lanes)
         self.live = {}
 
     def create(self, req):
