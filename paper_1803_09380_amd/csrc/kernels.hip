@@ -1177,8 +1177,9 @@ __device__ __forceinline__ void correct_node(const SimDev& S, int x, int y, int 
 
 // Steps 2-5 of a group's correction (gather, N sweeps on (rho, j), per-marker
 // totals of the sweeps) for one placement of its working arrays.  Groups with
-// fixed plans have their band records gathered beforehand (k_band_gather);
-// the final spread and correction of the populations is k_band_apply.
+// fixed plans have their band records gathered beforehand (gather_band in the
+// same workgroup, or k_band_gather for large bands); the final spread and
+// correction of the populations follow (apply_band, or k_band_apply).
 template <typename T, int NT, int MPT, bool CORE, bool EXTRA>
 __device__ __forceinline__ void correct_group(const SimDev& S, const GroupDev& G, const GroupLookup& L, Band<T> B,
                                               const T* phi_g, int M, int nband, int nent, int sw,
@@ -1199,9 +1200,19 @@ __device__ __forceinline__ void correct_group(const SimDev& S, const GroupDev& G
                 if (i < nent) stm<true>(B.ent16 + i, (unsigned short)ldm<false>(G.ent + i));
             }
         }
-        if (!G.dynamic)  // band records gathered by k_band_gather
-            for (int k = tid; k < nband; k += NT)
-                stm<true>(reinterpret_cast<nv4<T>*>(B.node) + k, ldm<false>(reinterpret_cast<const nv4<T>*>(G.node4) + k));
+        if (!G.dynamic) {  // band records gathered by gather_band or k_band_gather; four in flight
+            const nv4<T>* src = reinterpret_cast<const nv4<T>*>(G.node4);
+            nv4<T>* dst = reinterpret_cast<nv4<T>*>(B.node);
+            for (int k0 = tid; k0 < nband; k0 += 4 * NT) {
+                nv4<T> rec[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    if (k0 + u * NT < nband) rec[u] = ldm<false>(src + k0 + u * NT);
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    if (k0 + u * NT < nband) stm<true>(dst + k0 + u * NT, rec[u]);
+            }
+        }
     }
     IB_MARK(2);
     // gather (rho, j) of a rebuilt band from the post-stream populations, four
@@ -1419,25 +1430,32 @@ __device__ __forceinline__ void correct_group_col(const SimDev& S, const GroupDe
                                                   int gi) {
     const int tid = threadIdx.x;
     const nv4<T>* node4 = reinterpret_cast<const nv4<T>*>(G.node4);
-    const int len = max(nband, M);
-    for (int i = tid; i < len; i += NT) {
-        if (i < nband) {
-            const nv4<T> rec = ldm<false>(node4 + i);
-            nv2<T> jj;
-            jj.x = rec.z;
-            jj.y = rec.w;
-            stm<true>(B.inv + i, rec.y);
-            stm<true>(B.j + i, jj);
+    // band records into LDS, four per thread in flight
+    for (int i0 = tid; i0 < nband; i0 += 4 * NT) {
+        nv4<T> rec[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (i0 + u * NT < nband) rec[u] = ldm<false>(node4 + i0 + u * NT);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int i = i0 + u * NT;
+            if (i < nband) {
+                nv2<T> jj;
+                jj.x = rec[u].z;
+                jj.y = rec[u].w;
+                stm<true>(B.inv + i, rec[u].y);
+                stm<true>(B.j + i, jj);
+            }
         }
-        if (i < M) {
-            const int g = ldm<false>(G.cord + i);
-            const nv4<T>* src = reinterpret_cast<const nv4<T>*>(phi_g + g * 8);
-            nv4<T>* dst = reinterpret_cast<nv4<T>*>(B.phi + i * 8);
-            stm<true>(dst, ldm<false>(src));
-            stm<true>(dst + 1, ldm<false>(src + 1));
-            stm<true>(reinterpret_cast<nv2<unsigned>*>(B.rows + i * 4),
-                      ldm<false>(reinterpret_cast<const nv2<unsigned>*>(G.m_rows) + g));
-        }
+    }
+    for (int i = tid; i < M; i += NT) {
+        const int g = ldm<false>(G.cord + i);
+        const nv4<T>* src = reinterpret_cast<const nv4<T>*>(phi_g + g * 8);
+        nv4<T>* dst = reinterpret_cast<nv4<T>*>(B.phi + i * 8);
+        stm<true>(dst, ldm<false>(src));
+        stm<true>(dst + 1, ldm<false>(src + 1));
+        stm<true>(reinterpret_cast<nv2<unsigned>*>(B.rows + i * 4),
+                  ldm<false>(reinterpret_cast<const nv2<unsigned>*>(G.m_rows) + g));
     }
     IB_MARK(2);
     // the thread's markers g = tid + q NT and their positions
@@ -1622,20 +1640,14 @@ __device__ bool correct_free_lds(const SimDev& S, const GroupDev& G, const Group
     const int x0 = bbox[0], y0 = bbox[1];
     const long W = (long)bbox[2] - x0 + 1, H = (long)bbox[3] - y0 + 1;
     const long ncell_l = W * H;
-    // band nodes: at most one per cell and per entry
-    const long nbmax = ncell_l < NE ? ncell_l : NE;
-    unsigned short* run16 = reinterpret_cast<unsigned short*>(bp.take(2L * (nbmax + 1)));
-    int* cells = reinterpret_cast<int*>(bp.take(4L * nbmax));
-    // the counts and fill positions of the plan build share their space with
-    // the band records of the sweeps
-    const long plan_bytes = 8L * ncell_l, rec_bytes = 4L * nbmax * (long)sizeof(T);
-    char* shared = reinterpret_cast<char*>(bp.take(plan_bytes > rec_bytes ? plan_bytes : rec_bytes));
-    if (x0 < 0 || y0 < 0 || bbox[2] >= S.nx || bbox[3] >= S.ny || ncell_l > kBinCells || !run16 || !cells ||
-        !shared)
-        return false;
+    // per box cell: the count of entries, then the band node (-1 for none);
+    // the first entry, then the fill position.  The band records of the
+    // sweeps take this space over once the plan is built, when they fit.
+    char* plan = reinterpret_cast<char*>(bp.take(8L * ncell_l));
+    if (x0 < 0 || y0 < 0 || bbox[2] >= S.nx || bbox[3] >= S.ny || ncell_l > kBinCells || !plan) return false;
     const int ncell = (int)ncell_l, Wi = (int)W;
-    int* count = reinterpret_cast<int*>(shared);  // per box cell: entries, then band node
-    int* start = count + ncell;                   // per box cell: first entry, then fill position
+    int* count = reinterpret_cast<int*>(plan);
+    int* start = count + ncell;
     for (int c = tid; c < ncell; c += NT) count[c] = 0;
     __syncthreads();
     for (int e = tid; e < NE; e += NT) {
@@ -1655,13 +1667,22 @@ __device__ bool correct_free_lds(const SimDev& S, const GroupDev& G, const Group
     for (int c = c0; c < c1; ++c) {
         const int n = count[c];
         start[c] = ebase;
-        if (n > 0) {
-            cells[nbase] = c;
-            run16[nbase] = (unsigned short)ebase;
-            count[c] = nbase;
-            ++nbase;
-        }
+        count[c] = n > 0 ? nbase++ : -1;
         ebase += n;
+    }
+    // the band's arrays, sized now that the band is known (the same on every thread)
+    unsigned short* run16 = reinterpret_cast<unsigned short*>(bp.take(2L * (nband + 1)));
+    int* cells = reinterpret_cast<int*>(bp.take(4L * nband));
+    const long rec_bytes = 4L * nband * (long)sizeof(T);
+    T* node = rec_bytes <= 8L * ncell_l ? reinterpret_cast<T*>(plan) : reinterpret_cast<T*>(bp.take(rec_bytes));
+    if (!run16 || !cells || !node) return false;
+    __syncthreads();
+    for (int c = c0; c < c1; ++c) {
+        const int k = count[c];
+        if (k >= 0) {
+            cells[k] = c;
+            run16[k] = (unsigned short)start[c];
+        }
     }
     if (tid == 0) run16[nband] = (unsigned short)NE;
     __syncthreads();
@@ -1693,9 +1714,8 @@ __device__ bool correct_free_lds(const SimDev& S, const GroupDev& G, const Group
     }
     __syncthreads();
     IB_MARK(2);
-    // band records from the post-stream populations (over the counts, which
-    // are no longer needed), four nodes per thread in flight
-    T* node = reinterpret_cast<T*>(shared);
+    // band records from the post-stream populations (over the counts when
+    // they fit there), four nodes per thread in flight
     const T rho_base = T(S.rho_base);
     for (int k0 = tid; k0 < nband; k0 += 4 * NT) {
         T h[4][9];

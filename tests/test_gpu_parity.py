@@ -173,6 +173,30 @@ def test_far_apart_particles_sort_based_plan_fp32():
     check_fp32_velocity(g.fields(), o.fields())
 
 
+def _particle_across_periodic_seam(precision):
+    """A free circle straddling the x = 0 seam of a periodic box: its stencil
+    box wraps, so the correction rebuilds the plan by the binned path (the
+    in-workgroup plan takes only boxes inside the lattice)."""
+    case = wl.settling(nx=48, ny=64, D=10.0, density_ratio=1.3, two=False, precision=precision,
+                       lower=(1.5, 32.0), u_ref=0.05)
+    case["bc"] = (wl.PERIODIC,) * 4
+    return case
+
+
+def test_particle_across_periodic_seam_f64():
+    _say("free particle across a periodic seam f64, 60 steps")
+    _compare_case(_particle_across_periodic_seam(wl.F64), 60, check_state=True)
+
+
+def test_particle_across_periodic_seam_fp32():
+    _say("free particle across a periodic seam f32, 60 steps")
+    case = _particle_across_periodic_seam(wl.F32)
+    o, g = oracle_from_case(case), gpu_from_case(case, precision=lbmib.F32_SHIFTED)
+    o.step(60)
+    g.step(60)
+    check_fp32_velocity(g.fields(), o.fields())
+
+
 def test_particle_near_wall_collision_f64():
     """A particle close to a wall: stencils cut by the wall and the mirror
     collision force of Eq. 39 act."""
