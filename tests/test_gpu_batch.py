@@ -58,6 +58,28 @@ def test_batch_equals_alone_bitwise(steps):
         _same(_state(s, len(c["bodies"])), ref)
 
 
+def test_batch_with_band_kernels_equals_alone_bitwise():
+    """A member whose fixed plan is large enough for the band kernels (the
+    603-marker circle of Couette 256: about 2,400 band nodes) beside members
+    corrected entirely inside their workgroups: the same bits as alone."""
+    _say("batch with band kernels vs alone, 11 steps")
+    cases = [wl.couette(256, precision=wl.F32)] + _cases()[:2]
+    alone = []
+    for c in cases:
+        s = gpu_from_case(c, precision=lbmib.F32_SHIFTED)
+        s.step(11)
+        alone.append(_state(s, len(c["bodies"])))
+    sims = [gpu_from_case(c, precision=lbmib.F32_SHIFTED) for c in cases]
+    b = lbmib.Batch(lbmib.F32_SHIFTED)
+    for s in sims:
+        assert b.admit(s)
+    b.step(11)
+    b.sync()
+    for s, c, ref in zip(sims, cases, alone):
+        assert s.step_count == 11
+        _same(_state(s, len(c["bodies"])), ref)
+
+
 def test_batch_mixes_bgk_and_mrt_members():
     _say("batch with BGK and MRT members")
     cases = _cases()
