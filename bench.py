@@ -335,6 +335,34 @@ def mrt_leg(args, cases, lbmib, wl, torch, tiling, lanes):
             "rates": "s_e 1.1, s_eps 1.25, s_q 1.8, s_nu 1/tau"}
 
 
+def served_steady_leg(args, lbmib, wl, torch, steps):
+    """The first eight requests of the overload leg stepped together with no
+    arrivals or retirements: one lane, and two interleaved halves of equal
+    node count (lane mode 4), whose corrections run beside each other's
+    sweeps."""
+    arr = wl.arrivals(seed=args.seed + 1, rate=20.0, count=max(8, args.serve_overload), steps=10 * args.serve_steps)
+    cases = [r["case"] for r in arr[:8]]
+    cells = sum(c["nx"] * c["ny"] for c in cases)
+    sims = [lbmib.Sim.from_case(c, precision=lbmib.F32_SHIFTED) for c in cases]
+    b = lbmib.Batch(lbmib.F32_SHIFTED)
+    for s in sims:
+        assert b.admit(s)
+    out = {"requests": 8, "nodes": cells, "steps": steps}
+    for lanes, key in ((1, "one_lane"), (4, "two_interleaved_halves")):
+        b.set_lanes(lanes)
+        b.step(10)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        b.step(steps)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        out[key] = {"mlups": round(cells * steps / wall / 1e6, 1), "ms_per_step": round(wall / steps * 1e3, 4)}
+    b.close()
+    for s in sims:
+        s.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -365,6 +393,10 @@ def main():
     ap.add_argument("--serve-steps", type=int, default=2000)
     ap.add_argument("--serve-overload", type=int, default=16,
                     help="requests of the overload leg (10x the steps, HBM budget of 8 requests; 0 skips it)")
+    ap.add_argument("--served-steady-steps", type=int, default=200,
+                    help="steps of the served steady-state leg (0 skips it)")
+    ap.add_argument("--only-served-steady", action="store_true",
+                    help="run the served steady-state leg alone (for profiler runs)")
     ap.add_argument("--only-batch", action="store_true",
                     help="time the batched set only (for profiler runs): no CPU baseline, FP64 sample, "
                          "accuracy or serving legs")
@@ -379,9 +411,17 @@ def main():
         sys.exit(2)
 
     from paper_1803_09380_amd import workloads as wl
+    if args.only_served_steady:
+        import torch
+        from paper_1803_09380_amd import lbmib
+        torch.cuda.init()
+        print(json.dumps({"served_steady": served_steady_leg(args, lbmib, wl, torch, args.served_steady_steps)}),
+              flush=True)
+        return
     cases = wl.batch(seed=args.seed, count=args.sims, precision=wl.F32)
 
     if args.only_batch:
+        args.served_steady_steps = 0
         args.no_cpu = True
         args.fp64_sample = 0
         args.serve_requests = 0
@@ -494,6 +534,11 @@ def main():
                          "lattice": "400x4000 closed box", "steps_per_request": 10 * args.serve_steps,
                          "hbm_budget_bytes": budget, "budget_requests": 8})
 
+    # ---- the overload leg's mix in steady state, one lane and two interleaved halves
+    served_steady = None
+    if args.served_steady_steps > 0:
+        served_steady = served_steady_leg(args, lbmib, wl, torch, args.served_steady_steps)
+
     # ---- measured HBM copy (hand-written 16-byte copies and torch's) beside the datasheet peak
     copy = None
     if not args.only_batch:
@@ -557,6 +602,7 @@ def main():
         "unstable_members": unstable,
         "serving": serving,
         "serving_overload": overload,
+        "served_steady": served_steady,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
