@@ -438,87 +438,91 @@ __device__ __forceinline__ T heq_i(int i, T S_, T rho, T jx, T jy) {
              (double(S_) + 3.0 * ej + (4.5 * ej * ej - 1.5 * (jxd * jxd + jyd * jyd)) / double(rho)));
 }
 
+// Boundary rules of one item (simulation item.x, boundary nodes item.y ..
+// item.y + 255), node item.y + t for thread t of the 256 serving the item.
+template <typename T>
+__device__ __forceinline__ void boundary_item(const SimDev* __restrict__ sims, int2 item, int t, int parity) {
+    const SimDev& S = sims[item.x];
+    if (!S.active) return;
+    const int k = item.y + t;
+    if (k >= S.nperim) return;
+    const int sw = 1 - (parity >= 0 ? parity : S.swapped);  // state after this step's sweep
+    const int nx = S.nx, ny = S.ny;
+    int x, y;
+    if (S.bc[SIDE_W] == BC_DIRICHLET) {
+        perim_node(S, k, x, y);
+        // prescribed velocity: non-equilibrium extrapolation from the inward
+        // neighbour (diagonal at corners), which is interior on both axes
+        const int xn = x < 1 ? 1 : (x > nx - 2 ? nx - 2 : x);
+        const int yn = y < 1 ? 1 : (y > ny - 2 ? ny - 2 : y);
+        T fn[9];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) fn[i] = ldm<false>(pc<T>(S, i, xn - ex_of(i), yn - ey_of(i), sw));
+        const T Sn = ((fn[0] + fn[1]) + (fn[2] + fn[3])) + ((fn[4] + fn[5]) + (fn[6] + fn[7])) + fn[8];
+        const T jxn = (fn[1] + fn[5] + fn[8]) - (fn[3] + fn[6] + fn[7]);
+        const T jyn = (fn[2] + fn[5] + fn[6]) - (fn[4] + fn[7] + fn[8]);
+        const T rhon = T(S.rho_base) + Sn;
+        const T jxb = rhon * T(ldm<false>(S.ubound + 2 * k)), jyb = rhon * T(ldm<false>(S.ubound + 2 * k + 1));
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            const T v = heq_i<T>(i, Sn, rhon, jxb, jyb) + (fn[i] - heq_i<T>(i, Sn, rhon, jxn, jyn));
+            stm<false>(loc<T>(S, i, x, y, sw), v);
+        }
+        return;
+    }
+    // inlet column (west) first, then the outlet column (east)
+    const bool inlet = S.bc[SIDE_W] == BC_VELOCITY;
+    x = inlet && k < ny ? 0 : nx - 1;
+    y = inlet && k >= ny ? k - ny : k;
+    if (x == 0) {
+        // non-equilibrium extrapolation from column 1 (every population)
+        T f1[9];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) f1[i] = post_stream<T>(S, i, 1, y, sw);
+        const T S1 = ((f1[0] + f1[1]) + (f1[2] + f1[3])) + ((f1[4] + f1[5]) + (f1[6] + f1[7])) + f1[8];
+        const T jx1 = (f1[1] + f1[5] + f1[8]) - (f1[3] + f1[6] + f1[7]);
+        const T jy1 = (f1[2] + f1[5] + f1[6]) - (f1[4] + f1[7] + f1[8]);
+        const T rho1 = T(S.rho_base) + S1;
+        const T jxb = rho1 * T(S.u_in[0]), jyb = rho1 * T(S.u_in[1]);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            const T v = heq_i<T>(i, S1, rho1, jxb, jyb) + (f1[i] - heq_i<T>(i, S1, rho1, jx1, jy1));
+            stm<false>(loc<T>(S, i, 0, y, sw), v);
+        }
+        return;
+    }
+    if (S.bc[SIDE_E] == BC_PRESSURE) {
+        // non-equilibrium extrapolation from column nx-2 at density rho0
+        T f2[9];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) f2[i] = post_stream<T>(S, i, nx - 2, y, sw);
+        const T S2 = ((f2[0] + f2[1]) + (f2[2] + f2[3])) + ((f2[4] + f2[5]) + (f2[6] + f2[7])) + f2[8];
+        const T jx2 = (f2[1] + f2[5] + f2[8]) - (f2[3] + f2[6] + f2[7]);
+        const T jy2 = (f2[2] + f2[5] + f2[6]) - (f2[4] + f2[7] + f2[8]);
+        const T rho2 = T(S.rho_base) + S2;
+        const T rhob = T(S.rho0), Sb = T(S.rho0 - S.rho_base);
+        const T jxb = rhob * (jx2 / rho2), jyb = rhob * (jy2 / rho2);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            const T v = heq_i<T>(i, Sb, rhob, jxb, jyb) + (f2[i] - heq_i<T>(i, S2, rho2, jx2, jy2));
+            stm<false>(loc<T>(S, i, nx - 1, y, sw), v);
+        }
+        return;
+    }
+    // zero-gradient outlet: the populations entering from the east copy the
+    // post-stream values of column nx-2
+#pragma unroll
+    for (int i = 1; i < 9; ++i)
+        if (ex_of(i) < 0) stm<false>(loc<T>(S, i, nx - 1, y, sw), post_stream<T>(S, i, nx - 2, y, sw));
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256)
     k_boundary(const SimDev* __restrict__ sims, const int2* __restrict__ items,
                const BatchHeader* __restrict__ hdr, int nitems_arg, int parity) {
     raise_wave_priority();
     const int nitems = hdr ? hdr->nbc : nitems_arg;
-    for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
-        const int2 item = items[it];
-        const SimDev& S = sims[item.x];
-        if (!S.active) continue;
-        const int k = item.y + threadIdx.x;
-        if (k >= S.nperim) continue;
-        const int sw = 1 - (parity >= 0 ? parity : S.swapped);  // state after this step's sweep
-        const int nx = S.nx, ny = S.ny;
-        int x, y;
-        if (S.bc[SIDE_W] == BC_DIRICHLET) {
-            perim_node(S, k, x, y);
-            // prescribed velocity: non-equilibrium extrapolation from the inward
-            // neighbour (diagonal at corners), which is interior on both axes
-            const int xn = x < 1 ? 1 : (x > nx - 2 ? nx - 2 : x);
-            const int yn = y < 1 ? 1 : (y > ny - 2 ? ny - 2 : y);
-            T fn[9];
-#pragma unroll
-            for (int i = 0; i < 9; ++i) fn[i] = ldm<false>(pc<T>(S, i, xn - ex_of(i), yn - ey_of(i), sw));
-            const T Sn = ((fn[0] + fn[1]) + (fn[2] + fn[3])) + ((fn[4] + fn[5]) + (fn[6] + fn[7])) + fn[8];
-            const T jxn = (fn[1] + fn[5] + fn[8]) - (fn[3] + fn[6] + fn[7]);
-            const T jyn = (fn[2] + fn[5] + fn[6]) - (fn[4] + fn[7] + fn[8]);
-            const T rhon = T(S.rho_base) + Sn;
-            const T jxb = rhon * T(ldm<false>(S.ubound + 2 * k)), jyb = rhon * T(ldm<false>(S.ubound + 2 * k + 1));
-#pragma unroll
-            for (int i = 0; i < 9; ++i) {
-                const T v = heq_i<T>(i, Sn, rhon, jxb, jyb) + (fn[i] - heq_i<T>(i, Sn, rhon, jxn, jyn));
-                stm<false>(loc<T>(S, i, x, y, sw), v);
-            }
-            continue;
-        }
-        // inlet column (west) first, then the outlet column (east)
-        const bool inlet = S.bc[SIDE_W] == BC_VELOCITY;
-        x = inlet && k < ny ? 0 : nx - 1;
-        y = inlet && k >= ny ? k - ny : k;
-        if (x == 0) {
-            // non-equilibrium extrapolation from column 1 (every population)
-            T f1[9];
-#pragma unroll
-            for (int i = 0; i < 9; ++i) f1[i] = post_stream<T>(S, i, 1, y, sw);
-            const T S1 = ((f1[0] + f1[1]) + (f1[2] + f1[3])) + ((f1[4] + f1[5]) + (f1[6] + f1[7])) + f1[8];
-            const T jx1 = (f1[1] + f1[5] + f1[8]) - (f1[3] + f1[6] + f1[7]);
-            const T jy1 = (f1[2] + f1[5] + f1[6]) - (f1[4] + f1[7] + f1[8]);
-            const T rho1 = T(S.rho_base) + S1;
-            const T jxb = rho1 * T(S.u_in[0]), jyb = rho1 * T(S.u_in[1]);
-#pragma unroll
-            for (int i = 0; i < 9; ++i) {
-                const T v = heq_i<T>(i, S1, rho1, jxb, jyb) + (f1[i] - heq_i<T>(i, S1, rho1, jx1, jy1));
-                stm<false>(loc<T>(S, i, 0, y, sw), v);
-            }
-            continue;
-        }
-        if (S.bc[SIDE_E] == BC_PRESSURE) {
-            // non-equilibrium extrapolation from column nx-2 at density rho0
-            T f2[9];
-#pragma unroll
-            for (int i = 0; i < 9; ++i) f2[i] = post_stream<T>(S, i, nx - 2, y, sw);
-            const T S2 = ((f2[0] + f2[1]) + (f2[2] + f2[3])) + ((f2[4] + f2[5]) + (f2[6] + f2[7])) + f2[8];
-            const T jx2 = (f2[1] + f2[5] + f2[8]) - (f2[3] + f2[6] + f2[7]);
-            const T jy2 = (f2[2] + f2[5] + f2[6]) - (f2[4] + f2[7] + f2[8]);
-            const T rho2 = T(S.rho_base) + S2;
-            const T rhob = T(S.rho0), Sb = T(S.rho0 - S.rho_base);
-            const T jxb = rhob * (jx2 / rho2), jyb = rhob * (jy2 / rho2);
-#pragma unroll
-            for (int i = 0; i < 9; ++i) {
-                const T v = heq_i<T>(i, Sb, rhob, jxb, jyb) + (f2[i] - heq_i<T>(i, S2, rho2, jx2, jy2));
-                stm<false>(loc<T>(S, i, nx - 1, y, sw), v);
-            }
-            continue;
-        }
-        // zero-gradient outlet: the populations entering from the east copy the
-        // post-stream values of column nx-2
-#pragma unroll
-        for (int i = 1; i < 9; ++i)
-            if (ex_of(i) < 0) stm<false>(loc<T>(S, i, nx - 1, y, sw), post_stream<T>(S, i, nx - 2, y, sw));
-    }
+    for (int it = blockIdx.x; it < nitems; it += gridDim.x) boundary_item<T>(sims, items[it], threadIdx.x, parity);
 }
 
 // ---------------------------------------------------------------- correction sweeps
@@ -1878,10 +1882,14 @@ __device__ void apply_band(const SimDev& S, const GroupDev& G, int nband, int sw
 
 // The correction of every group of a launch, one workgroup per group at a
 // time (k_ib and k_ib_lean).
+// bc_items (batches): the lane's boundary items (hdr->nbc of them), taken by
+// every workgroup after its groups, 256 threads per item, when no band of the
+// lane comes near a non-periodic side (the rules and the correction then touch
+// disjoint populations); nullptr: none.
 template <typename T, int NT, int MPT>
 __device__ __forceinline__ void ib_groups(const SimDev* __restrict__ sims, GroupDev* __restrict__ groups,
                                           const BatchHeader* __restrict__ hdr, int ngroups_arg, int parity,
-                                          char* arena, int arena_bytes) {
+                                          char* arena, int arena_bytes, const int2* __restrict__ bc_items) {
     __shared__ double part[4 * 5];
     __shared__ int scan_tmp[NT];
     __shared__ double body_out[8][5];
@@ -2128,14 +2136,20 @@ __device__ __forceinline__ void ib_groups(const SimDev* __restrict__ sims, Group
         __syncthreads();
         IB_MARK(27);
     }
+    if (bc_items) {
+        constexpr int per = NT / 256;  // items per workgroup and round
+        const int nbc = hdr->nbc;
+        for (int it = blockIdx.x * per + tid / 256; it < nbc; it += gridDim.x * per)
+            boundary_item<T>(sims, bc_items[it], tid % 256, parity);
+    }
 }
 
 template <typename T, int NT, int MPT>
 __global__ void __launch_bounds__(NT)
     k_ib(const SimDev* __restrict__ sims, GroupDev* __restrict__ groups, const BatchHeader* __restrict__ hdr,
-         int ngroups_arg, int parity) {
+         int ngroups_arg, int parity, const int2* bc_items) {
     __shared__ __align__(16) char arena[kIbArenaBytes];
-    ib_groups<T, NT, MPT>(sims, groups, hdr, ngroups_arg, parity, arena, kIbArenaBytes);
+    ib_groups<T, NT, MPT>(sims, groups, hdr, ngroups_arg, parity, arena, kIbArenaBytes, bc_items);
 }
 
 // One wave per SIMD and at most 128 VGPRs: a workgroup of this form finds room
@@ -2146,9 +2160,9 @@ __global__ void __launch_bounds__(NT)
 template <typename T, int MPT>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8)))
     k_ib_lean(const SimDev* __restrict__ sims, GroupDev* __restrict__ groups, const BatchHeader* __restrict__ hdr,
-              int ngroups_arg, int parity) {
+              int ngroups_arg, int parity, const int2* bc_items) {
     extern __shared__ __align__(16) char lean_arena[];  // kIbLeanArenaBytes at launch
-    ib_groups<T, 256, MPT>(sims, groups, hdr, ngroups_arg, parity, lean_arena, kIbLeanArenaBytes);
+    ib_groups<T, 256, MPT>(sims, groups, hdr, ngroups_arg, parity, lean_arena, kIbLeanArenaBytes, bc_items);
 }
 
 // ---------------------------------------------------------------- bookkeeping and I/O
@@ -2351,20 +2365,21 @@ hipError_t launch_boundary(bool f64, const SimDev* sims, const int2* items, cons
 
 template <typename T, int NT, int MPT>
 static hipError_t ib_t(const SimDev* sims, GroupDev* groups, const BatchHeader* hdr, int ngroups, int grid,
-                       int parity, hipStream_t stream) {
-    hipLaunchKernelGGL((k_ib<T, NT, MPT>), dim3(grid), dim3(NT), 0, stream, sims, groups, hdr, ngroups, parity);
+                       int parity, hipStream_t stream, const int2* bc_items) {
+    hipLaunchKernelGGL((k_ib<T, NT, MPT>), dim3(grid), dim3(NT), 0, stream, sims, groups, hdr, ngroups, parity,
+                       bc_items);
     return hipGetLastError();
 }
 
 template <typename T, int MPT>
 static hipError_t ib_lean_t(const SimDev* sims, GroupDev* groups, const BatchHeader* hdr, int ngroups, int grid,
-                            int parity, hipStream_t stream) {
+                            int parity, hipStream_t stream, const int2* bc_items) {
     static const hipError_t attr =
         hipFuncSetAttribute(reinterpret_cast<const void*>(&k_ib_lean<T, MPT>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, kIbLeanArenaBytes);
     if (attr != hipSuccess) return attr;
     hipLaunchKernelGGL((k_ib_lean<T, MPT>), dim3(grid), dim3(256), kIbLeanArenaBytes, stream, sims, groups, hdr,
-                       ngroups, parity);
+                       ngroups, parity, bc_items);
     return hipGetLastError();
 }
 
@@ -2374,16 +2389,19 @@ int ib_variant(bool f64, int max_markers, bool lean) {
 }
 
 hipError_t launch_ib(bool f64, int max_markers, const SimDev* sims, GroupDev* groups, const BatchHeader* hdr,
-                     int ngroups, int grid, int parity, hipStream_t stream, bool lean) {
+                     int ngroups, int grid, int parity, hipStream_t stream, bool lean, const int2* bc_items) {
+    if (bc_items && !hdr) return hipErrorInvalidValue;  // the item count comes from the header
     if (grid <= 0) return hipSuccess;
     if (max_markers > kMaxGroupMarkers) return hipErrorInvalidValue;
     // each thread keeps up to MPT markers' running sums in registers
     if (f64)
-        return max_markers <= 8 * 256 ? ib_t<double, 256, 8>(sims, groups, hdr, ngroups, grid, parity, stream)
-                                      : ib_t<double, 256, 16>(sims, groups, hdr, ngroups, grid, parity, stream);
-    if (lean && max_markers <= 256) return ib_lean_t<float, 1>(sims, groups, hdr, ngroups, grid, parity, stream);
-    return max_markers <= 3 * 768 ? ib_t<float, 768, 3>(sims, groups, hdr, ngroups, grid, parity, stream)
-                                  : ib_t<float, 512, 8>(sims, groups, hdr, ngroups, grid, parity, stream);
+        return max_markers <= 8 * 256
+                   ? ib_t<double, 256, 8>(sims, groups, hdr, ngroups, grid, parity, stream, bc_items)
+                   : ib_t<double, 256, 16>(sims, groups, hdr, ngroups, grid, parity, stream, bc_items);
+    if (lean && max_markers <= 256)
+        return ib_lean_t<float, 1>(sims, groups, hdr, ngroups, grid, parity, stream, bc_items);
+    return max_markers <= 3 * 768 ? ib_t<float, 768, 3>(sims, groups, hdr, ngroups, grid, parity, stream, bc_items)
+                                  : ib_t<float, 512, 8>(sims, groups, hdr, ngroups, grid, parity, stream, bc_items);
 }
 
 hipError_t launch_band(bool f64, bool apply, const SimDev* sims, const GroupDev* groups, const int2* chunks,

@@ -41,8 +41,12 @@ hipError_t launch_boundary(bool f64, const SimDev* sims, const int2* items, cons
 // each thread carries; the results do not depend on it).  lean: FP32 groups of
 // at most 256 markers run in the 256-thread kernel that fits beside sweep
 // waves (for lanes whose corrections overlap another lane's sweep).
+// bc_items (with hdr): the lane's boundary items, applied by the correction
+// workgroups after their groups in place of launch_boundary (only when no band
+// of the lane comes within three nodes of a non-periodic side).
 hipError_t launch_ib(bool f64, int max_markers, const SimDev* sims, GroupDev* groups, const BatchHeader* hdr,
-                     int ngroups, int grid, int parity, hipStream_t stream, bool lean = false);
+                     int ngroups, int grid, int parity, hipStream_t stream, bool lean = false,
+                     const int2* bc_items = nullptr);
 // Band kernels over chunks of 256 band nodes (group, first node): apply =
 // false gathers the band records of fixed-plan groups before k_ib, apply =
 // true spreads the per-marker totals and corrects the populations after it.

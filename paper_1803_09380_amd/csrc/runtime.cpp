@@ -117,6 +117,9 @@ struct Lane {
     int max_group = 0;
     int grid_sweep = 0, grid_band = 0;
     bool mrt = false;  // some simulation of the lane uses the MRT collision
+    // the correction launch applies the boundary rules too (boundary items, body
+    // groups, and no band within three nodes of a non-periodic side)
+    bool bnd_in_ib = false;
     hipGraphExec_t graph1 = nullptr, graphK = nullptr;
     hipGraphExec_t graphA = nullptr, graphB = nullptr;  // one step split: the sweep, the rest (run_interleaved)
     void drop() {
@@ -1190,10 +1193,16 @@ lbm_status upload_tables(lbm_batch* b) {
         const int max_group = groups.empty() ? 0 : groups.front().M;
         bool changed = ib_variant(b->f64, max_group, il) != ib_variant(b->f64, L.max_group, il);
         L.max_group = max_group;
-        bool mrt = false;
-        for (int r = r0; r < r1; ++r) mrt = mrt || b->sims[b->order[r]]->h.collision != 0;
+        bool mrt = false, near_edge = false;
+        for (int r = r0; r < r1; ++r) {
+            mrt = mrt || b->sims[b->order[r]]->h.collision != 0;
+            near_edge = near_edge || b->sims[b->order[r]]->band_near_edge;
+        }
         changed = changed || mrt != L.mrt;
         L.mrt = mrt;
+        const bool bnd_in_ib = !bc.empty() && !groups.empty() && !near_edge;
+        changed = changed || bnd_in_ib != L.bnd_in_ib;
+        L.bnd_in_ib = bnd_in_ib;
         BatchHeader h{};
         h.nsims = r1 - r0;
         h.nbc = (int)bc.size();
@@ -1260,8 +1269,10 @@ hipError_t launch_kind(lbm_batch* b, int l, int k, hipStream_t st) {
     SimDev* sims = (SimDev*)b->d_sims.p;
     const BatchHeader* hdr = (const BatchHeader*)L.d_hdr.p;
     // kinds with no work in the lane are not launched (upload_tables drops
-    // the captured graphs when that changes)
-    if ((k == 1 && L.nbc == 0) || ((k == 2 || k == 4) && L.nchunks == 0) || (k == 3 && L.ngroups == 0))
+    // the captured graphs when that changes); the boundary rules ride on the
+    // correction launch when they cannot touch a band
+    if ((k == 1 && (L.nbc == 0 || L.bnd_in_ib)) || ((k == 2 || k == 4) && L.nchunks == 0) ||
+        (k == 3 && L.ngroups == 0))
         return hipSuccess;
     switch (k) {
         case 0: return launch_sweep(b->f64, L.mrt, b->tiling, sims, (const int4*)L.d_tiles.p, hdr, 0, L.grid_sweep, -1, st);
@@ -1271,7 +1282,7 @@ hipError_t launch_kind(lbm_batch* b, int l, int k, hipStream_t st) {
                                L.grid_band, -1, st);
         case 3:
             return launch_ib(b->f64, L.max_group, sims, (GroupDev*)L.d_groups.p, hdr, 0, b->grid_ib, -1, st,
-                             b->interleave);
+                             b->interleave, L.bnd_in_ib ? (const int2*)L.d_bc.p : nullptr);
         case 4:
             return launch_band(b->f64, true, sims, (const GroupDev*)L.d_groups.p, (const int2*)L.d_chunks.p, hdr, 0,
                                L.grid_band, -1, st);
