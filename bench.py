@@ -453,7 +453,7 @@ def main():
         batch.set_lanes(args.lanes)
     tiling = args.tiling
     if args.tiling < 0 and not args.no_autotune:
-        tiling = batch.autotune(trials=3)
+        tiling = batch.autotune(trials=10)
     lanes = batch.lanes
     batch.step(args.warmup)
     torch.cuda.synchronize()

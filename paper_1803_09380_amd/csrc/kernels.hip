@@ -286,25 +286,16 @@ template <typename T, bool MRT>
 constexpr int kSweepMinWaves = MRT ? 1 : (sizeof(T) == 4 ? 7 : 6);
 
 // Tile range of workgroup blockIdx.x: with a batch header and a grid that is a
-// multiple of 8, the tiles dealt to its XCD (part 0 or 1: the first or second
-// half of them); otherwise a grid-stride loop over every tile.
-__device__ __forceinline__ void tile_range(const BatchHeader* hdr, int ntiles_arg, int part, int& t0, int& t1,
-                                           int& dt) {
+// multiple of 8, the tiles dealt to its XCD; otherwise a grid-stride loop over
+// every tile.
+__device__ __forceinline__ void tile_range(const BatchHeader* hdr, int ntiles_arg, int& t0, int& t1, int& dt) {
     t0 = blockIdx.x;
     t1 = hdr ? hdr->ntiles : ntiles_arg;
     dt = gridDim.x;
     if (hdr && (gridDim.x & 7) == 0) {
         const int xcd = blockIdx.x & 7;
-        int s = hdr->xcd_start[xcd], e = hdr->xcd_start[xcd + 1];
-        if (part >= 0) {
-            const int mid = s + (e - s) / 2;
-            if (part == 0)
-                e = mid;
-            else
-                s = mid;
-        }
-        t0 = s + (blockIdx.x >> 3);
-        t1 = e;
+        t0 = hdr->xcd_start[xcd] + (blockIdx.x >> 3);
+        t1 = hdr->xcd_start[xcd + 1];
         dt = gridDim.x >> 3;
     }
 }
@@ -320,9 +311,9 @@ __device__ __forceinline__ void tile_range(const BatchHeader* hdr, int ntiles_ar
 template <typename T, int TX, int TY, int RPT, bool NTMP, bool MRT>
 __global__ void __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(kSweepMinWaves<T, MRT>, 7)))
     k_sweep(const SimDev* __restrict__ sims, const int4* __restrict__ tiles,
-            const BatchHeader* __restrict__ hdr, int ntiles_arg, int parity, int part) {
+            const BatchHeader* __restrict__ hdr, int ntiles_arg, int parity) {
     int t0, t1, dt;
-    tile_range(hdr, ntiles_arg, part, t0, t1, dt);
+    tile_range(hdr, ntiles_arg, t0, t1, dt);
     for (int t = t0; t < t1; t += dt) {
         const int4 tile = tiles[t];
         const SimDev& S = sims[tile.x];
@@ -358,9 +349,9 @@ __global__ void __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(kSw
 template <typename T, int W, int R, bool NTMP, bool MRT>
 __global__ void __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(kSweepMinWaves<T, MRT>, 7)))
     k_sweep_blk(const SimDev* __restrict__ sims, const int4* __restrict__ tiles,
-                const BatchHeader* __restrict__ hdr, int ntiles_arg, int parity, int part) {
+                const BatchHeader* __restrict__ hdr, int ntiles_arg, int parity) {
     int t0, t1, dt;
-    tile_range(hdr, ntiles_arg, part, t0, t1, dt);
+    tile_range(hdr, ntiles_arg, t0, t1, dt);
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     for (int t = t0; t < t1; t += dt) {
@@ -2301,56 +2292,56 @@ __global__ void k_set_eq(const SimDev* sim, int sw, const double* rho, const dou
 
 template <typename T, bool MRT, int TX, int TY, int RPT, bool NTMP>
 static hipError_t sweep_t(const SimDev* sims, const int4* tiles, const BatchHeader* hdr, int ntiles, int grid,
-                          int parity, int part, hipStream_t st) {
+                          int parity, hipStream_t st) {
     hipLaunchKernelGGL((k_sweep<T, TX, TY, RPT, NTMP, MRT>), dim3(grid), dim3(TX, TY), 0, st, sims, tiles, hdr, ntiles,
-                       parity, part);
+                       parity);
     return hipGetLastError();
 }
 
 template <typename T, bool MRT, int W, int R, bool NTMP>
 static hipError_t sweep_b(const SimDev* sims, const int4* tiles, const BatchHeader* hdr, int ntiles, int grid,
-                          int parity, int part, hipStream_t st) {
+                          int parity, hipStream_t st) {
     hipLaunchKernelGGL((k_sweep_blk<T, W, R, NTMP, MRT>), dim3(grid), dim3(64 * W), 0, st, sims, tiles, hdr, ntiles,
-                       parity, part);
+                       parity);
     return hipGetLastError();
 }
 
 template <typename T, bool MRT>
 static hipError_t sweep_tt(int tiling, const SimDev* sims, const int4* tiles, const BatchHeader* hdr, int ntiles,
-                           int grid, int parity, int part, hipStream_t st) {
+                           int grid, int parity, hipStream_t st) {
     switch (tiling) {
-        case 16: return sweep_b<T, MRT, 4, 1, true>(sims, tiles, hdr, ntiles, grid, parity, part, st);
-        case 17: return sweep_b<T, MRT, 4, 2, true>(sims, tiles, hdr, ntiles, grid, parity, part, st);
-        case 18: return sweep_b<T, MRT, 8, 1, true>(sims, tiles, hdr, ntiles, grid, parity, part, st);
-        case 19: return sweep_b<T, MRT, 4, 1, false>(sims, tiles, hdr, ntiles, grid, parity, part, st);
-        case 0: return sweep_t<T, MRT, 64, 4, 1, false>(sims, tiles, hdr, ntiles, grid, parity, part, st);
-        case 1: return sweep_t<T, MRT, 64, 4, 2, false>(sims, tiles, hdr, ntiles, grid, parity, part, st);
-        case 2: return sweep_t<T, MRT, 128, 2, 2, false>(sims, tiles, hdr, ntiles, grid, parity, part, st);
-        case 3: return sweep_t<T, MRT, 256, 1, 2, false>(sims, tiles, hdr, ntiles, grid, parity, part, st);
-        case 4: return sweep_t<T, MRT, 256, 1, 4, false>(sims, tiles, hdr, ntiles, grid, parity, part, st);
-        case 5: return sweep_t<T, MRT, 64, 4, 4, false>(sims, tiles, hdr, ntiles, grid, parity, part, st);
-        case 6: return sweep_t<T, MRT, 256, 1, 1, false>(sims, tiles, hdr, ntiles, grid, parity, part, st);
-        case 7: return sweep_t<T, MRT, 128, 2, 1, false>(sims, tiles, hdr, ntiles, grid, parity, part, st);
-        case 8: return sweep_t<T, MRT, 64, 4, 1, true>(sims, tiles, hdr, ntiles, grid, parity, part, st);
-        case 9: return sweep_t<T, MRT, 64, 4, 2, true>(sims, tiles, hdr, ntiles, grid, parity, part, st);
-        case 10: return sweep_t<T, MRT, 128, 2, 2, true>(sims, tiles, hdr, ntiles, grid, parity, part, st);
-        case 11: return sweep_t<T, MRT, 256, 1, 2, true>(sims, tiles, hdr, ntiles, grid, parity, part, st);
-        case 12: return sweep_t<T, MRT, 256, 1, 4, true>(sims, tiles, hdr, ntiles, grid, parity, part, st);
-        case 13: return sweep_t<T, MRT, 64, 4, 4, true>(sims, tiles, hdr, ntiles, grid, parity, part, st);
-        case 14: return sweep_t<T, MRT, 256, 1, 1, true>(sims, tiles, hdr, ntiles, grid, parity, part, st);
-        case 15: return sweep_t<T, MRT, 128, 2, 1, true>(sims, tiles, hdr, ntiles, grid, parity, part, st);
+        case 16: return sweep_b<T, MRT, 4, 1, true>(sims, tiles, hdr, ntiles, grid, parity, st);
+        case 17: return sweep_b<T, MRT, 4, 2, true>(sims, tiles, hdr, ntiles, grid, parity, st);
+        case 18: return sweep_b<T, MRT, 8, 1, true>(sims, tiles, hdr, ntiles, grid, parity, st);
+        case 19: return sweep_b<T, MRT, 4, 1, false>(sims, tiles, hdr, ntiles, grid, parity, st);
+        case 0: return sweep_t<T, MRT, 64, 4, 1, false>(sims, tiles, hdr, ntiles, grid, parity, st);
+        case 1: return sweep_t<T, MRT, 64, 4, 2, false>(sims, tiles, hdr, ntiles, grid, parity, st);
+        case 2: return sweep_t<T, MRT, 128, 2, 2, false>(sims, tiles, hdr, ntiles, grid, parity, st);
+        case 3: return sweep_t<T, MRT, 256, 1, 2, false>(sims, tiles, hdr, ntiles, grid, parity, st);
+        case 4: return sweep_t<T, MRT, 256, 1, 4, false>(sims, tiles, hdr, ntiles, grid, parity, st);
+        case 5: return sweep_t<T, MRT, 64, 4, 4, false>(sims, tiles, hdr, ntiles, grid, parity, st);
+        case 6: return sweep_t<T, MRT, 256, 1, 1, false>(sims, tiles, hdr, ntiles, grid, parity, st);
+        case 7: return sweep_t<T, MRT, 128, 2, 1, false>(sims, tiles, hdr, ntiles, grid, parity, st);
+        case 8: return sweep_t<T, MRT, 64, 4, 1, true>(sims, tiles, hdr, ntiles, grid, parity, st);
+        case 9: return sweep_t<T, MRT, 64, 4, 2, true>(sims, tiles, hdr, ntiles, grid, parity, st);
+        case 10: return sweep_t<T, MRT, 128, 2, 2, true>(sims, tiles, hdr, ntiles, grid, parity, st);
+        case 11: return sweep_t<T, MRT, 256, 1, 2, true>(sims, tiles, hdr, ntiles, grid, parity, st);
+        case 12: return sweep_t<T, MRT, 256, 1, 4, true>(sims, tiles, hdr, ntiles, grid, parity, st);
+        case 13: return sweep_t<T, MRT, 64, 4, 4, true>(sims, tiles, hdr, ntiles, grid, parity, st);
+        case 14: return sweep_t<T, MRT, 256, 1, 1, true>(sims, tiles, hdr, ntiles, grid, parity, st);
+        case 15: return sweep_t<T, MRT, 128, 2, 1, true>(sims, tiles, hdr, ntiles, grid, parity, st);
         default: return hipErrorInvalidValue;
     }
 }
 
 hipError_t launch_sweep(bool f64, bool mrt, int tiling, const SimDev* sims, const int4* tiles, const BatchHeader* hdr,
-                        int ntiles, int grid, int parity, hipStream_t stream, int part) {
+                        int ntiles, int grid, int parity, hipStream_t stream) {
     if (grid <= 0) return hipSuccess;
     if (mrt)
-        return f64 ? sweep_tt<double, true>(tiling, sims, tiles, hdr, ntiles, grid, parity, part, stream)
-                   : sweep_tt<float, true>(tiling, sims, tiles, hdr, ntiles, grid, parity, part, stream);
-    return f64 ? sweep_tt<double, false>(tiling, sims, tiles, hdr, ntiles, grid, parity, part, stream)
-               : sweep_tt<float, false>(tiling, sims, tiles, hdr, ntiles, grid, parity, part, stream);
+        return f64 ? sweep_tt<double, true>(tiling, sims, tiles, hdr, ntiles, grid, parity, stream)
+                   : sweep_tt<float, true>(tiling, sims, tiles, hdr, ntiles, grid, parity, stream);
+    return f64 ? sweep_tt<double, false>(tiling, sims, tiles, hdr, ntiles, grid, parity, stream)
+               : sweep_tt<float, false>(tiling, sims, tiles, hdr, ntiles, grid, parity, stream);
 }
 
 hipError_t launch_boundary(bool f64, const SimDev* sims, const int2* items, const BatchHeader* hdr, int nitems,

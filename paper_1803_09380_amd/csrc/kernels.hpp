@@ -29,12 +29,9 @@ hipError_t static_scratch(double** out);
 // step starts from; -1 reads it from each simulation's descriptor (batches).
 // Counts come from `hdr` when it is non-null (graph-captured batches),
 // otherwise from the explicit count arguments.
-// part (batches): -1 every tile; 0 or 1 the first or second half of every
-// XCD's tiles, for a sweep split into two launches.
 // mrt: some simulation of the launch uses the MRT collision.
 hipError_t launch_sweep(bool f64, bool mrt, int tiling, const SimDev* sims, const int4* tiles,
-                        const BatchHeader* hdr, int ntiles, int grid, int parity,
-                        hipStream_t stream, int part = -1);
+                        const BatchHeader* hdr, int ntiles, int grid, int parity, hipStream_t stream);
 hipError_t launch_boundary(bool f64, const SimDev* sims, const int2* items, const BatchHeader* hdr,
                            int nitems, int grid, int parity, hipStream_t stream);
 // max_markers: the largest group's marker count (selects how many markers
