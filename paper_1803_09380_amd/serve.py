@@ -32,9 +32,13 @@ class Request:
 class GpuExecutor:
     """Executor over lbmib.Batch (one precision, one HBM budget)."""
 
-    def __init__(self, precision, hbm_budget, tiling=None, lanes=None):
+    def __init__(self, precision, hbm_budget, tiling=None, lanes=None, halves_from=8):
         """lanes: the batch's lane mode (lbmib.Batch.set_lanes), None for the
-        library's choice."""
+        library's choice.  halves_from > 0: two interleaved halves (lane mode
+        4, one half's correction beside the other half's sweep) while at
+        least that many requests are on the device, set afresh at every
+        admission and retirement; the library's choice below that (one lane
+        costs less with few members).  0: never."""
         from . import lbmib
         self.lbmib = lbmib
         self.batch = lbmib.Batch(precision, hbm_budget=hbm_budget)
@@ -43,7 +47,15 @@ class GpuExecutor:
             self.batch.set_tiling(tiling)
         if lanes is not None:
             self.batch.set_lanes(lanes)
+        self.halves_from = halves_from
+        self.halves = False
         self.live = {}
+
+    def _lanes(self):
+        want = self.halves_from > 0 and len(self.live) >= self.halves_from
+        if want or self.halves:
+            self.batch.set_lanes(4 if want else 0)
+        self.halves = want
 
     def create(self, req):
         return self.lbmib.Sim.from_case(req.case, precision=self.precision)
@@ -60,6 +72,7 @@ class GpuExecutor:
         ok = self.batch.admit(handle, steps=req.steps)
         if ok:
             self.live[req.rid] = handle
+            self._lanes()
         return ok
 
     def step(self, n):
@@ -72,6 +85,7 @@ class GpuExecutor:
     def finish(self, req):
         h = self.live.pop(req.rid)
         self.batch.retire(h)
+        self._lanes()
         res = {"steps": h.step_count, "bodies": [h.forces(k) for k in range(len(req.case["bodies"]))]}
         h.close()
         return res
