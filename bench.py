@@ -453,8 +453,9 @@ def main():
         batch.set_lanes(args.lanes)
     tiling = args.tiling
     if args.tiling < 0 and not args.no_autotune:
-        tiling = batch.autotune(trials=10)
+        tiling = batch.autotune(trials=20)
     lanes = batch.lanes
+    lane_mode = batch.lane_mode
     batch.step(args.warmup)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -571,7 +572,7 @@ def main():
                         "channel 20Dx10D with D 16..64, Re 10..100), FP32 shifted populations, "
                         "10 correction sweeps per step" % args.sims,
             "seed": args.seed, "sims": args.sims, "cells": cells, "markers": markers,
-            "tiling": in_use, "lanes": lanes,
+            "tiling": in_use, "lanes": lanes, "lane_mode": lane_mode,
         },
         "roofline": {
             "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -258,10 +258,11 @@ lbm_status lbm_batch_remaining(lbm_batch* b, lbm_sim* s, int64_t* remaining);
 size_t lbm_batch_bytes(const lbm_batch* b);
 /* Time candidate sweep tilings on the admitted set (each candidate runs `trials`
  * steps, after which the state is restored, so it is not advanced) and keep the
- * fastest; when two lanes are in use, then time one lane against two at that
- * tiling and keep the faster (lbm_batch_set_lanes).  Tilings and lanes change
- * scheduling only, never the arithmetic.  chosen (nullable) receives the index
- * of the tiling kept. */
+ * fastest; then, at that tiling, time the lane schedules (lbm_batch_set_lanes):
+ * the two lanes in use, two interleaved halves (lanes = 4) when the lanes are
+ * chosen automatically, and one lane, and keep the fastest.  Tilings and lanes
+ * change scheduling only, never the arithmetic.  chosen (nullable) receives the
+ * index of the tiling kept. */
 lbm_status lbm_batch_autotune(lbm_batch* b, int32_t trials, int32_t* chosen);
 /* Force a tiling index (0 .. lbm_tiling_count()-1). */
 lbm_status lbm_batch_set_tiling(lbm_batch* b, int32_t tiling);
@@ -279,8 +280,11 @@ int32_t lbm_batch_get_tiling(const lbm_batch* b);
  * lanes = 4 interleaves two lanes the same way but splits the simulations
  * into two halves of about equal node count instead (at least two
  * simulations), so that either half's correction can run under the other
- * half's sweep.  lanes = 0 (the default) takes 3 for batches of at least
- * 16 Mi nodes and 2 below; lanes = 1 keeps one lane.  The second stream is ordered after
+ * half's sweep.  In interleaved FP32 lanes the corrections run in 256-thread
+ * kernels that fit beside sweep waves (groups of up to 1280 markers), each of
+ * which also gathers and applies its group's band.  lanes = 0 (the default)
+ * takes 3 for batches of at least 16 Mi nodes and 2 below; lanes = 1 keeps
+ * one lane.  The second stream is ordered after
  * the batch stream's earlier work and the batch stream waits for it, so the
  * batch behaves as one stream to the caller.  Results do not depend on the
  * lanes.  lbm_batch_autotune may switch to one lane when it is faster.
@@ -288,6 +292,9 @@ int32_t lbm_batch_get_tiling(const lbm_batch* b);
 lbm_status lbm_batch_set_lanes(lbm_batch* b, int32_t lanes);
 /* Lanes in use now (1 or 2). */
 int32_t lbm_batch_get_lanes(const lbm_batch* b);
+/* The lane request in force (0 .. 4, as lbm_batch_set_lanes takes it; the
+ * autotuner may have replaced the caller's), -1 for a null batch. */
+int32_t lbm_batch_get_lane_mode(const lbm_batch* b);
 int32_t lbm_tiling_count(void);
 /* Describe tiling k: threads along x, rows per block, rows per thread. */
 lbm_status lbm_tiling_info(int32_t k, int32_t* tx, int32_t* ty, int32_t* rows_per_thread);

@@ -1966,8 +1966,10 @@ __device__ __forceinline__ void ib_groups(const SimDev* __restrict__ sims, Group
             // placement of the working arrays (the same decision on every thread):
             // the segment band when the plan has one and it fits, else the entry band
             bool done = false;
-            // (two markers per thread at most: larger groups never fit the class band)
-            constexpr int MPTC = MPT < 2 ? MPT : 2;
+            // (two markers per thread at most in the wide kernels, whose larger
+            // groups never fit the class band; the 256-thread kernels keep all
+            // of theirs, at most 1280 markers, whose class band fits the arena)
+            constexpr int MPTC = NT <= 256 ? MPT : (MPT < 2 ? MPT : 2);
             if (G.ncolor > 0 && M <= MPTC * NT) {
                 Bump cb;
                 cb.base = arena;
@@ -2143,17 +2145,22 @@ __global__ void __launch_bounds__(NT)
     ib_groups<T, NT, MPT>(sims, groups, hdr, ngroups_arg, parity, arena, kIbArenaBytes, bc_items);
 }
 
-// One wave per SIMD and at most 128 VGPRs: a workgroup of this form finds room
-// on a CU as soon as two sweep waves per SIMD have finished there, so the
-// correction of one lane runs while the other lane's sweep streams (a
-// 768-thread k_ib needs a CU with no sweep wave left).  For groups of at most
-// MPT * 256 markers.
+// One wave per SIMD: a workgroup of this form finds room on a CU once a few
+// sweep waves per SIMD have finished there, so the correction of one lane runs
+// while the other lane's sweep streams (a 768-thread k_ib needs a CU with no
+// sweep wave left).  MPT = 1 (groups of at most 256 markers): at most 128
+// VGPRs and a 96 KiB arena, room once two sweep waves per SIMD are gone;
+// MPT = 2 and 5 (at most 512 and 1280 markers): up to 256 VGPRs (a tighter
+// cap spills, and measured slower) and the full arena, room once four are gone.
+template <int MPT>
+constexpr int kLeanArenaBytes = MPT == 1 ? kIbLeanArenaBytes : kIbArenaBytes;
+
 template <typename T, int MPT>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8)))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MPT == 1 ? 4 : 2, 8)))
     k_ib_lean(const SimDev* __restrict__ sims, GroupDev* __restrict__ groups, const BatchHeader* __restrict__ hdr,
               int ngroups_arg, int parity, const int2* bc_items) {
-    extern __shared__ __align__(16) char lean_arena[];  // kIbLeanArenaBytes at launch
-    ib_groups<T, 256, MPT>(sims, groups, hdr, ngroups_arg, parity, lean_arena, kIbLeanArenaBytes, bc_items);
+    extern __shared__ __align__(16) char lean_arena[];  // kLeanArenaBytes<MPT> at launch
+    ib_groups<T, 256, MPT>(sims, groups, hdr, ngroups_arg, parity, lean_arena, kLeanArenaBytes<MPT>, bc_items);
 }
 
 // ---------------------------------------------------------------- bookkeeping and I/O
@@ -2367,16 +2374,17 @@ static hipError_t ib_lean_t(const SimDev* sims, GroupDev* groups, const BatchHea
                             int parity, hipStream_t stream, const int2* bc_items) {
     static const hipError_t attr =
         hipFuncSetAttribute(reinterpret_cast<const void*>(&k_ib_lean<T, MPT>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, kIbLeanArenaBytes);
+                            hipFuncAttributeMaxDynamicSharedMemorySize, kLeanArenaBytes<MPT>);
     if (attr != hipSuccess) return attr;
-    hipLaunchKernelGGL((k_ib_lean<T, MPT>), dim3(grid), dim3(256), kIbLeanArenaBytes, stream, sims, groups, hdr,
+    hipLaunchKernelGGL((k_ib_lean<T, MPT>), dim3(grid), dim3(256), kLeanArenaBytes<MPT>, stream, sims, groups, hdr,
                        ngroups, parity, bc_items);
     return hipGetLastError();
 }
 
 int ib_variant(bool f64, int max_markers, bool lean) {
     if (f64) return max_markers <= 8 * 256 ? 0 : 1;
-    return lean && max_markers <= 256 ? 4 : max_markers <= 3 * 768 ? 2 : 3;
+    if (lean && max_markers <= 1280) return max_markers <= 256 ? 4 : (max_markers <= 512 ? 5 : 6);
+    return max_markers <= 3 * 768 ? 2 : 3;
 }
 
 hipError_t launch_ib(bool f64, int max_markers, const SimDev* sims, GroupDev* groups, const BatchHeader* hdr,
@@ -2391,6 +2399,10 @@ hipError_t launch_ib(bool f64, int max_markers, const SimDev* sims, GroupDev* gr
                    : ib_t<double, 256, 16>(sims, groups, hdr, ngroups, grid, parity, stream, bc_items);
     if (lean && max_markers <= 256)
         return ib_lean_t<float, 1>(sims, groups, hdr, ngroups, grid, parity, stream, bc_items);
+    if (lean && max_markers <= 512)
+        return ib_lean_t<float, 2>(sims, groups, hdr, ngroups, grid, parity, stream, bc_items);
+    if (lean && max_markers <= 1280)
+        return ib_lean_t<float, 5>(sims, groups, hdr, ngroups, grid, parity, stream, bc_items);
     return max_markers <= 3 * 768 ? ib_t<float, 768, 3>(sims, groups, hdr, ngroups, grid, parity, stream, bc_items)
                                   : ib_t<float, 512, 8>(sims, groups, hdr, ngroups, grid, parity, stream, bc_items);
 }

@@ -36,7 +36,7 @@ hipError_t launch_boundary(bool f64, const SimDev* sims, const int2* items, cons
                            int nitems, int grid, int parity, hipStream_t stream);
 // max_markers: the largest group's marker count (selects how many markers
 // each thread carries; the results do not depend on it).  lean: FP32 groups of
-// at most 256 markers run in the 256-thread kernel that fits beside sweep
+// at most 1280 markers run in the 256-thread kernels that fit beside sweep
 // waves (for lanes whose corrections overlap another lane's sweep).
 // bc_items (with hdr): the lane's boundary items, applied by the correction
 // workgroups after their groups in place of launch_boundary (only when no band

@@ -139,7 +139,8 @@ constexpr int kHeavyGroupMarkers = 400;
 // their correction workgroup; larger ones by the band kernels over all CUs (a
 // node's nine populations lie in nine cache lines, which one CU fetches at a
 // fraction of the chip's rate: 5,000 nodes took 50 us each way in one
-// workgroup against a few us spread over the chip).
+// workgroup against a few us spread over the chip), except in interleaved
+// FP32 lanes, where the correction runs beside a sweep and takes every band.
 constexpr int kFuseBandNodes = 1024;
 // Two interleaved lanes are launched step by step from the host; below this
 // many nodes the automatic choice replays each lane's graphs of several steps
@@ -1183,6 +1184,11 @@ lbm_status upload_tables(lbm_batch* b) {
             for (Group* g : s->grp) {
                 GroupDev d = g->d;
                 d.sim = r;
+                // interleaved FP32 lanes: every band is gathered and applied by
+                // its correction workgroup, which runs beside the other lane's
+                // sweep (the band kernels would need the whole chip between the
+                // sweeps; the results are the same)
+                if (il && !b->f64) d.in_kernel = 1;
                 groups.push_back(d);
             }
         }
@@ -1588,16 +1594,28 @@ lbm_status lbm_batch_autotune(lbm_batch* b, int32_t trials, int32_t* chosen) {
         }
     }
     b->tiling = best;
-    // then one lane against two at the chosen tiling (when two are possible)
-    if (rc == LBM_OK && b->lanes_req != 1 && b->nlanes == 2) {
+    // then the lane schedules at the chosen tiling: the requested two lanes,
+    // two interleaved halves (when the choice is automatic) and one lane; the
+    // fastest stays (ties go to the earlier one)
+    if (rc == LBM_OK && b->lanes_req != 1 && b->sims.size() >= 2) {
         const int req = b->lanes_req;
-        float ms2 = 0.f, ms1 = 0.f;
-        rc = trial(ms2);
-        if (rc == LBM_OK) {
-            b->lanes_req = 1;
-            rc = trial(ms1);
-            if (rc == LBM_OK && ms2 <= ms1) b->lanes_req = req;
+        std::vector<int> cand;
+        if (b->nlanes == 2) cand.push_back(req);
+        if (req == 0) cand.push_back(4);
+        if (!cand.empty()) cand.push_back(1);
+        float best_l = 1e30f;
+        int pick = req;
+        for (int c : cand) {
+            b->lanes_req = c;
+            float ms = 0.f;
+            rc = trial(ms);
+            if (rc != LBM_OK) break;
+            if (ms < best_l) {
+                best_l = ms;
+                pick = c;
+            }
         }
+        b->lanes_req = rc == LBM_OK ? pick : req;
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -1618,6 +1636,8 @@ lbm_status lbm_batch_set_lanes(lbm_batch* b, int32_t lanes) {
 }
 
 int32_t lbm_batch_get_lanes(const lbm_batch* b) { return b ? b->nlanes : -1; }
+
+int32_t lbm_batch_get_lane_mode(const lbm_batch* b) { return b ? b->lanes_req : -1; }
 
 lbm_status lbm_batch_profile(lbm_batch* b, int32_t nsteps, double ms[4], int64_t* cells) {
     if (!b || nsteps < 0 || !ms) return LBM_ERR_INVALID;

@@ -81,6 +81,7 @@ SIGNATURES = [
     ("lbm_batch_get_tiling", _I32, [_P]),
     ("lbm_batch_set_lanes", _ST, [_P, _I32]),
     ("lbm_batch_get_lanes", _I32, [_P]),
+    ("lbm_batch_get_lane_mode", _I32, [_P]),
     ("lbm_tiling_count", _I32, []),
     ("lbm_tiling_info", _ST, [_I32, ctypes.POINTER(_I32), ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
     ("lbm_batch_profile", _ST, [_P, _I32, _DP, ctypes.POINTER(_I64)]),
@@ -402,6 +403,11 @@ class Batch:
     def lanes(self):
         """Lanes (streams) the batch replays its steps on."""
         return load().lbm_batch_get_lanes(self._h)
+
+    @property
+    def lane_mode(self):
+        """The lane request in force (0 .. 4, as set_lanes takes it)."""
+        return load().lbm_batch_get_lane_mode(self._h)
 
 
 def tilings():

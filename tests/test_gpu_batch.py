@@ -251,6 +251,34 @@ def test_two_lanes_give_the_same_bits():
         _same(res[lanes][0], _state(alone, 2))
 
 
+def test_interleaved_lanes_with_large_groups_give_the_same_bits():
+    """Groups of 1206 and 603 markers (Couette 512 and 256) in interleaved
+    lanes run in the 256-thread corrections, which also gather and apply the
+    bands that the band kernels take with one lane: the same bits as one lane
+    and as alone, with the heavy/light split and with equal halves."""
+    _say("interleaved lanes with groups of 603 and 1206 markers, 9 steps")
+    cases = [wl.couette(512, precision=wl.F32), wl.couette(256, precision=wl.F32),
+             wl.cylinder(nx=800, ny=400, D=16.0, centre=(200.0, 200.0), U=0.05, Re=40.0)] + _cases()
+    res = {}
+    for lanes in (1, 3, 4):
+        sims = [gpu_from_case(c, precision=lbmib.F32_SHIFTED) for c in cases]
+        b = lbmib.Batch(lbmib.F32_SHIFTED)
+        for s in sims:
+            assert b.admit(s)
+        b.set_lanes(lanes)
+        assert b.lanes == min(lanes, 2)
+        b.step(9)
+        b.sync()
+        res[lanes] = [_state(s, len(c["bodies"])) for s, c in zip(sims, cases)]
+        b.close()
+    alone = gpu_from_case(cases[0], precision=lbmib.F32_SHIFTED)
+    alone.step(9)
+    for lanes in (3, 4):
+        for x, y in zip(res[1], res[lanes]):
+            _same(x, y)
+    _same(res[1][0], _state(alone, 2))
+
+
 def test_two_lanes_with_boundary_beside_correction_give_the_same_bits():
     """The light lane holds channel cylinders far from the sides and periodic
     Couette cells only, so its boundary rules run on their own stream beside
