@@ -133,7 +133,7 @@ def _cpu_configs():
     number of steps: (name, case, steps)."""
     from paper_1803_09380_amd import workloads as wl
     out = [("couette64", wl.couette(64), 2000), ("couette256", wl.couette(256), 100),
-           ("cylinder1600x800_re20", wl.cylinder(Re=20.0), 20)]
+           ("cylinder1600x800_re20", wl.cylinder(Re=20.0), 2000)]
     for k, r in enumerate(wl.arrivals(seed=0, rate=20.0, count=4, steps=2000)):
         out.append(("served_request%d" % k, r["case"], 10))
     return out
@@ -152,6 +152,8 @@ def cpu_worker(spec):
     else:
         res = {}
         for name, case, steps in _cpu_configs():
+            print("cpu baseline: %s, %d steps, %s threads" % (name, steps, os.environ.get("OMP_NUM_THREADS")),
+                  file=sys.stderr, flush=True)
             o = _oracle_from_case(po, case)
             o.step(1)
             t0 = time.perf_counter()
@@ -166,7 +168,7 @@ def _run_worker(spec, threads):
     import subprocess
     env = dict(os.environ, OMP_NUM_THREADS=str(threads), OMP_PROC_BIND="false")
     out = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-worker", json.dumps(spec)],
-                         stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True, env=env, check=True)
+                         stdout=subprocess.PIPE, text=True, env=env, check=True)
     return json.loads(out.stdout.strip().splitlines()[-1])
 
 
