@@ -516,7 +516,7 @@ def main():
         serving.update({"arrivals": "Poisson, mean 20/s, seed %d" % args.seed, "lattice": "400x4000 closed box",
                         "steps_per_request": args.serve_steps, "hbm_budget_bytes": budget,
                         "particles": "1 or 2 free circles, D 16..40, density ratio 1.01..1.5",
-                        "lanes": "two interleaved halves while %d requests are on the device" % ex.halves_from})
+                        "lanes": "two interleaved halves while at least %d requests are on the device" % ex.halves_from})
 
     # ---- overload: ten times the steps per request and an HBM budget of eight
     # requests, so that arrivals queue for admission
@@ -537,7 +537,7 @@ def main():
         overload.update({"arrivals": "Poisson, mean 20/s, seed %d" % (args.seed + 1),
                          "lattice": "400x4000 closed box", "steps_per_request": 10 * args.serve_steps,
                          "hbm_budget_bytes": budget, "budget_requests": 8,
-                         "lanes": "two interleaved halves while %d requests are on the device" % ex.halves_from})
+                         "lanes": "two interleaved halves while at least %d requests are on the device" % ex.halves_from})
 
     # ---- the overload leg's mix in steady state, one lane and two interleaved halves
     served_steady = None
