@@ -256,13 +256,13 @@ lbm_status lbm_batch_sync(lbm_batch* b);
 /* Steps still to run for s in the batch (reads device state; synchronises). */
 lbm_status lbm_batch_remaining(lbm_batch* b, lbm_sim* s, int64_t* remaining);
 size_t lbm_batch_bytes(const lbm_batch* b);
-/* Time candidate sweep tilings on the admitted set (each candidate runs `trials`
- * steps, after which the state is restored, so it is not advanced) and keep the
- * fastest; then, at that tiling, time the lane schedules (lbm_batch_set_lanes):
- * the two lanes in use, two interleaved halves (lanes = 4) when the lanes are
- * chosen automatically, and one lane, and keep the fastest.  Tilings and lanes
- * change scheduling only, never the arithmetic.  chosen (nullable) receives the
- * index of the tiling kept. */
+/* Time every sweep tiling under each candidate lane schedule on the admitted
+ * set (each candidate runs `trials` steps, after which the state is restored,
+ * so it is not advanced) and keep the fastest pair.  The lane schedules
+ * (lbm_batch_set_lanes) are the one requested, two interleaved halves
+ * (lanes = 4) when the lanes are chosen automatically, and one lane (batches of
+ * two simulations or more).  Tilings and lanes change scheduling only, never
+ * the arithmetic.  chosen (nullable) receives the index of the tiling kept. */
 lbm_status lbm_batch_autotune(lbm_batch* b, int32_t trials, int32_t* chosen);
 /* Force a tiling index (0 .. lbm_tiling_count()-1). */
 lbm_status lbm_batch_set_tiling(lbm_batch* b, int32_t tiling);

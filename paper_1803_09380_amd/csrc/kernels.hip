@@ -1827,19 +1827,21 @@ __device__ bool correct_free_lds(const SimDev& S, const GroupDev& G, const Group
 }
 
 // Band records of a plan in device memory (node cells, records in node4),
-// from the post-stream populations, four nodes per thread in flight.
+// from the post-stream populations, four nodes per thread in flight (their
+// four cells requested together, then their 36 populations).
 template <typename T, int NT>
 __device__ void gather_band(const SimDev& S, const GroupDev& G, int nband, int sw) {
     const T rho_base = T(S.rho_base);
     nv4<T>* node4 = reinterpret_cast<nv4<T>*>(G.node4);
     for (int k0 = threadIdx.x; k0 < nband; k0 += 4 * NT) {
+        int cell[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) cell[u] = k0 + u * NT < nband ? ldm<false>(G.node_cell + k0 + u * NT) : 0;
         T h[4][9];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            const int k = k0 + u * NT;
-            if (k < nband) {
-                const int cell = ldm<false>(G.node_cell + k);
-                const int x = cell % S.nx, y = cell / S.nx;
+            if (k0 + u * NT < nband) {
+                const int x = cell[u] % S.nx, y = cell[u] / S.nx;
 #pragma unroll
                 for (int i = 0; i < 9; ++i) h[u][i] = ldm<false>(loc<T>(S, i, x, y, sw));
             }
@@ -1857,17 +1859,35 @@ __device__ void gather_band(const SimDev& S, const GroupDev& G, int nband, int s
 // correct_group_col, which leave the per-marker totals in m_wtot).  Groups
 // never share a band node, and every (node, population) pair has a slot of
 // its own in either AA state, so the groups of a launch apply side by side.
-template <typename T, int NT>
+// U nodes per thread at a time: their run bounds and cells are requested
+// together before the spreads (one node per round left the workgroup waiting
+// on their loads too); each node's spread and Eq. 28 then follow as in
+// k_band_apply, so both give the same bits.
+template <typename T, int NT, int U>
 __device__ void apply_band(const SimDev& S, const GroupDev& G, int nband, int sw) {
     Band<T> B;
     B.entpk = G.ent_D;
     B.run32 = G.node_run;
-    for (int k = threadIdx.x; k < nband; k += NT) {
-        T t[5];
-        spread_node<T, false, false, 5>(B, reinterpret_cast<const T*>(G.m_wtot), 5, ldm<false>(G.node_run + k),
-                                        ldm<false>(G.node_run + k + 1), t);
-        const int cell = ldm<false>(G.node_cell + k);
-        correct_node<T>(S, cell % S.nx, cell / S.nx, sw, t);
+    for (int k0 = threadIdx.x; k0 < nband; k0 += U * NT) {
+        int e0[U], e1[U], cell[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int k = k0 + u * NT;
+            e0[u] = e1[u] = cell[u] = 0;
+            if (k < nband) {
+                e0[u] = ldm<false>(G.node_run + k);
+                e1[u] = ldm<false>(G.node_run + k + 1);
+                cell[u] = ldm<false>(G.node_cell + k);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (k0 + u * NT < nband) {
+                T t[5];
+                spread_node<T, false, false, 5>(B, reinterpret_cast<const T*>(G.m_wtot), 5, e0[u], e1[u], t);
+                correct_node<T>(S, cell[u] % S.nx, cell[u] / S.nx, sw, t);
+            }
+        }
     }
 }
 
@@ -2033,7 +2053,7 @@ __device__ __forceinline__ void ib_groups(const SimDev* __restrict__ sims, Group
             }
             __syncthreads();
             if (G.in_kernel) {
-                apply_band<T, NT>(S, G, nband, sw);
+                apply_band<T, NT, (NT == 256 && MPT == 1) ? 2 : 4>(S, G, nband, sw);
                 __syncthreads();
             }
             IB_MARK(25);

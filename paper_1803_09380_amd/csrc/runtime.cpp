@@ -1582,41 +1582,34 @@ lbm_status lbm_batch_autotune(lbm_batch* b, int32_t trials, int32_t* chosen) {
         HIPB(b, hipStreamSynchronize(b->stream));
         return LBM_OK;
     };
-    int best = b->tiling;
-    float best_ms = 1e30f;
-    for (int k = 0; k < kNumTilings && rc == LBM_OK; ++k) {
-        b->tiling = k;
-        float ms = 0.f;
-        rc = trial(ms);
-        if (rc == LBM_OK && ms < best_ms) {
-            best_ms = ms;
-            best = k;
-        }
-    }
-    b->tiling = best;
-    // then the lane schedules at the chosen tiling: the requested two lanes,
-    // two interleaved halves (when the choice is automatic) and one lane; the
-    // fastest stays (ties go to the earlier one)
-    if (rc == LBM_OK && b->lanes_req != 1 && b->sims.size() >= 2) {
-        const int req = b->lanes_req;
-        std::vector<int> cand;
-        if (b->nlanes == 2) cand.push_back(req);
+    // every tiling under each lane schedule: the requested one; with an
+    // automatic request also two interleaved halves; and one lane (when there
+    // are two simulations or more).  The fastest pair stays (ties go to the
+    // earlier one): the best tiling differs between schedules.
+    const int req = b->lanes_req;
+    std::vector<int> cand{req};
+    if (req != 1 && b->sims.size() >= 2) {
         if (req == 0) cand.push_back(4);
-        if (!cand.empty()) cand.push_back(1);
-        float best_l = 1e30f;
-        int pick = req;
-        for (int c : cand) {
-            b->lanes_req = c;
+        cand.push_back(1);
+    }
+    int best = b->tiling, best_lanes = req;
+    float best_ms = 1e30f;
+    for (int c : cand) {
+        b->lanes_req = c;
+        for (int k = 0; k < kNumTilings && rc == LBM_OK; ++k) {
+            b->tiling = k;
             float ms = 0.f;
             rc = trial(ms);
-            if (rc != LBM_OK) break;
-            if (ms < best_l) {
-                best_l = ms;
-                pick = c;
+            if (rc == LBM_OK && ms < best_ms) {
+                best_ms = ms;
+                best = k;
+                best_lanes = c;
             }
         }
-        b->lanes_req = rc == LBM_OK ? pick : req;
+        if (rc != LBM_OK) break;
     }
+    b->tiling = best;
+    b->lanes_req = rc == LBM_OK ? best_lanes : req;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     drop_graphs(b);
