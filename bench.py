@@ -387,8 +387,9 @@ def main():
                     help="keep the default sweep tiling instead of timing the candidates on the set")
     ap.add_argument("--tiling", type=int, default=-1)
     ap.add_argument("--lanes", type=int, default=0,
-                    help="1, 2 (free-running) or 3 (interleaved) to force the batch's lanes "
-                         "(default: the library's choice, kept by the autotuner)")
+                    help="1, 2 (free-running), 3 (interleaved heavy/light) or 4 (interleaved equal halves) "
+                         "to request the batch's lanes (default 0: the autotuner times the heavy/light split, "
+                         "equal halves and one lane under every tiling and keeps the fastest)")
     ap.add_argument("--mrt-steps", type=int, default=100,
                     help="timed steps of the same set with the MRT collision (0: skip)")
     ap.add_argument("--serve-requests", type=int, default=24)
