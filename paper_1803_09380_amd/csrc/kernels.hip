@@ -1149,25 +1149,32 @@ __device__ __forceinline__ void marker_outputs(const SimDev& S, const GroupDev& 
     for (int c = 0; c < 5; ++c) stm<false>(reinterpret_cast<T*>(G.m_wtot) + g * 5 + c, T(ds * (double)acc[c]));
 }
 
-// Eq. 28 at node (x, y): the populations corrected by the spread totals t
-// (ds-weighted sums of dm_x, dm_y, dPi_xx, dPi_xy, dPi_yy), in place.
+// Eq. 28 on the nine populations f of one node, given the spread totals t
+// (ds-weighted sums of dm_x, dm_y, dPi_xx, dPi_xy, dPi_yy): f_i += delta f_i.
+// No multiply-add is fused here, so every caller (band kernel, correction
+// workgroup, whatever the code around it) rounds the same way.
 template <typename T>
-__device__ __forceinline__ void correct_node(const SimDev& S, int x, int y, int sw, const T t[5]) {
-    LBM_AS1 T* p[9];
-    T f[9];
-#pragma unroll
-    for (int i = 0; i < 9; ++i) {
-        p[i] = gptr(loc<T>(S, i, x, y, sw));
-        f[i] = *p[i];
-    }
+__device__ __forceinline__ void correct_pops(const T t[5], T f[9]) {
+#pragma clang fp contract(off)
     const T trB = T(1.5) * (t[2] + t[4]);
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
         const T ex = T(ex_of(i)), ey = T(ey_of(i));
         const T d = weight_of<T>(i) *
                     (T(3) * (ex * t[0] + ey * t[1]) + T(4.5) * (ex * ex * t[2] + T(2) * ex * ey * t[3] + ey * ey * t[4]) - trB);
-        *p[i] = f[i] + d;
+        f[i] = f[i] + d;
     }
+}
+
+// Eq. 28 at node (x, y), in place.
+template <typename T>
+__device__ __forceinline__ void correct_node(const SimDev& S, int x, int y, int sw, const T t[5]) {
+    T f[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) f[i] = ldm<false>(loc<T>(S, i, x, y, sw));
+    correct_pops<T>(t, f);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) stm<false>(loc<T>(S, i, x, y, sw), f[i]);
 }
 
 // Steps 2-5 of a group's correction (gather, N sweeps on (rho, j), per-marker
@@ -1862,7 +1869,8 @@ __device__ void gather_band(const SimDev& S, const GroupDev& G, int nband, int s
 // U nodes per thread at a time: their run bounds and cells are requested
 // together before the spreads (one node per round left the workgroup waiting
 // on their loads too); each node's spread and Eq. 28 then follow as in
-// k_band_apply, so both give the same bits.
+// k_band_apply (loading the populations before the spreads as well measured
+// slower).
 template <typename T, int NT, int U>
 __device__ void apply_band(const SimDev& S, const GroupDev& G, int nband, int sw) {
     Band<T> B;
