@@ -279,6 +279,35 @@ def test_interleaved_lanes_with_large_groups_give_the_same_bits():
     _same(res[1][0], _state(alone, 2))
 
 
+def test_interleaved_lanes_with_large_moving_groups_give_the_same_bits():
+    """Free circles of 314 and 503 markers (plans rebuilt on the device every
+    step: in LDS for the first, in device memory for the second, whose box is
+    too large for the LDS plan) corrected by the 256-thread kernels of
+    interleaved lanes: the same bits as with one lane and as alone."""
+    _say("interleaved lanes with moving groups of 314 and 503 markers, 7 steps")
+    cases = [wl.settling(nx=400, ny=800, D=100.0, lower=(200.0, 450.0)),
+             wl.settling(nx=400, ny=900, D=160.0, lower=(200.0, 500.0))] + _cases()[:2]
+    assert [c["bodies"][0]["n"] for c in cases[:2]] == [314, 503]
+    res = {}
+    for lanes in (1, 4):
+        sims = [gpu_from_case(c, precision=lbmib.F32_SHIFTED) for c in cases]
+        b = lbmib.Batch(lbmib.F32_SHIFTED)
+        for s in sims:
+            assert b.admit(s)
+        b.set_lanes(lanes)
+        assert b.lanes == lanes if lanes == 1 else b.lanes == 2
+        b.step(7)
+        b.sync()
+        res[lanes] = [_state(s, len(c["bodies"])) for s, c in zip(sims, cases)]
+        b.close()
+    for x, y in zip(res[1], res[4]):
+        _same(x, y)
+    for k in (0, 1):
+        alone = gpu_from_case(cases[k], precision=lbmib.F32_SHIFTED)
+        alone.step(7)
+        _same(res[4][k], _state(alone, 1))
+
+
 def test_two_lanes_with_boundary_beside_correction_give_the_same_bits():
     """The light lane holds channel cylinders far from the sides and periodic
     Couette cells only, so its boundary rules run on their own stream beside
