@@ -2179,9 +2179,7 @@ __global__ void __launch_bounds__(NT)
 // sweep wave left).  MPT = 1 (groups of at most 256 markers): at most 128
 // VGPRs and a 96 KiB arena, room once two sweep waves per SIMD are gone;
 // MPT = 2 and 5 (at most 512 and 1280 markers): up to 256 VGPRs (a tighter
-// cap spills, and measured slower) and the full arena, room once four are gone
-// (groups of moving bodies have at most 512 markers, so MPT = 5 serves fixed
-// plans only).
+// cap spills, and measured slower) and the full arena, room once four are gone.
 template <int MPT>
 constexpr int kLeanArenaBytes = MPT == 1 ? kIbLeanArenaBytes : kIbArenaBytes;
 
