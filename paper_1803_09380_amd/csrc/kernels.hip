@@ -1996,7 +1996,8 @@ __device__ __forceinline__ void ib_groups(const SimDev* __restrict__ sims, Group
             bool done = false;
             // (two markers per thread at most in the wide kernels, whose larger
             // groups never fit the class band; the 256-thread kernels keep all
-            // of theirs, at most 1280 markers, whose class band fits the arena)
+            // of theirs, at most 1280 markers, whose class band fits the arena;
+            // the 512-thread lean kernel carries one)
             constexpr int MPTC = NT <= 256 ? MPT : (MPT < 2 ? MPT : 2);
             if (G.ncolor > 0 && M <= MPTC * NT) {
                 Bump cb;
@@ -2061,7 +2062,7 @@ __device__ __forceinline__ void ib_groups(const SimDev* __restrict__ sims, Group
             }
             __syncthreads();
             if (G.in_kernel) {
-                apply_band<T, NT, (NT == 256 && MPT == 1) ? 2 : 4>(S, G, nband, sw);
+                apply_band<T, NT, MPT == 1 ? 2 : 4>(S, G, nband, sw);
                 __syncthreads();
             }
             IB_MARK(25);
@@ -2173,22 +2174,27 @@ __global__ void __launch_bounds__(NT)
     ib_groups<T, NT, MPT>(sims, groups, hdr, ngroups_arg, parity, arena, kIbArenaBytes, bc_items);
 }
 
-// One wave per SIMD: a workgroup of this form finds room on a CU once a few
-// sweep waves per SIMD have finished there, so the correction of one lane runs
-// while the other lane's sweep streams (a 768-thread k_ib needs a CU with no
-// sweep wave left).  MPT = 1 (groups of at most 256 markers): at most 128
-// VGPRs and a 96 KiB arena, room once two sweep waves per SIMD are gone;
-// MPT = 2 and 5 (at most 512 and 1280 markers): up to 256 VGPRs (a tighter
-// cap spills, and measured slower) and the full arena, room once four are gone.
+// Workgroups that find room on a CU once a few sweep waves per SIMD have
+// finished there, so the correction of one lane runs while the other lane's
+// sweep streams (a 768-thread k_ib needs a CU with no sweep wave left).
+// MPT = 1 (groups of at most 256 markers): 512 threads, two waves per SIMD of
+// at most 128 VGPRs and a 96 KiB arena, room once four sweep waves per SIMD are
+// gone (256 threads: 0.210 against 0.198 ms per step on the served mix in
+// halves); MPT = 2 and 5 (at most 512 and 1280 markers): 256 threads, one
+// wave per SIMD of up to 256 VGPRs (a tighter cap spills, and measured slower)
+// and the full arena, room once four are gone.
 template <int MPT>
 constexpr int kLeanArenaBytes = MPT == 1 ? kIbLeanArenaBytes : kIbArenaBytes;
+template <int MPT>
+constexpr int kLeanThreads = MPT == 1 ? 512 : 256;
 
 template <typename T, int MPT>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MPT == 1 ? 4 : 2, 8)))
+__global__ void __launch_bounds__(kLeanThreads<MPT>) __attribute__((amdgpu_waves_per_eu(MPT == 1 ? 4 : 2, 8)))
     k_ib_lean(const SimDev* __restrict__ sims, GroupDev* __restrict__ groups, const BatchHeader* __restrict__ hdr,
               int ngroups_arg, int parity, const int2* bc_items) {
     extern __shared__ __align__(16) char lean_arena[];  // kLeanArenaBytes<MPT> at launch
-    ib_groups<T, 256, MPT>(sims, groups, hdr, ngroups_arg, parity, lean_arena, kLeanArenaBytes<MPT>, bc_items);
+    ib_groups<T, kLeanThreads<MPT>, MPT>(sims, groups, hdr, ngroups_arg, parity, lean_arena, kLeanArenaBytes<MPT>,
+                                         bc_items);
 }
 
 // ---------------------------------------------------------------- bookkeeping and I/O
@@ -2404,8 +2410,8 @@ static hipError_t ib_lean_t(const SimDev* sims, GroupDev* groups, const BatchHea
         hipFuncSetAttribute(reinterpret_cast<const void*>(&k_ib_lean<T, MPT>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, kLeanArenaBytes<MPT>);
     if (attr != hipSuccess) return attr;
-    hipLaunchKernelGGL((k_ib_lean<T, MPT>), dim3(grid), dim3(256), kLeanArenaBytes<MPT>, stream, sims, groups, hdr,
-                       ngroups, parity, bc_items);
+    hipLaunchKernelGGL((k_ib_lean<T, MPT>), dim3(grid), dim3(kLeanThreads<MPT>), kLeanArenaBytes<MPT>, stream, sims,
+                       groups, hdr, ngroups, parity, bc_items);
     return hipGetLastError();
 }
 
