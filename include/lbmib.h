@@ -295,6 +295,14 @@ int32_t lbm_batch_get_lanes(const lbm_batch* b);
 /* The lane request in force (0 .. 4, as lbm_batch_set_lanes takes it; the
  * autotuner may have replaced the caller's), -1 for a null batch. */
 int32_t lbm_batch_get_lane_mode(const lbm_batch* b);
+/* Whether the second lane's stream was seen running kernels beside the batch
+ * stream (the two reach the GPU through different hardware queues, which the
+ * lanes need to overlap): 1 yes, 0 no (the lanes then run one after the other,
+ * with the same results), -1 while no second lane has run (or a null batch).
+ * The batch makes up to six candidate streams when the second lane first runs
+ * and keeps the first that passes a bounded check (two tiny kernels, at most
+ * about 0.2 ms each). */
+int32_t lbm_batch_lanes_concurrent(const lbm_batch* b);
 int32_t lbm_tiling_count(void);
 /* Describe tiling k: threads along x, rows per block, rows per thread. */
 lbm_status lbm_tiling_info(int32_t k, int32_t* tx, int32_t* ty, int32_t* rows_per_thread);

@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblbmib.so")
-SOURCES = [os.path.join(CSRC, "kernels.hip"), os.path.join(CSRC, "runtime.cpp")]
+SOURCES = [os.path.join(CSRC, "kernels.hip"), os.path.join(CSRC, "queues.hip"), os.path.join(CSRC, "runtime.cpp")]
 ARCH = os.environ.get("LBMIB_ARCH", "gfx950")
 
 FLAGS = [

@@ -50,6 +50,10 @@ hipError_t launch_ib(bool f64, int max_markers, const SimDev* sims, GroupDev* gr
 hipError_t launch_band(bool f64, bool apply, const SimDev* sims, const GroupDev* groups, const int2* chunks,
                        const BatchHeader* hdr, int nchunks, int grid, int parity, hipStream_t stream);
 hipError_t launch_advance(SimDev* sims, const BatchHeader* hdr, int nsims, hipStream_t stream);
+// Whether kernels launched on `second` run while one on `first` runs (the two
+// streams reach the GPU through different hardware queues).  flags: two ints
+// of device memory; synchronises both streams; takes at most about 0.2 ms.
+hipError_t streams_run_concurrently(hipStream_t first, hipStream_t second, int* flags, bool* concurrent);
 // which k_ib instance launch_ib picks for a largest group of max_markers
 int ib_variant(bool f64, int max_markers, bool lean);
 // Field and population I/O of one simulation (state `sw` = AA state now).

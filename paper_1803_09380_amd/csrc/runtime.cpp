@@ -163,6 +163,8 @@ struct lbm_batch {
     std::vector<int> order;         // simulation table row -> index into sims
     DevBuf d_sims;
     size_t cap_sims = 0;
+    DevBuf d_probe;                 // two flags of the hardware-queue check (ensure_lane_stream)
+    int lanes_concurrent = -1;      // the second stream was seen running beside the batch stream (-1: not made)
     Lane lane[2];
     int lanes_req = 0;              // 0 automatic, 1 one lane, 2 two free-running, 3 two interleaved,
                                     // 4 two interleaved halves of equal node count (upload_tables)
@@ -1326,10 +1328,43 @@ hipError_t capture(lbm_batch* b, int l, int n, hipStream_t st, hipGraphExec_t* o
 }
 
 // Lane 1 runs on the batch's second stream, ordered after everything already
-// enqueued on the batch stream; the batch stream waits for it at the end.
+// enqueued on the batch stream; the batch stream waits for it at the end.  The
+// second stream must reach the GPU through another hardware queue than the
+// batch stream (else the lanes run one after the other): candidates are
+// created until one runs concurrently with the batch stream, the others are
+// destroyed afterwards (kept until then, so that the next candidate lands
+// elsewhere); if none does, the last one serves (same results, no overlap).
+constexpr int kLaneStreamTries = 6;
+
 lbm_status ensure_lane_stream(lbm_batch* b) {
     if (b->stream2) return LBM_OK;
-    HIPB(b, hipStreamCreateWithFlags(&b->stream2, hipStreamNonBlocking));
+    if (!b->d_probe.p) HIPB(b, b->d_probe.alloc(2 * sizeof(int)));
+    std::vector<hipStream_t> rejected;
+    hipStream_t pick = nullptr;
+    bool concurrent = false;
+    hipError_t err = hipSuccess;
+    for (int k = 0; k < kLaneStreamTries && !concurrent; ++k) {
+        hipStream_t c = nullptr;
+        err = hipStreamCreateWithFlags(&c, hipStreamNonBlocking);
+        if (err != hipSuccess) break;
+        err = streams_run_concurrently(b->stream, c, (int*)b->d_probe.p, &concurrent);
+        if (err != hipSuccess) {
+            rejected.push_back(c);
+            break;
+        }
+        if (concurrent)
+            pick = c;
+        else
+            rejected.push_back(c);
+    }
+    if (err == hipSuccess && !pick) {
+        pick = rejected.back();
+        rejected.pop_back();
+    }
+    for (hipStream_t r : rejected) (void)hipStreamDestroy(r);
+    HIPB(b, err);
+    b->stream2 = pick;
+    b->lanes_concurrent = concurrent ? 1 : 0;
     HIPB(b, hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming));
     HIPB(b, hipEventCreateWithFlags(&b->ev_join, hipEventDisableTiming));
     HIPB(b, hipEventCreateWithFlags(&b->ev_sweep0, hipEventDisableTiming));
@@ -1634,6 +1669,8 @@ lbm_status lbm_batch_set_lanes(lbm_batch* b, int32_t lanes) {
 int32_t lbm_batch_get_lanes(const lbm_batch* b) { return b ? b->nlanes : -1; }
 
 int32_t lbm_batch_get_lane_mode(const lbm_batch* b) { return b ? b->lanes_req : -1; }
+
+int32_t lbm_batch_lanes_concurrent(const lbm_batch* b) { return b ? b->lanes_concurrent : -1; }
 
 lbm_status lbm_batch_profile(lbm_batch* b, int32_t nsteps, double ms[4], int64_t* cells) {
     if (!b || nsteps < 0 || !ms) return LBM_ERR_INVALID;

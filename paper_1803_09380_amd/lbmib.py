@@ -82,6 +82,7 @@ SIGNATURES = [
     ("lbm_batch_set_lanes", _ST, [_P, _I32]),
     ("lbm_batch_get_lanes", _I32, [_P]),
     ("lbm_batch_get_lane_mode", _I32, [_P]),
+    ("lbm_batch_lanes_concurrent", _I32, [_P]),
     ("lbm_tiling_count", _I32, []),
     ("lbm_tiling_info", _ST, [_I32, ctypes.POINTER(_I32), ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
     ("lbm_batch_profile", _ST, [_P, _I32, _DP, ctypes.POINTER(_I64)]),
@@ -408,6 +409,12 @@ class Batch:
     def lane_mode(self):
         """The lane request in force (0 .. 4, as set_lanes takes it)."""
         return load().lbm_batch_get_lane_mode(self._h)
+
+    @property
+    def lanes_concurrent(self):
+        """1 when the second lane's stream runs beside the batch stream, 0 when
+        not, -1 before a second lane has run."""
+        return load().lbm_batch_lanes_concurrent(self._h)
 
 
 def tilings():

@@ -32,7 +32,7 @@ class Request:
 class GpuExecutor:
     """Executor over lbmib.Batch (one precision, one HBM budget)."""
 
-    def __init__(self, precision, hbm_budget, tiling=None, lanes=None, halves_from=6):
+    def __init__(self, precision, hbm_budget, tiling=None, lanes=None, halves_from=5):
         """lanes: the batch's lane mode (lbmib.Batch.set_lanes), None for the
         library's choice.  halves_from > 0: two interleaved halves (lane mode
         4, one half's correction beside the other half's sweep) while at

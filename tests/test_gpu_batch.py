@@ -308,6 +308,26 @@ def test_interleaved_lanes_with_large_moving_groups_give_the_same_bits():
         _same(res[4][k], _state(alone, 1))
 
 
+def test_second_lane_runs_beside_the_first():
+    """However many streams the process made before (every simulation makes
+    its own), the second lane's stream is one that runs kernels beside the
+    batch stream, so interleaved lanes can overlap."""
+    _say("second lane's stream runs beside the batch stream")
+    for extra in (0, 3, 5, 9):
+        sims = [gpu_from_case(wl.couette(48, precision=wl.F32), precision=lbmib.F32_SHIFTED) for _ in range(extra + 2)]
+        b = lbmib.Batch(lbmib.F32_SHIFTED)
+        for s in sims:
+            assert b.admit(s)
+        assert b.lanes_concurrent == -1
+        b.set_lanes(4)
+        b.step(2)
+        b.sync()
+        assert b.lanes == 2 and b.lanes_concurrent == 1, extra
+        b.close()
+        for s in sims:
+            s.close()
+
+
 def test_two_lanes_with_boundary_beside_correction_give_the_same_bits():
     """The light lane holds channel cylinders far from the sides and periodic
     Couette cells only, so its boundary rules run on their own stream beside
